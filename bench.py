@@ -1,0 +1,216 @@
+#!/usr/bin/env python3
+"""Benchmark of the Nekbone Poisson hot path on one MI355X.
+
+Workload (default): the paper's shape -- a 16x16x16 box of E = 4096 hexahedra
+of degree N = 9 (n = 10 GLL points per direction), perturbed geometry, rhs
+uniform in [-1, 1] per global node, zero Dirichlet boundary.
+
+* One timed step = one FP64 CG solve of exactly 100 iterations (Sec. V): the
+  local operator, dssum + mask and the CG vector updates, all on the device.
+  `value` is the whole-step throughput in GFLOP/s counted with the paper's
+  cost model, eq. (1): (12n + 34) flops per local point per iteration.
+* The dominant kernel, the local operator ax_e, is also timed alone with HIP
+  events on its own stream (back-to-back launches, rotating over buffer sets
+  larger than the 256 MB last-level cache) and reported against the HBM
+  roofline with its algorithmic bytes (u + 6 g + w = 64 B per point in FP64).
+* cpu_baseline: the FP64 oracle timed on this host on a bounded sample.
+
+Prints ONE JSON line.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0      # MI355X published HBM3E bandwidth
+FP64_PEAK_TFLOPS = 78.6    # MI355X published FP64 vector peak
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--E", type=int, default=4096)
+    ap.add_argument("--N", type=int, default=9)
+    ap.add_argument("--iters", type=int, default=100)
+    ap.add_argument("--ax-reps", type=int, default=200)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    return ap.parse_args()
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1 "
+                                   "(the multi-GPU sharding is described, not built)"}))
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import paper_2005_13425_amd as nek
+    import synth
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    dev = torch.device("cuda:0")
+    E, N, iters = args.E, args.N, args.iters
+    Ex, Ey, Ez = synth.box_for(E)
+    n = N + 1
+    P = E * n ** 3
+
+    # ---------------- setup with the library's own generators (no oracle)
+    _, _, Dh = nek.gll(N)
+    D = torch.from_numpy(Dh).to(dev)
+    g, _, _ = nek.box_geometry(Ex, Ey, Ez, N, synth.AMP, synth.geom_coeffs())
+    glo, dirichlet = nek.box_numbering(Ex, Ey, Ez, N)
+    gs = nek.GatherScatter(E, N, glo, dirichlet)
+    vals = synth.lattice_uniform(Ex, Ey, Ez, N)
+    bh = vals[glo]
+    bh[dirichlet == 1] = 0.0
+    b = torch.from_numpy(bh).to(dev)
+    x = torch.empty_like(b)
+    ws = nek.cg_workspace(E, N)
+    torch.cuda.synchronize()
+
+    stream = torch.cuda.current_stream()
+
+    # ---------------- timed region: K CG solves of `iters` iterations
+    for _ in range(args.warmup):
+        nek.cg_solve(D, g, gs, b, x, max_iter=iters, workspace=ws)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ev0.record(stream)
+    last = None
+    for _ in range(args.steps):
+        _, last = nek.cg_solve(D, g, gs, b, x, max_iter=iters, workspace=ws)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    cg_ms = ev0.elapsed_time(ev1) / args.steps
+    ms_per_step = max(cg_ms, 1e3 * wall / args.steps)
+    flops_step = iters * P * (12 * n + 34)
+    value = flops_step / (ms_per_step * 1e-3) / 1e9
+
+    # ---------------- ax_e alone: rotating buffer sets (cold) and one set (warm)
+    nsets = max(1, int(np.ceil(1.2e9 / (64 * P))))      # > 1 GB touched per rotation
+    us = [torch.rand(P, dtype=torch.float64, device=dev) * 2 - 1 for _ in range(nsets)]
+    gsets = [g] + [g.clone() for _ in range(nsets - 1)]
+    wsets = [torch.empty(P, dtype=torch.float64, device=dev) for _ in range(nsets)]
+    for q in range(nsets):
+        nek.ax(us[q], D, gsets[q], N, out=wsets[q])
+    torch.cuda.synchronize()
+    # direct C-ABI calls with prepared pointers keep host overhead far below a launch
+    import ctypes
+    sp = ctypes.c_void_p(stream.cuda_stream)
+    Dp = ctypes.c_void_p(D.data_ptr())
+    args_q = [(ctypes.c_void_p(us[q].data_ptr()), ctypes.c_void_p(gsets[q].data_ptr()),
+               ctypes.c_void_p(wsets[q].data_ptr())) for q in range(nsets)]
+    call = nek._lib.nek_ax
+    reps = args.ax_reps
+    a0, a1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a0.record(stream)
+    for r in range(reps):
+        up, gp, wp = args_q[r % nsets]
+        call(E, N, up, Dp, gp, wp, sp)
+    a1.record(stream)
+    torch.cuda.synchronize()
+    ax_us_cold = 1e3 * a0.elapsed_time(a1) / reps
+    up, gp, wp = args_q[0]
+    a0.record(stream)
+    for r in range(reps):
+        call(E, N, up, Dp, gp, wp, sp)
+    a1.record(stream)
+    torch.cuda.synchronize()
+    ax_us_warm = 1e3 * a0.elapsed_time(a1) / reps
+    ax_bytes = 64 * P
+    ax_flops = (12 * n + 15) * P
+    ax_gbs = ax_bytes / (ax_us_cold * 1e-6) / 1e9
+
+    # ---------------- measured copy roofline at the same footprint (the method of Sec. V)
+    src = torch.empty(ax_bytes // 8, dtype=torch.float64, device=dev).uniform_()
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    c0, c1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    c0.record(stream)
+    for _ in range(20):
+        dst.copy_(src)
+    c1.record(stream)
+    torch.cuda.synchronize()
+    copy_gbs = 2 * ax_bytes * 20 / (c0.elapsed_time(c1) * 1e-3) / 1e9
+    del src, dst
+
+    out = {
+        "metric": "ax_e GFLOP/s + % HBM roofline at E=4096 N=9; CG solves/s, p50/p99 latency",
+        "value": round(value, 2),
+        "unit": "GFLOP/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": f"FP64 CG, {iters} iterations, box {Ex}x{Ey}x{Ez} E={E} N={N} "
+                               f"(n={n}), perturbed geometry (amp {synth.AMP}), rhs U[-1,1] per node, "
+                               "zero Dirichlet boundary; value counted with eq. (1) (12n+34 flop/point/iter)",
+                   "E": E, "N": N, "iters": iters, "box": [Ex, Ey, Ez]},
+        "roofline": {"bound": "hbm", "achieved": round(ax_gbs, 1), "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": round(ax_gbs / HBM_PEAK_GBS, 4), "traffic": None,
+                     "kernel": "ax_kernel<10,double,double,false> (nek_ax)",
+                     "bytes_per_launch": ax_bytes},
+        "ax_e": {"us_per_call_cold": round(ax_us_cold, 2), "us_per_call_warm": round(ax_us_warm, 2),
+                 "gflops_cold": round(ax_flops / (ax_us_cold * 1e-6) / 1e9, 1),
+                 "gbs_cold": round(ax_gbs, 1),
+                 "gbs_warm": round(ax_bytes / (ax_us_warm * 1e-6) / 1e9, 1),
+                 "frac_of_measured_copy_bw": round(ax_gbs / copy_gbs, 4),
+                 "flops_per_point": 12 * n + 15, "bytes_per_point": 64},
+        "cg": {"ms_per_solve": round(cg_ms, 4), "solves_per_s": round(1e3 / ms_per_step, 3),
+               "us_per_iter": round(1e3 * cg_ms / iters, 2), "final_rel_res": last.rel_res if last else None},
+        "measured_copy_gbs": round(copy_gbs, 1),
+    }
+
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(Ex, Ey, Ez, N, args.cpu_seconds)
+    gs.close()
+    print(json.dumps(out), flush=True)
+
+
+def cpu_baseline(Ex, Ey, Ez, N, budget_s):
+    """The FP64 oracle, as it stands, on this host: CG iterations on the same
+    workload shape, as many as fit in about budget_s seconds (at least 1)."""
+    import numpy as np
+
+    import oracle
+    import synth
+    mesh = oracle.box_mesh(Ex, Ey, Ez, N, synth.AMP, synth.geom_coeffs())
+    b = oracle.lattice_to_local(mesh, synth.lattice_uniform(Ex, Ey, Ez, N))
+    t0 = time.perf_counter()
+    oracle.cg(mesh, b, max_iter=1)
+    t1 = time.perf_counter() - t0
+    k = int(max(1, min(100, budget_s / max(t1, 1e-3))))
+    t0 = time.perf_counter()
+    oracle.cg(mesh, b, max_iter=k)
+    dt = time.perf_counter() - t0
+    n = N + 1
+    gflops = k * mesh.P * (12 * n + 34) / dt / 1e9
+    return {"value": round(gflops, 3), "unit": "GFLOP/s", "cores": oracle.max_threads(),
+            "kind": "oracle",
+            "sample": f"{k} FP64 CG iterations of the oracle on the same E={mesh.E} N={N} mesh "
+                      f"({dt:.1f} s; OpenMP over elements in the local operator, the rest serial); "
+                      "counted with eq. (1)"}
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,206 @@
+/*
+ * nek.h -- C ABI of libnek: the Nekbone Poisson hot path on AMD MI355X (gfx950).
+ *
+ * The operation is the one of Karp et al., "Optimization of Tensor-product
+ * Operations in Nekbone on GPUs" (arXiv 2005.13425):
+ *   - Sec. III, Listing 1: the local Poisson operator of every spectral element,
+ *     w = Dt (G (D u)) with three contractions by the GLL derivative matrix, a
+ *     symmetric 3x3 multiply by six geometric factors per node and three
+ *     transposed contractions;
+ *   - Sec. III (second step of Ax): direct-stiffness summation (dssum), which
+ *     sums the copies of every node shared by several elements;
+ *   - Sec. VI-B: masking of the Dirichlet boundary;
+ *   - Sec. III / Sec. V: the conjugate-gradient loop around them (100
+ *     iterations in the paper's runs), and the cost model of Sec. III-A.
+ *
+ * Layouts are the Fortran arrays of Listing 1, 0-based, i fastest:
+ *   u, w, x, b : u(i,j,k,e)      at [i + n*(j + n*(k + n*e))],   n = N + 1
+ *   g          : gxyz(i,j,k,c,e) at [i + n*(j + n*(k + n*(c + 6*e)))], c = 0..5 is
+ *                (rr, rs, rt, ss, st, tt) of the symmetric 3x3 factor
+ *   D          : dxm1(i,l)       at [i + n*l]   (so dxtm1(i,l) = D[l + n*i])
+ *
+ * Conventions:
+ *   - Sizes are int64_t, the degree N is int (1 <= N <= NEK_MAX_DEGREE).
+ *   - "device" pointers are HIP device memory of the current device (for
+ *     instance torch tensors on cuda:0); "host" pointers are ordinary memory.
+ *   - stream is a hipStream_t passed as void*; NULL means the default stream.
+ *     Calls marked "asynchronous" only enqueue work on that stream.
+ *   - The caller owns every buffer it passes.  The library never frees them
+ *     and keeps no reference to them after the call returns.
+ *   - Every entry point returns NEK_OK (0) or a negative NEK_ERR_* code.
+ *     Argument errors are detected on the host before anything is enqueued.
+ *     A device fault inside an asynchronous call surfaces at the next
+ *     synchronising call.  nek_last_error() gives a message for the calling
+ *     thread's last failure.
+ */
+#ifndef NEK_H
+#define NEK_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define NEK_MAX_DEGREE 15
+
+/* status codes */
+#define NEK_OK               0
+#define NEK_ERR_ARG         -1  /* bad size, null or misaligned pointer, aliasing */
+#define NEK_ERR_UNSUPPORTED -2  /* degree outside 1..NEK_MAX_DEGREE, unknown dtype */
+#define NEK_ERR_DEVICE      -3  /* a HIP call failed; nek_last_error() has the text */
+#define NEK_ERR_NOMEM       -4  /* device or host allocation failed / budget exceeded */
+#define NEK_ERR_BREAKDOWN   -5  /* CG: (p, Ap) <= 0 or a non-finite scalar */
+#define NEK_ERR_NOCONV      -6  /* CG: the tolerance was not reached in max_iter */
+#define NEK_ERR_STATE       -7  /* call not valid in the object's current state */
+
+/* storage types of the geometric factors for the FP32 operator */
+#define NEK_G_F32  1
+#define NEK_G_BF16 2
+
+/* CG precision modes */
+#define NEK_PREC_F64      0  /* FP64 operator (Listing 1 in double precision) */
+#define NEK_PREC_F32G32   1  /* FP32 operator, g stored FP32, FP64 reliable updates */
+#define NEK_PREC_F32GBF16 2  /* FP32 operator, g stored BF16, FP64 reliable updates */
+
+/* Text of a status code (static string). */
+const char *nek_strerror(int code);
+
+/* Message of the calling thread's last failure ("" if none). */
+const char *nek_last_error(void);
+
+/* Library version, major*10000 + minor*100 + patch. */
+int nek_version(void);
+
+/* ------------------------------------------------------------------ setup */
+
+/* GLL nodes z[0..N], weights w[0..N] and the derivative matrix D[(N+1)^2]
+ * (dxm1 of Listing 1, column-major as above) for degree N; n = N + 1 GLL
+ * points per direction (Sec. III-A).  Host pointers, any of them may be
+ * NULL.  Synchronous, no device work. */
+int nek_gll(int N, double *z, double *w, double *D);
+
+/* Box of Ex x Ey x Ez hexahedra on [0,1]^3 (Sec. III: Poisson on a cubic
+ * domain).  Element e = ex + Ex*(ey + Ey*ez).  Fills, on the host, the global
+ * id of every local point, glo[P] with P = E*n^3 (lattice node
+ * I + (Ex*N+1)*(J + (Ey*N+1)*K), I = ex*N + i, ...), and dirichlet[P] = 1 on
+ * the six faces of the box.  Either output may be NULL.  Synchronous. */
+int nek_box_numbering(int Ex, int Ey, int Ez, int N, int64_t *glo, uint8_t *dirichlet);
+
+/* Geometric factors of the box mesh, on the device: nodes at the tensor GLL
+ * points of each element, displaced by amp * a[d] * sin(pi x) sin(pi y)
+ * sin(pi z) (evaluated at the undisplaced point; zero on the boundary).  The
+ * Jacobian is the derivative matrix applied to the nodal coordinates along
+ * each direction; g = w_i w_j w_k det(J) J^-1 J^-T in the gxyz layout.
+ *   a      host, 3 doubles
+ *   g      device, 6*P doubles (required)
+ *   bm     device, P doubles: diagonal mass w_i w_j w_k det(J) (may be NULL)
+ *   X      device, 3*P doubles: x, y, z coordinate arrays (may be NULL)
+ * Asynchronous. */
+int nek_box_geometry(int Ex, int Ey, int Ez, int N, double amp, const double *a,
+                     double *g, double *bm, double *X, void *stream);
+
+/* ------------------------------------------------------- local operator */
+
+/* w = A_e u for every element: Listing 1 in FP64.  No dssum, no mask.
+ *   u, g, w, D device pointers in the layouts above; u and w must not
+ *   overlap; all 8-byte aligned.  E >= 1.  Allocates nothing.
+ * Asynchronous. */
+int nek_ax(int64_t E, int N, const double *u, const double *D, const double *g,
+           double *w, void *stream);
+
+/* The same operator computed in FP32: u is read in FP64 and rounded, the
+ * contractions and the geometric multiply run in FP32 with D32 (FP32 copy of
+ * D) and g_lo (the factors stored as FP32 or BF16, g_dtype = NEK_G_F32 or
+ * NEK_G_BF16, same gxyz layout), and w is written in FP64.  Used inside the
+ * FP64 reliable-update CG (NEK_PREC_F32G*).  Allocates nothing.
+ * Asynchronous. */
+int nek_ax_f32(int64_t E, int N, const double *u, const float *D32, const void *g_lo,
+               int g_dtype, double *w, void *stream);
+
+/* Round g (6*P FP64 values, device) to FP32 or BF16 (round to nearest even)
+ * into g_lo (device, 6*P elements of the chosen type).  Asynchronous. */
+int nek_convert_g(int64_t E, int N, const double *g, int g_dtype, void *g_lo, void *stream);
+
+/* ---------------------------------------------------- gather-scatter (dssum) */
+
+typedef struct nek_gs nek_gs;
+
+/* Build the direct-stiffness summation of a mesh from host arrays:
+ * glo[P] global id of each local point (any non-negative ids), dirichlet[P]
+ * 1 where the node carries the zero Dirichlet condition (NULL = none).  A
+ * node is masked when any of its copies is flagged.  The handle owns device
+ * copies of the map (CSR over the shared or masked nodes, in ascending local
+ * index), and of the dot-product weights.  P must be < 2^31.
+ * Synchronous (allocates device memory and uploads). */
+int nek_gs_create(int64_t E, int N, const int64_t *glo, const uint8_t *dirichlet, nek_gs **out);
+
+/* Free the handle (synchronises the device first).  NULL is accepted. */
+int nek_gs_destroy(nek_gs *gs);
+
+/* Sizes of a handle: unique nodes, shared-or-masked nodes handled by the
+ * CSR, CSR entries, masked unique nodes.  Any output may be NULL. */
+int nek_gs_info(const nek_gs *gs, int64_t *n_unique, int64_t *n_rows, int64_t *n_entries,
+                int64_t *n_masked);
+
+/* In place on device w[P]: w <- mask(dssum(w)).  Every copy of a node
+ * receives the sum of all its copies (summed in ascending local index), and
+ * masked nodes receive 0 (Sec. III step 2, Sec. VI-B).  Deterministic.
+ * Allocates nothing.  Asynchronous. */
+int nek_dssum(const nek_gs *gs, double *w, void *stream);
+
+/* Inner product of two continuous local vectors over unique global nodes
+ * (each node counted once): *result (device, one double) = sum a_G b_G.
+ * Deterministic.  Allocates nothing.  Asynchronous. */
+int nek_gs_dot(const nek_gs *gs, const double *a, const double *b, double *result, void *stream);
+
+/* --------------------------------------------------------------------- CG */
+
+typedef struct {
+    int max_iter;          /* iteration cap (100 in the paper's runs) */
+    double rel_tol;        /* stop when ||r||/||b|| <= rel_tol; <= 0: run max_iter */
+    int precision;         /* NEK_PREC_* */
+    const float *D32;      /* FP32 copy of D (device), required for NEK_PREC_F32G* */
+    const void *g_lo;      /* g as FP32 / BF16 (device), required for NEK_PREC_F32G* */
+    int check_every;       /* host polls convergence every this many iterations (0: 25) */
+    int true_residual;     /* 1: report ||b - A x|| / ||b|| computed in FP64 at the end */
+    double reliable_drop;  /* NEK_PREC_F32G*: replace r by b - A64 x whenever ||r|| fell
+                              by this factor since the last replacement (0: 0.1) */
+    void *workspace;       /* device scratch of nek_cg_workspace_bytes() bytes, or NULL
+                              to let the call allocate and free its own */
+    size_t workspace_bytes;
+} nek_cg_opts;
+
+typedef struct {
+    int iters;             /* iterations performed */
+    int status;            /* NEK_OK, NEK_ERR_BREAKDOWN or NEK_ERR_NOCONV */
+    double rel_res;        /* recurrence residual sqrt((r,r)/(b,b)) at exit */
+    double rel_res_true;   /* ||b - A x|| / ||b|| in FP64 if requested, else -1 */
+    int n_replacements;    /* reliable updates of r (mixed precision), else 0 */
+} nek_cg_stats;
+
+/* Fill opts with defaults: 100 iterations, rel_tol 0, FP64, no workspace. */
+void nek_cg_default_opts(nek_cg_opts *opts);
+
+/* Device bytes of scratch nek_cg_solve needs for E elements of degree N. */
+size_t nek_cg_workspace_bytes(int64_t E, int N);
+
+/* Solve mask(dssum(A_L x)) = b by unpreconditioned CG with x_0 = 0 (Sec. III,
+ * Sec. V).  b and x are device vectors in the local layout; b must be
+ * continuous (copies equal) and zero at masked nodes; x receives a vector of
+ * the same kind.  D, g device.  gs from nek_gs_create for the same mesh.
+ * Every step runs on the device; the host only polls a status word every
+ * opts->check_every iterations.  Blocking: returns after the work on stream
+ * has finished.  stats may be NULL.  Returns NEK_OK, or the failure code
+ * (also stored in stats->status) -- NEK_ERR_NOCONV when rel_tol > 0 was not
+ * reached. */
+int nek_cg_solve(int64_t E, int N, const double *D, const double *g, const nek_gs *gs,
+                 const double *b, double *x, const nek_cg_opts *opts, nek_cg_stats *stats,
+                 void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* NEK_H */

@@ -1,0 +1,215 @@
+"""GPU parity: the HIP path through the C ABI against the FP64 CPU oracle.
+
+Inputs are seeded (synth) and the geometry, numbering and derivative matrix
+come from the oracle, so both sides see the same arrays.  Bars: rel-L2 <= 1e-12
+for FP64 floating point (the bar the method's target sets), bit-exact for the
+integer numbering and for dssum (same summation order on both sides).
+"""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-12
+
+
+@pytest.fixture(scope="module")
+def nek():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2005_13425_amd as nek
+    return nek
+
+
+def _dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def _rel(a, b):
+    a = a.detach().cpu().numpy() if hasattr(a, "detach") else np.asarray(a)
+    return np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300)
+
+
+def _mesh(box, N, amp=synth.AMP):
+    return oracle.box_mesh(*box, N, amp, synth.geom_coeffs())
+
+
+# boxes span several workgroups and leave a ragged last workgroup for every degree
+BOX_FOR_N = {1: (6, 5, 5), 2: (4, 4, 4), 3: (3, 3, 7), 4: (3, 3, 3), 5: (3, 3, 3), 6: (3, 3, 3)}
+
+
+@pytest.mark.parametrize("N", list(range(1, 16)))
+def test_ax_parity_every_degree(nek, N):
+    box = BOX_FOR_N.get(N, (3, 2, 2))
+    m = _mesh(box, N)
+    print(f"ax parity N={N} E={m.E}", flush=True)
+    u = synth.local_uniform(m.P, seed=100 + N)
+    w = nek.ax(_dev(u), _dev(m.D), _dev(m.g), N)
+    ref = oracle.ax(m.E, N, m.D, m.g, u)
+    assert _rel(w, ref) <= TOL
+    # invariant on the GPU output itself: constants are in the kernel
+    w1 = nek.ax(torch.ones(m.P, dtype=torch.float64, device="cuda"), _dev(m.D), _dev(m.g), N)
+    assert torch.max(torch.abs(w1)).item() < 1e-11 * max(1, N * N)
+
+
+def test_ax_single_element_and_affine(nek):
+    m = oracle.box_mesh(1, 1, 1, 9)
+    u = synth.local_uniform(m.P, seed=3)
+    w = nek.ax(_dev(u), _dev(m.D), _dev(m.g), 9)
+    assert _rel(w, oracle.ax(1, 9, m.D, m.g, u)) <= TOL
+
+
+@pytest.mark.parametrize("E_box", [(16, 8, 8), (16, 16, 16)])
+def test_ax_parity_paper_shapes(nek, E_box):
+    m = _mesh(E_box, 9)
+    print(f"ax parity paper shape E={m.E}", flush=True)
+    u = synth.local_uniform(m.P)
+    w = nek.ax(_dev(u), _dev(m.D), _dev(m.g), 9)
+    ref = oracle.ax(m.E, 9, m.D, m.g, u)
+    assert _rel(w, ref) <= TOL
+
+
+def test_ax_sampled_sweep_shape(nek):
+    # the degree-sweep box at N=9 (32^3 elements): compare sampled elements
+    N = 9
+    Ex, Ey, Ez = synth.SWEEP_BOXES[N]
+    E = Ex * Ey * Ez
+    n3 = (N + 1) ** 3
+    z, wq = oracle.gll(N)
+    # product geometry on the device, oracle operator on sampled elements
+    g, _, X = nek.box_geometry(Ex, Ey, Ez, N, synth.AMP, synth.geom_coeffs(), want_coords=True)
+    _, _, D = nek.gll(N)
+    Dt = _dev(D)
+    u = torch.rand(E * n3, dtype=torch.float64, device="cuda", generator=torch.Generator("cuda").manual_seed(7)) * 2 - 1
+    w = nek.ax(u, Dt, g, N)
+    torch.cuda.synchronize()
+    rng = np.random.default_rng(9)
+    sample = np.unique(np.concatenate([[0, E - 1], rng.integers(0, E, 64)]))
+    gh = g.view(E, 6 * n3)[torch.from_numpy(sample).cuda()].cpu().numpy().reshape(-1)
+    uh = u.view(E, n3)[torch.from_numpy(sample).cuda()].cpu().numpy().reshape(-1)
+    wh = w.view(E, n3)[torch.from_numpy(sample).cuda()].cpu().numpy().reshape(-1)
+    ref = oracle.ax(len(sample), N, D, gh, uh)
+    assert _rel(wh, ref) <= TOL
+
+
+def test_geometry_parity(nek):
+    for box, N in [((3, 2, 2), 4), ((4, 4, 4), 7), ((2, 2, 2), 9)]:
+        m = _mesh(box, N)
+        g, bm, X = nek.box_geometry(*box, N, synth.AMP, synth.geom_coeffs(), want_mass=True, want_coords=True)
+        torch.cuda.synchronize()
+        assert _rel(X, m.X.reshape(-1)) <= 1e-14
+        assert _rel(bm, m.bm) <= 1e-12
+        assert _rel(g, m.g) <= 1e-12
+
+
+def test_dssum_bit_exact(nek):
+    for box, N in [((4, 4, 4), 7), ((3, 2, 5), 3), ((16, 8, 8), 9)]:
+        m = _mesh(box, N)
+        gs = nek.GatherScatter(m.E, N, m.glo, m.dirichlet)
+        info = gs.info()
+        assert info["n_unique"] == m.U
+        w = synth.local_uniform(m.P, seed=5)
+        wt = _dev(w.copy())
+        gs.dssum(wt)
+        ref = oracle.mask(m.dirichlet, oracle.dssum(m.glo, w, m.U))
+        np.testing.assert_array_equal(wt.cpu().numpy(), ref)
+        gs.close()
+
+
+def test_dssum_without_mask_and_general_ids(nek):
+    m = _mesh((3, 3, 2), 4)
+    # renumber ids with gaps and a permutation: the handle must not depend on compact ids
+    perm = np.random.default_rng(2).permutation(m.U).astype(np.int64) * 7 + 11
+    glo = perm[m.glo]
+    gs = nek.GatherScatter(m.E, 4, glo, None)
+    w = synth.local_uniform(m.P, seed=6)
+    wt = _dev(w.copy())
+    gs.dssum(wt)
+    np.testing.assert_array_equal(wt.cpu().numpy(), oracle.dssum(m.glo, w, m.U))
+    a, b = synth.local_uniform(m.P, 1), synth.local_uniform(m.P, 2)
+    a = oracle.dssum(m.glo, a, m.U) / oracle.dssum(m.glo, np.ones(m.P), m.U)
+    b = oracle.dssum(m.glo, b, m.U) / oracle.dssum(m.glo, np.ones(m.P), m.U)
+    d = gs.dot(_dev(a), _dev(b)).item()
+    ref = oracle.gdot(m.glo, a, b, m.U)
+    assert abs(d - ref) <= 1e-13 * abs(ref)
+    gs.close()
+
+
+def _cg_case(nek, box, N, iters, rel_tol=0.0):
+    m = _mesh(box, N)
+    b = oracle.lattice_to_local(m, synth.lattice_uniform(*box, N))
+    gs = nek.GatherScatter(m.E, N, m.glo, m.dirichlet)
+    x, res = nek.cg_solve(_dev(m.D), _dev(m.g), gs, _dev(b), max_iter=iters, rel_tol=rel_tol,
+                          true_residual=True)
+    torch.cuda.synchronize()
+    ref = oracle.cg(m, b, max_iter=iters, rel_tol=rel_tol)
+    gs.close()
+    return m, x, res, ref
+
+
+def test_cg_100_iterations_small_config(nek):
+    m, x, res, ref = _cg_case(nek, (4, 4, 4), 7, 100)
+    print(f"CG E=64 N=7: iters {res.iters} rel_res {res.rel_res:.3e} oracle {ref.res_hist[-1]:.3e}", flush=True)
+    assert res.iters == 100 and res.status == 0
+    assert _rel(x, ref.x) <= TOL
+    assert abs(res.rel_res - ref.res_hist[-1]) <= 1e-9 * ref.res_hist[-1]
+
+
+def test_cg_100_iterations_paper_shape(nek):
+    m, x, res, ref = _cg_case(nek, (16, 8, 8), 9, 100)
+    print(f"CG E=1024 N=9: rel-L2 {_rel(x, ref.x):.2e}", flush=True)
+    assert res.iters == 100
+    assert _rel(x, ref.x) <= TOL
+
+
+def test_cg_to_tolerance(nek):
+    m, x, res, ref = _cg_case(nek, (4, 4, 4), 7, 2000, rel_tol=1e-13)
+    assert res.status == 0 and ref.status == 0
+    assert abs(res.iters - ref.iters) <= 3
+    assert res.rel_res <= 1e-13 and res.rel_res_true <= 1e-12
+    assert _rel(x, ref.x) <= 1e-10
+
+
+def test_cg_deterministic(nek):
+    m = _mesh((4, 4, 4), 7)
+    b = _dev(oracle.lattice_to_local(m, synth.lattice_uniform(4, 4, 4, 7)))
+    gs = nek.GatherScatter(m.E, 7, m.glo, m.dirichlet)
+    x1, _ = nek.cg_solve(_dev(m.D), _dev(m.g), gs, b, max_iter=60)
+    x2, _ = nek.cg_solve(_dev(m.D), _dev(m.g), gs, b, max_iter=60)
+    torch.cuda.synchronize()
+    assert torch.equal(x1, x2)
+    gs.close()
+
+
+def test_cg_breakdown_and_noconv(nek):
+    m = _mesh((2, 2, 2), 5)
+    b = oracle.lattice_to_local(m, synth.lattice_uniform(2, 2, 2, 5))
+    gs = nek.GatherScatter(m.E, 5, m.glo, m.dirichlet)
+    bad = b.copy()
+    bad[np.argmax(m.dirichlet == 0)] = np.nan
+    _, res = nek.cg_solve(_dev(m.D), _dev(m.g), gs, _dev(bad), max_iter=5, raise_on_error=False)
+    assert res.status == nek.NEK_ERR_BREAKDOWN
+    _, res = nek.cg_solve(_dev(m.D), _dev(m.g), gs, _dev(b), max_iter=3, rel_tol=1e-12,
+                          raise_on_error=False)
+    assert res.status == nek.NEK_ERR_NOCONV and res.iters == 3
+    with pytest.raises(nek.NekError):
+        nek.cg_solve(_dev(m.D), _dev(m.g), gs, _dev(b), max_iter=3, rel_tol=1e-12)
+    # zero rhs: x = 0 with no iterations
+    x, res = nek.cg_solve(_dev(m.D), _dev(m.g), gs, _dev(np.zeros(m.P)), max_iter=5)
+    assert res.iters == 0 and torch.count_nonzero(x).item() == 0
+    gs.close()
+
+
+def test_ax_argument_errors_on_device(nek):
+    m = _mesh((2, 1, 1), 3)
+    u = _dev(synth.local_uniform(m.P))
+    with pytest.raises(nek.NekError) as ei:
+        nek._check(nek._lib.nek_ax(m.E, 3, u.data_ptr(), _dev(m.D).data_ptr(), _dev(m.g).data_ptr(),
+                                   u.data_ptr(), None), "nek_ax")
+    assert ei.value.code == nek.NEK_ERR_ARG
+    with pytest.raises(TypeError):
+        nek.ax(u.float(), _dev(m.D), _dev(m.g), 3)
