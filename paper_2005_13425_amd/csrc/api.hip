@@ -13,8 +13,8 @@
 
 struct nek_gs {
     nek::GsDevice d;
-    double *partials = nullptr;      // RED_BLOCKS doubles for nek_gs_dot
-    unsigned int *ticket = nullptr;  // one counter
+    double *partials = nullptr;      // reduction site of nek_gs_dot
+    unsigned int *ticket = nullptr;  // its counters
 };
 
 namespace nek {
@@ -200,8 +200,7 @@ int nek_ax(int64_t E, int N, const double *u, const double *D, const double *g, 
     int rc = check_ax_args("nek_ax", E, N, u, D, g, w, sizeof(double));
     if (rc) return rc;
     if (!aligned8(D) || !aligned8(g)) return fail(NEK_ERR_ARG, "nek_ax: misaligned D or g");
-    NEK_HIP(launch_ax_f64(E, N, D, g, nullptr, const_cast<double *>(u), nullptr, w, nullptr,
-                          (hipStream_t)stream));
+    NEK_HIP(launch_ax_f64(E, N, D, g, const_cast<double *>(u), w, AxFuse{}, (hipStream_t)stream));
     return NEK_OK;
 }
 
@@ -214,8 +213,8 @@ int nek_ax_f32(int64_t E, int N, const double *u, const float *D32, const void *
         return fail(NEK_ERR_UNSUPPORTED, "nek_ax_f32: g_dtype must be NEK_G_F32 or NEK_G_BF16");
     if (g_dtype == NEK_G_F32 && ((uintptr_t)g_lo & 3u))
         return fail(NEK_ERR_ARG, "nek_ax_f32: misaligned g");
-    NEK_HIP(launch_ax_f32(E, N, D32, g_lo, g_dtype, nullptr, const_cast<double *>(u), nullptr, w,
-                          nullptr, (hipStream_t)stream));
+    NEK_HIP(launch_ax_f32(E, N, D32, g_lo, g_dtype, const_cast<double *>(u), w, AxFuse{},
+                          (hipStream_t)stream));
     return NEK_OK;
 }
 
@@ -235,14 +234,13 @@ int nek_convert_g(int64_t E, int N, const double *g, int g_dtype, void *g_lo, vo
 // ---------------------------------------------------------------- gather-scatter
 static void gs_free(nek_gs *h) {
     if (!h) return;
-    (void)hipFree(h->d.row_off);
-    (void)hipFree(h->d.row_idx);
-    (void)hipFree(h->d.row_keep);
-    (void)hipFree(h->d.own);
+    (void)hipFree(h->d.arena);
     (void)hipFree(h->partials);
     (void)hipFree(h->ticket);
     delete h;
 }
+
+static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 int nek_gs_create(int64_t E, int N, const int64_t *glo, const uint8_t *dirichlet, nek_gs **out) {
     clear_error();
@@ -251,7 +249,9 @@ int nek_gs_create(int64_t E, int N, const int64_t *glo, const uint8_t *dirichlet
     if (E < 1) return fail(NEK_ERR_ARG, "nek_gs_create: E must be >= 1");
     if (N < 1 || N > NEK_MAX_DEGREE) return fail(NEK_ERR_UNSUPPORTED, "nek_gs_create: degree must be in 1..15");
     if (!glo) return fail(NEK_ERR_ARG, "nek_gs_create: glo is null");
-    const int64_t P = E * n3_of(N);
+    const int n = N + 1;
+    const int64_t n3 = n3_of(N);
+    const int64_t P = E * n3;
     if (P >= ((int64_t)1 << 31)) return fail(NEK_ERR_ARG, "nek_gs_create: E*(N+1)^3 must be < 2^31");
 
     // dense renumbering of the ids: counting when the id range is compact
@@ -275,64 +275,142 @@ int nek_gs_create(int64_t E, int N, const int64_t *glo, const uint8_t *dirichlet
         std::sort(ids.begin(), ids.end());
         ids.erase(std::unique(ids.begin(), ids.end()), ids.end());
         U = (int64_t)ids.size();
-        for (int64_t L = 0; L < P; ++L)
-            dense[(size_t)L] = (int32_t)(std::lower_bound(ids.begin(), ids.end(), glo[L]) - ids.begin());
+        std::vector<int32_t> first_seen((size_t)U, -1);
+        int32_t next = 0;
+        for (int64_t L = 0; L < P; ++L) {
+            const size_t sid = (size_t)(std::lower_bound(ids.begin(), ids.end(), glo[L]) - ids.begin());
+            if (first_seen[sid] < 0) first_seen[sid] = next++;
+            dense[(size_t)L] = first_seen[sid];
+        }
     }
-    // copies of every node, in ascending local index (counting sort)
-    std::vector<int32_t> cnt((size_t)U + 1, 0), first((size_t)U, -1);
+    // copies of every node in ascending local index (counting sort); since the
+    // dense ids are assigned in order of first appearance, node order is the
+    // order of first copies
+    std::vector<int32_t> start((size_t)U + 1, 0);
     std::vector<uint8_t> masked((size_t)U, 0);
     for (int64_t L = 0; L < P; ++L) {
         const int32_t G = dense[(size_t)L];
-        cnt[(size_t)G + 1]++;
-        if (first[(size_t)G] < 0) first[(size_t)G] = (int32_t)L;
+        start[(size_t)G + 1]++;
         if (dirichlet && dirichlet[L]) masked[(size_t)G] = 1;
     }
-    for (int64_t G = 0; G < U; ++G) cnt[(size_t)G + 1] += cnt[(size_t)G];
-    std::vector<int32_t> copies((size_t)P), fillpos(cnt.begin(), cnt.end() - 1);
+    for (int64_t G = 0; G < U; ++G) start[(size_t)G + 1] += start[(size_t)G];
+    std::vector<int32_t> copies((size_t)P), fillpos(start.begin(), start.end() - 1);
     for (int64_t L = 0; L < P; ++L) copies[(size_t)fillpos[(size_t)dense[(size_t)L]]++] = (int32_t)L;
 
-    std::vector<int32_t> row_off(1, 0), row_idx;
-    std::vector<uint8_t> row_keep, own((size_t)P, 0);
-    int64_t n_masked = 0;
-    for (int64_t L = 0; L < P; ++L) {
+    // element-interior points (1 <= i,j,k <= n-2) unshared and unmasked?
+    auto interior = [&](int64_t L) {
+        const int64_t q = L % n3;
+        const int i = (int)(q % n), j = (int)((q / n) % n), k = (int)(q / ((int64_t)n * n));
+        return i > 0 && i < n - 1 && j > 0 && j < n - 1 && k > 0 && k < n - 1;
+    };
+    bool interior_dot = true;
+    for (int64_t L = 0; L < P && interior_dot; ++L) {
+        if (!interior(L)) continue;
         const int32_t G = dense[(size_t)L];
-        if (first[(size_t)G] != (int32_t)L) continue;
-        own[(size_t)L] = 1;
-        const int32_t c0 = cnt[(size_t)G], c1 = cnt[(size_t)G + 1];
-        if (masked[(size_t)G]) ++n_masked;
-        if (c1 - c0 > 1 || masked[(size_t)G]) {
-            for (int32_t q = c0; q < c1; ++q) row_idx.push_back(copies[(size_t)q]);
-            row_off.push_back((int32_t)row_idx.size());
-            row_keep.push_back(masked[(size_t)G] ? 0 : 1);
+        if (start[(size_t)G + 1] - start[(size_t)G] != 1 || masked[(size_t)G]) interior_dot = false;
+    }
+
+    // groups
+    std::vector<int32_t> zero;                       // copies of masked nodes
+    std::vector<std::vector<int32_t>> rows(GS_MAXC + 1);  // first copy ids per copy count
+    std::vector<int32_t> csr_nodes;
+    int64_t n_masked = 0, n_rows = 0, n_entries = 0;
+    for (int64_t G = 0; G < U; ++G) {
+        const int32_t c0 = start[(size_t)G], c1 = start[(size_t)G + 1];
+        const int c = c1 - c0;
+        if (masked[(size_t)G]) {
+            ++n_masked;
+            for (int32_t q = c0; q < c1; ++q) zero.push_back(copies[(size_t)q]);
+            continue;
         }
+        if (c == 1 && interior_dot && interior(copies[(size_t)c0])) continue;   // left to ax
+        ++n_rows;
+        n_entries += c;
+        if (c <= GS_MAXC) rows[(size_t)c].push_back((int32_t)G);
+        else csr_nodes.push_back((int32_t)G);
+    }
+    std::sort(zero.begin(), zero.end());
+
+    // one device arena: zero list | SoA groups | CSR offsets + entries | own bits
+    std::vector<int32_t> host;
+    struct Pending { int kind; int32_t rows; size_t idx_at; size_t off_at; };
+    std::vector<Pending> pend;
+    if (!zero.empty()) {
+        pend.push_back({0, (int32_t)zero.size(), host.size(), 0});
+        host.insert(host.end(), zero.begin(), zero.end());
+    }
+    for (int c = 1; c <= GS_MAXC; ++c) {
+        const auto &R = rows[(size_t)c];
+        if (R.empty()) continue;
+        const size_t at = host.size();
+        host.resize(at + (size_t)c * R.size());
+        for (size_t rr = 0; rr < R.size(); ++rr)
+            for (int m = 0; m < c; ++m)
+                host[at + (size_t)m * R.size() + rr] = copies[(size_t)start[(size_t)R[rr]] + m];
+        pend.push_back({c, (int32_t)R.size(), at, 0});
+    }
+    if (!csr_nodes.empty()) {
+        const size_t off_at = host.size();
+        host.resize(off_at + csr_nodes.size() + 1);
+        const size_t idx_at = host.size();
+        int32_t o = 0;
+        for (size_t rr = 0; rr < csr_nodes.size(); ++rr) {
+            host[off_at + rr] = o;
+            const int32_t G = csr_nodes[rr];
+            for (int32_t q = start[(size_t)G]; q < start[(size_t)G + 1]; ++q) {
+                host.push_back(copies[(size_t)q]);
+                ++o;
+            }
+        }
+        host[off_at + csr_nodes.size()] = o;
+        pend.push_back({-1, (int32_t)csr_nodes.size(), idx_at, off_at});
+    }
+    const size_t words = (size_t)((P + 31) / 32);
+    std::vector<uint32_t> own(words, 0u);
+    for (int64_t G = 0; G < U; ++G) {
+        const int32_t L = copies[(size_t)start[(size_t)G]];
+        own[(size_t)L >> 5] |= 1u << (L & 31);
     }
 
     nek_gs *h = new nek_gs();
-    h->d.E = E;
-    h->d.N = N;
-    h->d.P = P;
-    h->d.n_unique = U;
-    h->d.n_rows = (int64_t)row_keep.size();
-    h->d.n_entries = (int64_t)row_idx.size();
-    h->d.n_masked = n_masked;
-    hipError_t e = hipSuccess;
-    auto up = [&](void **dst, const void *src, size_t bytes) {
-        if (e != hipSuccess) return;
-        e = hipMalloc(dst, bytes ? bytes : 8);
-        if (e == hipSuccess && bytes) e = hipMemcpy(*dst, src, bytes, hipMemcpyHostToDevice);
-    };
-    up((void **)&h->d.row_off, row_off.data(), row_off.size() * sizeof(int32_t));
-    up((void **)&h->d.row_idx, row_idx.data(), row_idx.size() * sizeof(int32_t));
-    up((void **)&h->d.row_keep, row_keep.data(), row_keep.size());
-    up((void **)&h->d.own, own.data(), own.size());
-    if (e == hipSuccess) e = hipMalloc((void **)&h->partials, RED_BLOCKS * sizeof(double));
-    if (e == hipSuccess) e = hipMalloc((void **)&h->ticket, sizeof(unsigned int));
-    if (e == hipSuccess) e = hipMemset(h->ticket, 0, sizeof(unsigned int));
+    GsDevice &d = h->d;
+    d.E = E;
+    d.N = N;
+    d.P = P;
+    d.n_unique = U;
+    d.n_rows = n_rows;
+    d.n_entries = n_entries;
+    d.n_masked = n_masked;
+    d.n_zero = (int64_t)zero.size();
+    d.interior_dot = interior_dot;
+    const size_t idx_bytes = align256(host.size() * sizeof(int32_t) + 4);
+    const size_t bytes = idx_bytes + words * sizeof(uint32_t);
+    hipError_t e = hipMalloc(&d.arena, bytes);
+    if (e == hipSuccess && !host.empty())
+        e = hipMemcpy(d.arena, host.data(), host.size() * sizeof(int32_t), hipMemcpyHostToDevice);
+    d.own_bits = (uint32_t *)((char *)d.arena + idx_bytes);
+    if (e == hipSuccess) e = hipMemcpy(d.own_bits, own.data(), words * sizeof(uint32_t), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMalloc((void **)&h->partials, RED_SITE_DOUBLES * sizeof(double));
+    if (e == hipSuccess) e = hipMalloc((void **)&h->ticket, RED_TICKETS * sizeof(unsigned int));
+    if (e == hipSuccess) e = hipMemset(h->ticket, 0, RED_TICKETS * sizeof(unsigned int));
     if (e != hipSuccess) {
         gs_free(h);
         return fail(e == hipErrorOutOfMemory ? NEK_ERR_NOMEM : NEK_ERR_DEVICE,
                     std::string("nek_gs_create: ") + hipGetErrorString(e));
     }
+    const int32_t *base = (const int32_t *)d.arena;
+    d.args.ngroups = 0;
+    int32_t blocks = 0;
+    for (const Pending &q : pend) {
+        GsGroup &G = d.args.grp[d.args.ngroups++];
+        G.kind = q.kind;
+        G.rows = q.rows;
+        G.block0 = blocks;
+        G.idx = base + q.idx_at;
+        G.off = q.kind == -1 ? base + q.off_at : nullptr;
+        blocks += (q.rows + GS_THREADS - 1) / GS_THREADS;
+    }
+    d.args.nblocks = blocks;
     *out = h;
     return NEK_OK;
 }
@@ -361,16 +439,19 @@ int nek_dssum(const nek_gs *gs, double *w, void *stream) {
     clear_error();
     if (!gs || !w) return fail(NEK_ERR_ARG, "nek_dssum: null argument");
     if (!aligned8(w)) return fail(NEK_ERR_ARG, "nek_dssum: misaligned w");
-    NEK_HIP(launch_gs(gs->d, w, nullptr, (hipStream_t)stream));
+    NEK_HIP(launch_gs(gs->d, w, nullptr, RedSite{}, nullptr, (hipStream_t)stream));
     return NEK_OK;
 }
+
+static bool aligned16(const void *p) { return ((uintptr_t)p & 15u) == 0; }
 
 int nek_gs_dot(const nek_gs *gs, const double *a, const double *b, double *result, void *stream) {
     clear_error();
     if (!gs || !a || !b || !result) return fail(NEK_ERR_ARG, "nek_gs_dot: null argument");
-    if (!aligned8(a) || !aligned8(b) || !aligned8(result)) return fail(NEK_ERR_ARG, "nek_gs_dot: misaligned pointer");
-    NEK_HIP(launch_gdot(gs->d.P, a, b, gs->d.own, gs->partials, gs->ticket, result,
-                        (hipStream_t)stream));
+    if (!aligned16(a) || !aligned16(b) || !aligned8(result))
+        return fail(NEK_ERR_ARG, "nek_gs_dot: a and b must be 16-byte aligned");
+    const RedSite red{gs->partials, gs->partials + RED_MAX_BLOCKS, gs->ticket, nullptr, 0};
+    NEK_HIP(launch_gdot(gs->d.P, a, b, gs->d.own_bits, red, result, (hipStream_t)stream));
     return NEK_OK;
 }
 
@@ -386,13 +467,30 @@ void nek_cg_default_opts(nek_cg_opts *o) {
     o->reliable_drop = 0.0;
 }
 
-static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+// Workspace layout: r, p, w | interior partials of ax | reduction sites |
+// their counters | CG scalars | one scratch double.
+enum { SITE_INIT, SITE_GS, SITE_UPDATE, SITE_REPLACE, SITE_RESID, N_SITES };
+
+struct CgLayout {
+    size_t vec, axp, sites, tickets, scalars, scratch, total;
+};
+
+static CgLayout cg_layout(int64_t E, int N) {
+    const size_t P = (size_t)(E * n3_of(N));
+    CgLayout L;
+    L.vec = 0;
+    L.axp = 3 * align256(P * sizeof(double));
+    L.sites = L.axp + align256((size_t)ax_blocks(E, N) * sizeof(double));
+    L.tickets = L.sites + align256(N_SITES * RED_SITE_DOUBLES * sizeof(double));
+    L.scalars = L.tickets + align256(N_SITES * RED_TICKETS * sizeof(unsigned int));
+    L.scratch = L.scalars + align256(sizeof(CgScalars));
+    L.total = L.scratch + align256(sizeof(double));
+    return L;
+}
 
 size_t nek_cg_workspace_bytes(int64_t E, int N) {
     if (E < 1 || N < 1 || N > NEK_MAX_DEGREE) return 0;
-    const size_t P = (size_t)(E * n3_of(N));
-    return 3 * align256(P * sizeof(double)) + align256(RED_BLOCKS * sizeof(double)) +
-           align256(sizeof(CgScalars)) + align256(sizeof(double));
+    return cg_layout(E, N).total;
 }
 
 namespace {
@@ -422,8 +520,8 @@ int nek_cg_solve(int64_t E, int N, const double *D, const double *g, const nek_g
     if (E < 1) return fail(NEK_ERR_ARG, "nek_cg_solve: E must be >= 1");
     if (N < 1 || N > NEK_MAX_DEGREE) return fail(NEK_ERR_UNSUPPORTED, "nek_cg_solve: degree must be in 1..15");
     if (!D || !g || !gs || !b || !x) return fail(NEK_ERR_ARG, "nek_cg_solve: null argument");
-    if (!aligned8(D) || !aligned8(g) || !aligned8(b) || !aligned8(x))
-        return fail(NEK_ERR_ARG, "nek_cg_solve: misaligned pointer");
+    if (!aligned8(D) || !aligned8(g) || !aligned16(b) || !aligned16(x))
+        return fail(NEK_ERR_ARG, "nek_cg_solve: misaligned pointer (b and x need 16 bytes)");
     if (gs->d.E != E || gs->d.N != N) return fail(NEK_ERR_ARG, "nek_cg_solve: gather-scatter built for another mesh");
     if (b == x) return fail(NEK_ERR_ARG, "nek_cg_solve: b and x must differ");
     if (opts.max_iter < 0) return fail(NEK_ERR_ARG, "nek_cg_solve: max_iter must be >= 0");
@@ -454,13 +552,20 @@ int nek_cg_solve(int64_t E, int N, const double *D, const double *g, const nek_g
                         std::string("nek_cg_solve: workspace allocation: ") + hipGetErrorString(e));
         own_ws = true;
     }
+    const CgLayout lay = cg_layout(E, N);
     const size_t vb = align256((size_t)P * sizeof(double));
     double *r = (double *)ws;
     double *p = (double *)(ws + vb);
     double *w = (double *)(ws + 2 * vb);
-    double *partials = (double *)(ws + 3 * vb);
-    CgScalars *sc = (CgScalars *)(ws + 3 * vb + align256(RED_BLOCKS * sizeof(double)));
-    double *scratch1 = (double *)((char *)sc + align256(sizeof(CgScalars)));   // one double
+    double *axp = (double *)(ws + lay.axp);
+    double *site_mem = (double *)(ws + lay.sites);
+    unsigned int *tickets = (unsigned int *)(ws + lay.tickets);
+    CgScalars *sc = (CgScalars *)(ws + lay.scalars);
+    double *scratch1 = (double *)(ws + lay.scratch);   // one double
+    auto site = [&](int k, const double *extra, long nextra) {
+        double *base = site_mem + (size_t)k * RED_SITE_DOUBLES;
+        return RedSite{base, base + RED_MAX_BLOCKS, tickets + (size_t)k * RED_TICKETS, extra, nextra};
+    };
 
     if (!g_snap.buf) {
         hipError_t e = hipHostMalloc((void **)&g_snap.buf, 2 * sizeof(CgScalars), hipHostMallocDefault);
@@ -470,6 +575,36 @@ int nek_cg_solve(int64_t E, int N, const double *D, const double *g, const nek_g
         }
     }
     CgScalars *snap = g_snap.buf;
+    const uint32_t *own = gs->d.own_bits;
+    const bool idot = gs->d.interior_dot;
+    const int64_t ax_parts = idot ? ax_blocks(E, N) : 0;
+
+    // one CG iteration; `first` uses p = b as set by the init kernel
+    const RedSite red_gs = site(SITE_GS, axp, (long)ax_parts);
+    const RedSite red_upd = site(SITE_UPDATE, nullptr, 0);
+    auto iterate = [&](bool first) -> hipError_t {
+        AxFuse fz;
+        fz.sc = sc;
+        fz.partials = idot ? axp : nullptr;
+        if (!first) {
+            fz.r = r;
+            fz.x = x;
+        }
+        hipError_t e = mixed ? launch_ax_f32(E, N, opts.D32, opts.g_lo, g_dtype, p, w, fz, s)
+                             : launch_ax_f64(E, N, D, g, p, w, fz, s);
+        if (e != hipSuccess) return e;
+        e = launch_gs(gs->d, w, p, red_gs, sc, s);
+        if (e != hipSuccess) return e;
+        return launch_cg_update(P, r, w, own, red_upd, sc, s);
+    };
+    // w <- mask(dssum(A64 x)) with x brought up to date first
+    auto true_ax = [&]() -> hipError_t {
+        hipError_t e = launch_cg_finish(P, x, p, sc, s);
+        if (e != hipSuccess) return e;
+        e = launch_ax_f64(E, N, D, g, x, w, AxFuse{}, s);
+        if (e != hipSuccess) return e;
+        return launch_gs(gs->d, w, nullptr, RedSite{}, nullptr, s);
+    };
 
     int rc = NEK_OK;
     hipError_t he = hipSuccess;
@@ -482,23 +617,14 @@ int nek_cg_solve(int64_t E, int N, const double *D, const double *g, const nek_g
         if (he != hipSuccess) { rc = check_hip(he, #call); goto out; }   \
     } while (0)
     {
-        CG_TRY(launch_cg_reset(sc, opts.max_iter, opts.rel_tol, drop, s));
-        CG_TRY(launch_cg_init(P, b, x, r, p, gs->d.own, partials, sc, s));
-        const int *done = &sc->done;
+        CG_TRY(launch_cg_reset(sc, tickets, N_SITES * RED_TICKETS, opts.max_iter, opts.rel_tol, drop, s));
+        CG_TRY(launch_cg_init(P, b, x, r, p, own, site(SITE_INIT, nullptr, 0), sc, s));
         int enq = 0;
         bool first = true;
         while (enq < opts.max_iter) {
             const int chunk = std::min(check_every, opts.max_iter - enq);
             for (int q = 0; q < chunk; ++q) {
-                // first iteration: p = b as set by init; later ones fuse p <- r + beta p
-                const double *rr = first ? nullptr : r;
-                if (mixed)
-                    CG_TRY(launch_ax_f32(E, N, opts.D32, opts.g_lo, g_dtype, rr, p, &sc->beta, w, done, s));
-                else
-                    CG_TRY(launch_ax_f64(E, N, D, g, rr, p, &sc->beta, w, done, s));
-                CG_TRY(launch_gs(gs->d, w, done, s));
-                CG_TRY(launch_cg_dot_pw(P, p, w, gs->d.own, partials, sc, s));
-                CG_TRY(launch_cg_update(P, x, r, p, w, gs->d.own, partials, sc, s));
+                CG_TRY(iterate(first));
                 first = false;
             }
             enq += chunk;
@@ -508,24 +634,24 @@ int nek_cg_solve(int64_t E, int N, const double *D, const double *g, const nek_g
             if (snap->done) break;
             if (mixed && snap->need_replace) {
                 // reliable update: r <- b - mask(dssum(A64 x)) in FP64
-                CG_TRY(launch_ax_f64(E, N, D, g, nullptr, x, nullptr, w, nullptr, s));
-                CG_TRY(launch_gs(gs->d, w, nullptr, s));
-                CG_TRY(launch_cg_replace(P, b, w, r, gs->d.own, partials, sc, s));
+                CG_TRY(true_ax());
+                CG_TRY(launch_cg_replace(P, b, w, r, own, site(SITE_REPLACE, nullptr, 0), sc, s));
             }
         }
+        CG_TRY(launch_cg_finish(P, x, p, sc, s));
         CG_TRY(hipMemcpyAsync(snap, sc, sizeof(CgScalars), hipMemcpyDeviceToHost, s));
         CG_TRY(hipStreamSynchronize(s));
         S = *snap;
         if (opts.true_residual || mixed) {
-            // ||b - mask(dssum(A64 x))|| over unique nodes, in FP64
-            CG_TRY(launch_ax_f64(E, N, D, g, nullptr, x, nullptr, w, nullptr, s));
-            CG_TRY(launch_gs(gs->d, w, nullptr, s));
-            CG_TRY(launch_gdiff2(P, b, w, gs->d.own, partials, &sc->ticket[3], scratch1, s));
-            double t2 = 0.0;
+            // ||b - mask(dssum(A64 x))|| over unique nodes, in FP64 (x is up to date:
+            // the finish kernel above ran; running it again is a no-op only if the
+            // lag flag says so, so evaluate A x directly)
+            CG_TRY(launch_ax_f64(E, N, D, g, x, w, AxFuse{}, s));
+            CG_TRY(launch_gs(gs->d, w, nullptr, RedSite{}, nullptr, s));
+            CG_TRY(launch_gdiff2(P, b, w, own, site(SITE_RESID, nullptr, 0), scratch1, s));
             CG_TRY(hipMemcpyAsync(&snap[1].bb, scratch1, sizeof(double), hipMemcpyDeviceToHost, s));
             CG_TRY(hipStreamSynchronize(s));
-            t2 = snap[1].bb;
-            true_rel = S.bb > 0.0 ? sqrt(t2 / S.bb) : 0.0;
+            true_rel = S.bb > 0.0 ? sqrt(snap[1].bb / S.bb) : 0.0;
         }
     }
 out:

@@ -23,6 +23,7 @@
 //   * optionally the CG direction update p <- r + beta p is fused into the
 //     load of u, writing p back once.
 #include "nek_internal.h"
+#include "reduce.h"
 
 namespace nek {
 namespace {
@@ -82,10 +83,8 @@ __device__ __forceinline__ float load_g<float, uint16_t>(const uint16_t *p) {
 // read once or twice.
 template <int NX, typename T, typename GT, bool FUSE>
 __global__ void __launch_bounds__((AxShape<NX, T>::THREADS), (AxShape<NX, T>::MINW))
-ax_kernel(int64_t E, const T *__restrict__ D, const GT *__restrict__ g,
-          const double *__restrict__ r, double *__restrict__ p,
-          const double *__restrict__ beta, double *__restrict__ w,
-          const int *__restrict__ done)
+ax_kernel(int64_t E, const T *__restrict__ D, const GT *__restrict__ g, double *__restrict__ p,
+          double *__restrict__ w, AxFuse fz)
 {
     using S = AxShape<NX, T>;
     constexpr int NN = S::NN;
@@ -95,7 +94,7 @@ ax_kernel(int64_t E, const T *__restrict__ D, const GT *__restrict__ g,
     constexpr int LS = S::LS;
     constexpr int BUF = S::BUF;
 
-    if (done != nullptr && *done) return;   // uniform: CG already finished
+    if (FUSE && fz.sc->done) return;   // uniform: CG already finished
 
     __shared__ T lds[EPB * 3 * BUF];
 
@@ -112,29 +111,42 @@ ax_kernel(int64_t E, const T *__restrict__ D, const GT *__restrict__ g,
     T *B1 = B0 + BUF;
     T *B2 = B1 + BUF;
 
-    // ---- 1. u column (optionally p <- r + beta p on the way in)
+    // ---- 1. u column (in the CG: x += alpha p_old and p <- r + beta p_old first)
     T ucol[NX];
+    double pcol[NX];   // FP64 p of this column, kept for the interior (p, w) sum
     const int64_t base = e * N3 + c;
     if (active) {
-        double tmp[NX];
 #pragma unroll
-        for (int k = 0; k < NX; ++k) tmp[k] = p[base + k * NN];
+        for (int k = 0; k < NX; ++k) pcol[k] = p[base + k * NN];
         if constexpr (FUSE) {
-            const double bt = *beta;
-            double rr[NX];
+            if (fz.x != nullptr && fz.sc->lag_applied == 0) {
+                const double al = fz.sc->alpha;
+                double xx[NX];
 #pragma unroll
-            for (int k = 0; k < NX; ++k) rr[k] = r[base + k * NN];
+                for (int k = 0; k < NX; ++k) xx[k] = fz.x[base + k * NN];
 #pragma unroll
-            for (int k = 0; k < NX; ++k) {
-                tmp[k] = rr[k] + bt * tmp[k];
-                p[base + k * NN] = tmp[k];
+                for (int k = 0; k < NX; ++k) fz.x[base + k * NN] = xx[k] + al * pcol[k];
+            }
+            if (fz.r != nullptr) {
+                const double bt = fz.sc->beta;
+                double rr[NX];
+#pragma unroll
+                for (int k = 0; k < NX; ++k) rr[k] = fz.r[base + k * NN];
+#pragma unroll
+                for (int k = 0; k < NX; ++k) {
+                    pcol[k] = rr[k] + bt * pcol[k];
+                    p[base + k * NN] = pcol[k];
+                }
             }
         }
 #pragma unroll
-        for (int k = 0; k < NX; ++k) ucol[k] = (T)tmp[k];
+        for (int k = 0; k < NX; ++k) ucol[k] = (T)pcol[k];
     } else {
 #pragma unroll
-        for (int k = 0; k < NX; ++k) ucol[k] = T(0);
+        for (int k = 0; k < NX; ++k) {
+            ucol[k] = T(0);
+            pcol[k] = 0.0;
+        }
     }
 
     // geometric factors of the first two layers go out now, the rest one
@@ -261,36 +273,49 @@ ax_kernel(int64_t E, const T *__restrict__ D, const GT *__restrict__ g,
     __syncthreads();
 
     // ---- 6. w = t part + r part + s part
+    double pw = 0.0;
     if (active) {
+        const bool inner_col = a > 0 && a < NX - 1 && b > 0 && b < NX - 1;
 #pragma unroll
-        for (int k = 0; k < NX; ++k)
-            w[base + k * NN] = (double)(wcol[k] + B0[k * LS + col] + B1[k * LS + col]);
+        for (int k = 0; k < NX; ++k) {
+            const double wv = (double)(wcol[k] + B0[k * LS + col] + B1[k * LS + col]);
+            w[base + k * NN] = wv;
+            if (FUSE && inner_col && k > 0 && k < NX - 1) pw += pcol[k] * wv;
+        }
+    }
+    // ---- 7. CG: per-workgroup sum of p w over element-interior points
+    if constexpr (FUSE) {
+        if (fz.partials != nullptr) {
+            __shared__ double red[S::THREADS / 64];
+            const double bs = block_sum<S::THREADS>(pw, red);
+            if (threadIdx.x == 0) fz.partials[blockIdx.x] = bs;
+        }
     }
 }
 
 template <int NX, typename T, typename GT>
-hipError_t launch_one(int64_t E, const T *D, const GT *g, const double *r, double *p,
-                      const double *beta, double *w, const int *done, hipStream_t s)
+hipError_t launch_one(int64_t E, const T *D, const GT *g, double *p, double *w, const AxFuse &fz,
+                      hipStream_t s)
 {
     using S = AxShape<NX, T>;
     const int64_t blocks = (E + S::EPB - 1) / S::EPB;
     if (blocks > 0x7fffffff) return hipErrorInvalidValue;
-    if (r != nullptr)
+    if (fz.sc != nullptr)
         hipLaunchKernelGGL((ax_kernel<NX, T, GT, true>), dim3((unsigned)blocks), dim3(S::THREADS),
-                           0, s, E, D, g, r, p, beta, w, done);
+                           0, s, E, D, g, p, w, fz);
     else
         hipLaunchKernelGGL((ax_kernel<NX, T, GT, false>), dim3((unsigned)blocks), dim3(S::THREADS),
-                           0, s, E, D, g, r, p, beta, w, done);
+                           0, s, E, D, g, p, w, fz);
     return hipGetLastError();
 }
 
 template <typename T, typename GT>
-hipError_t dispatch(int64_t E, int N, const T *D, const GT *g, const double *r, double *p,
-                    const double *beta, double *w, const int *done, hipStream_t s)
+hipError_t dispatch(int64_t E, int N, const T *D, const GT *g, double *p, double *w,
+                    const AxFuse &fz, hipStream_t s)
 {
     switch (N + 1) {
 #define NEK_CASE(NX) \
-    case NX: return launch_one<NX, T, GT>(E, D, g, r, p, beta, w, done, s);
+    case NX: return launch_one<NX, T, GT>(E, D, g, p, w, fz, s);
         NEK_CASE(2) NEK_CASE(3) NEK_CASE(4) NEK_CASE(5) NEK_CASE(6) NEK_CASE(7) NEK_CASE(8)
         NEK_CASE(9) NEK_CASE(10) NEK_CASE(11) NEK_CASE(12) NEK_CASE(13) NEK_CASE(14)
         NEK_CASE(15) NEK_CASE(16)
@@ -323,21 +348,27 @@ __global__ void convert_g_kernel(int64_t count, const double *__restrict__ g, in
 
 }  // namespace
 
-hipError_t launch_ax_f64(int64_t E, int N, const double *D, const double *g, const double *r,
-                         double *p, const double *beta, double *w, const int *done, hipStream_t s)
+hipError_t launch_ax_f64(int64_t E, int N, const double *D, const double *g, double *p, double *w,
+                         const AxFuse &fz, hipStream_t s)
 {
-    return dispatch<double, double>(E, N, D, g, r, p, beta, w, done, s);
+    return dispatch<double, double>(E, N, D, g, p, w, fz, s);
 }
 
 hipError_t launch_ax_f32(int64_t E, int N, const float *D32, const void *g_lo, int g_dtype,
-                         const double *r, double *p, const double *beta, double *w,
-                         const int *done, hipStream_t s)
+                         double *p, double *w, const AxFuse &fz, hipStream_t s)
 {
     if (g_dtype == NEK_G_F32)
-        return dispatch<float, float>(E, N, D32, (const float *)g_lo, r, p, beta, w, done, s);
+        return dispatch<float, float>(E, N, D32, (const float *)g_lo, p, w, fz, s);
     if (g_dtype == NEK_G_BF16)
-        return dispatch<float, uint16_t>(E, N, D32, (const uint16_t *)g_lo, r, p, beta, w, done, s);
+        return dispatch<float, uint16_t>(E, N, D32, (const uint16_t *)g_lo, p, w, fz, s);
     return hipErrorInvalidValue;
+}
+
+int64_t ax_blocks(int64_t E, int N)
+{
+    const int nn = (N + 1) * (N + 1);
+    const int64_t epb = nn >= 64 ? 1 : 256 / nn;   // AxShape<N+1, .>::EPB
+    return (E + epb - 1) / epb;
 }
 
 hipError_t launch_convert_g(int64_t count, const double *g, int g_dtype, void *out, hipStream_t s)

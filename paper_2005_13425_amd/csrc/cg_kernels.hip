@@ -1,85 +1,108 @@
-// cg_kernels.hip -- direct-stiffness summation with masking, deterministic
-// reductions and the vector steps of unpreconditioned CG (Sec. III, Sec. V,
-// Sec. VI-B), all on the device.
+// cg_kernels.hip -- direct-stiffness summation with masking and the vector
+// steps of unpreconditioned CG (Sec. III, Sec. V, Sec. VI-B), all on the device.
 //
-// Reductions: every kernel reduces a fixed grid of RED_BLOCKS workgroups
-// (wavefront shuffles, then LDS), writes one partial per workgroup, and the
-// last workgroup to finish (ticket counter) sums the partials in index order
-// and updates the CG scalars in device memory.  The order of every sum is
-// fixed by the grid, so results are bitwise reproducible from run to run.
+// Gather-scatter: nodes are grouped by copy count, each group stored as
+// structure-of-arrays indices, so a thread handles one node with a fixed trip
+// count and lanes load their indices coalesced.  Copies are summed in
+// ascending local index (the oracle's order), masked nodes are written as 0.
+// In the CG the same launch also accumulates the (p, w) contributions of the
+// shared nodes; the element-interior part comes from the ax launch before it,
+// and the last workgroup turns the total into alpha.
+//
+// Vector steps: double2 loads, VEC_PAIRS pairs per thread issued together;
+// the first-copy mask is one bit per point.
 #include "nek_internal.h"
+#include "reduce.h"
 
 namespace nek {
 namespace {
 
-__device__ __forceinline__ double wave_sum(double v) {
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
-    return v;
-}
-
-// sum over the workgroup (RED_THREADS threads); result valid in thread 0
-__device__ __forceinline__ double block_sum(double v, double *lds) {
-    v = wave_sum(v);
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    if (lane == 0) lds[wave] = v;
-    __syncthreads();
-    double s = 0.0;
-    if (threadIdx.x == 0) {
-#pragma unroll
-        for (int q = 0; q < RED_THREADS / 64; ++q) s += lds[q];
-    }
-    __syncthreads();
-    return s;
-}
-
-__device__ __forceinline__ double load_coherent(const double *p) {
-    unsigned long long bits =
-        __hip_atomic_load((const unsigned long long *)p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    return __longlong_as_double((long long)bits);
-}
-
-// Publish this workgroup's partial; returns true (in every thread) for the
-// last workgroup, which then holds the ordered total in thread 0 via *total.
-__device__ bool finish_partials(double s, double *partials, unsigned int *ticket,
-                                double *total, double *lds) {
-    __shared__ int last;
-    if (threadIdx.x == 0) {
-        partials[blockIdx.x] = s;
-        __threadfence();
-        unsigned int t = atomicAdd(ticket, 1u);
-        last = (t == gridDim.x - 1);
-    }
-    __syncthreads();
-    if (!last) return false;
-    __threadfence();
-    double v = 0.0;
-    for (unsigned int q = threadIdx.x; q < gridDim.x; q += blockDim.x) v += load_coherent(&partials[q]);
-    v = block_sum(v, lds);
-    if (threadIdx.x == 0) {
-        *total = v;
-        *ticket = 0u;   // ready for the next launch
-    }
-    return true;
+__device__ __forceinline__ unsigned own_pair(const uint32_t *own, int64_t pt) {
+    // bits of points pt, pt+1 (pt even)
+    return (own[pt >> 5] >> (pt & 31)) & 3u;
 }
 
 // ---------------------------------------------------------------- dssum + mask
-__global__ void gs_kernel(int64_t n_rows, const int32_t *__restrict__ off,
-                          const int32_t *__restrict__ idx, const uint8_t *__restrict__ keep,
-                          double *__restrict__ w, const int *__restrict__ done) {
-    if (done != nullptr && *done) return;
-    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    for (int64_t row = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; row < n_rows; row += stride) {
-        const int32_t o0 = off[row], o1 = off[row + 1];
-        double s = 0.0;
-        for (int32_t o = o0; o < o1; ++o) s += w[idx[o]];
-        if (!keep[row]) s = 0.0;
-        for (int32_t o = o0; o < o1; ++o) w[idx[o]] = s;
+template <int C>
+__device__ __forceinline__ double gs_row(const GsGroup &G, int32_t row, double *__restrict__ w,
+                                         const double *__restrict__ p) {
+    int32_t id[C];
+#pragma unroll
+    for (int m = 0; m < C; ++m) id[m] = G.idx[(int64_t)m * G.rows + row];
+    double v[C];
+#pragma unroll
+    for (int m = 0; m < C; ++m) v[m] = w[id[m]];
+    double pv = p ? p[id[0]] : 0.0;
+    double s = 0.0;
+#pragma unroll
+    for (int m = 0; m < C; ++m) s += v[m];
+    if (C > 1) {
+#pragma unroll
+        for (int m = 0; m < C; ++m) w[id[m]] = s;
+    }
+    return pv * s;
+}
+
+__device__ __forceinline__ double gs_vblock(const GsArgs &a, int vb, double *__restrict__ w,
+                                            const double *__restrict__ p) {
+    int g = 0;
+    while (g + 1 < a.ngroups && vb >= a.grp[g + 1].block0) ++g;
+    const GsGroup &G = a.grp[g];
+    const int32_t row = (vb - G.block0) * GS_THREADS + (int32_t)threadIdx.x;
+    double contrib = 0.0;
+    if (row < G.rows) {
+        switch (G.kind) {
+        case 0: w[G.idx[row]] = 0.0; break;
+        case 1: contrib = gs_row<1>(G, row, w, p); break;
+        case 2: contrib = gs_row<2>(G, row, w, p); break;
+        case 3: contrib = gs_row<3>(G, row, w, p); break;
+        case 4: contrib = gs_row<4>(G, row, w, p); break;
+        case 5: contrib = gs_row<5>(G, row, w, p); break;
+        case 6: contrib = gs_row<6>(G, row, w, p); break;
+        case 7: contrib = gs_row<7>(G, row, w, p); break;
+        case 8: contrib = gs_row<8>(G, row, w, p); break;
+        default: {   // CSR rows with many copies
+            const int32_t o0 = G.off[row], o1 = G.off[row + 1];
+            double s = 0.0;
+            for (int32_t o = o0; o < o1; ++o) s += w[G.idx[o]];
+            for (int32_t o = o0; o < o1; ++o) w[G.idx[o]] = s;
+            if (p) contrib = p[G.idx[o0]] * s;
+        }
+        }
+    }
+    return contrib;
+}
+
+// Workgroup b handles virtual blocks b, b + grid, ... of the group table.
+__global__ void __launch_bounds__(GS_THREADS)
+gs_kernel(GsArgs a, double *__restrict__ w, const double *__restrict__ p, RedSite red,
+          CgScalars *sc) {
+    if (sc != nullptr && sc->done) return;
+    __shared__ double lds[GS_THREADS / 64];
+    double contrib = 0.0;
+    for (int vb = blockIdx.x; vb < a.nblocks; vb += gridDim.x) contrib += gs_vblock(a, vb, w, p);
+    if (sc == nullptr) return;
+    const double bs = block_sum<GS_THREADS>(contrib, lds);
+    double tot;
+    if (grid_finish<GS_THREADS>(bs, red, &tot, lds) && threadIdx.x == 0) {
+        sc->pw = tot;
+        if (!(tot > 0.0) || !__builtin_isfinite(tot)) {
+            sc->status = NEK_ERR_BREAKDOWN;
+            sc->done = 1;
+            sc->alpha = 0.0;
+            sc->lag_applied = 1;
+        } else {
+            sc->alpha = sc->rho / tot;
+            sc->lag_applied = 0;
+        }
     }
 }
 
 // ---------------------------------------------------------------- CG steps
-__global__ void cg_reset_kernel(CgScalars *sc, int max_iter, double rel_tol, double drop) {
+__global__ void cg_reset_kernel(CgScalars *sc, unsigned int *tickets, int nticket, int max_iter,
+                                double rel_tol, double drop) {
+    for (int q = threadIdx.x; q < nticket; q += blockDim.x) tickets[q] = 0u;
+    if (threadIdx.x != 0) return;
     sc->bb = 0.0;
     sc->rho = 0.0;
     sc->pw = 0.0;
@@ -94,27 +117,66 @@ __global__ void cg_reset_kernel(CgScalars *sc, int max_iter, double rel_tol, dou
     sc->status = NEK_OK;
     sc->need_replace = 0;
     sc->n_replace = 0;
-    for (int q = 0; q < 4; ++q) sc->ticket[q] = 0u;
+    sc->lag_applied = 1;
+    sc->pad_ = 0;
 }
 
+// Pairs of a chunk: chunk c covers pairs [c * VEC_THREADS * VEC_PAIRS, ...);
+// thread t takes pairs base + t + m * VEC_THREADS (m < VEC_PAIRS), pair q
+// covering points 2q and 2q+1.  Workgroups stride over the chunks.
+constexpr int64_t VEC_CHUNK = (int64_t)VEC_THREADS * VEC_PAIRS;
+
+// the odd last point belongs to the last thread of the grid
+__device__ __forceinline__ bool owns_tail(int64_t P) {
+    return (P & 1) && blockIdx.x == gridDim.x - 1 && threadIdx.x == VEC_THREADS - 1;
+}
+
+__device__ __forceinline__ bool own_bit(const uint32_t *own, int64_t t) {
+    return (own[t >> 5] >> (t & 31)) & 1u;
+}
+
+#define NEK_CHUNKS                                                                       \
+    for (int64_t base = blockIdx.x * VEC_CHUNK; base < npairs; base += (int64_t)gridDim.x * VEC_CHUNK)
+
 // x = 0, r = b, p = b, rho = (b, b)
-__global__ void __launch_bounds__(RED_THREADS)
+__global__ void __launch_bounds__(VEC_THREADS)
 cg_init_kernel(int64_t P, const double *__restrict__ b, double *__restrict__ x,
-               double *__restrict__ r, double *__restrict__ p, const uint8_t *__restrict__ own,
-               double *partials, CgScalars *sc) {
-    __shared__ double lds[RED_THREADS / 64];
+               double *__restrict__ r, double *__restrict__ p, const uint32_t *__restrict__ own,
+               RedSite red, CgScalars *sc) {
+    __shared__ double lds[VEC_THREADS / 64];
+    const int64_t npairs = P >> 1;
     double acc = 0.0;
-    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < P; t += stride) {
+    NEK_CHUNKS {
+        double2 bv[VEC_PAIRS];
+#pragma unroll
+        for (int m = 0; m < VEC_PAIRS; ++m) {
+            const int64_t q = base + threadIdx.x + (int64_t)m * VEC_THREADS;
+            if (q < npairs) bv[m] = ((const double2 *)b)[q];
+        }
+#pragma unroll
+        for (int m = 0; m < VEC_PAIRS; ++m) {
+            const int64_t q = base + threadIdx.x + (int64_t)m * VEC_THREADS;
+            if (q < npairs) {
+                ((double2 *)x)[q] = make_double2(0.0, 0.0);
+                ((double2 *)r)[q] = bv[m];
+                ((double2 *)p)[q] = bv[m];
+                const unsigned o = own_pair(own, 2 * q);
+                if (o & 1u) acc += bv[m].x * bv[m].x;
+                if (o & 2u) acc += bv[m].y * bv[m].y;
+            }
+        }
+    }
+    if (owns_tail(P)) {
+        const int64_t t = P - 1;
         const double bv = b[t];
         x[t] = 0.0;
         r[t] = bv;
         p[t] = bv;
-        if (own[t]) acc += bv * bv;
+        if (own_bit(own, t)) acc += bv * bv;
     }
-    double s = block_sum(acc, lds);
+    const double s = block_sum<VEC_THREADS>(acc, lds);
     double tot;
-    if (finish_partials(s, partials, &sc->ticket[0], &tot, lds) && threadIdx.x == 0) {
+    if (grid_finish<VEC_THREADS>(s, red, &tot, lds) && threadIdx.x == 0) {
         sc->bb = tot;
         sc->rho = tot;
         sc->rho_last_true = tot;
@@ -127,48 +189,48 @@ cg_init_kernel(int64_t P, const double *__restrict__ b, double *__restrict__ x,
     }
 }
 
-// pw = (p, w); alpha = rho / pw
-__global__ void __launch_bounds__(RED_THREADS)
-cg_dot_pw_kernel(int64_t P, const double *__restrict__ p, const double *__restrict__ w,
-                 const uint8_t *__restrict__ own, double *partials, CgScalars *sc) {
+// r -= alpha w; rho' = (r, r); beta = rho' / rho; convergence and iteration cap
+__global__ void __launch_bounds__(VEC_THREADS)
+cg_update_kernel(int64_t P, double *__restrict__ r, const double *__restrict__ w,
+                 const uint32_t *__restrict__ own, RedSite red, CgScalars *sc) {
     if (sc->done) return;
-    __shared__ double lds[RED_THREADS / 64];
+    __shared__ double lds[VEC_THREADS / 64];
+    const double alpha = sc->alpha;
+    const int64_t npairs = P >> 1;
     double acc = 0.0;
-    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < P; t += stride)
-        if (own[t]) acc += p[t] * w[t];
-    double s = block_sum(acc, lds);
-    double tot;
-    if (finish_partials(s, partials, &sc->ticket[1], &tot, lds) && threadIdx.x == 0) {
-        sc->pw = tot;
-        if (!(tot > 0.0) || !__builtin_isfinite(tot)) {
-            sc->status = NEK_ERR_BREAKDOWN;
-            sc->done = 1;
-        } else {
-            sc->alpha = sc->rho / tot;
+    NEK_CHUNKS {
+        double2 rv[VEC_PAIRS], wv[VEC_PAIRS];
+#pragma unroll
+        for (int m = 0; m < VEC_PAIRS; ++m) {
+            const int64_t q = base + threadIdx.x + (int64_t)m * VEC_THREADS;
+            if (q < npairs) {
+                rv[m] = ((const double2 *)r)[q];
+                wv[m] = ((const double2 *)w)[q];
+            }
+        }
+#pragma unroll
+        for (int m = 0; m < VEC_PAIRS; ++m) {
+            const int64_t q = base + threadIdx.x + (int64_t)m * VEC_THREADS;
+            if (q < npairs) {
+                double2 nr;
+                nr.x = rv[m].x - alpha * wv[m].x;
+                nr.y = rv[m].y - alpha * wv[m].y;
+                ((double2 *)r)[q] = nr;
+                const unsigned o = own_pair(own, 2 * q);
+                if (o & 1u) acc += nr.x * nr.x;
+                if (o & 2u) acc += nr.y * nr.y;
+            }
         }
     }
-}
-
-// x += alpha p; r -= alpha w; rho' = (r, r); beta = rho'/rho
-__global__ void __launch_bounds__(RED_THREADS)
-cg_update_kernel(int64_t P, double *__restrict__ x, double *__restrict__ r,
-                 const double *__restrict__ p, const double *__restrict__ w,
-                 const uint8_t *__restrict__ own, double *partials, CgScalars *sc) {
-    if (sc->done) return;
-    __shared__ double lds[RED_THREADS / 64];
-    const double alpha = sc->alpha;
-    double acc = 0.0;
-    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < P; t += stride) {
-        x[t] = x[t] + alpha * p[t];
-        const double rv = r[t] - alpha * w[t];
-        r[t] = rv;
-        if (own[t]) acc += rv * rv;
+    if (owns_tail(P)) {
+        const int64_t t = P - 1;
+        const double nr = r[t] - alpha * w[t];
+        r[t] = nr;
+        if (own_bit(own, t)) acc += nr * nr;
     }
-    double s = block_sum(acc, lds);
+    const double s = block_sum<VEC_THREADS>(acc, lds);
     double tot;
-    if (finish_partials(s, partials, &sc->ticket[2], &tot, lds) && threadIdx.x == 0) {
+    if (grid_finish<VEC_THREADS>(s, red, &tot, lds) && threadIdx.x == 0) {
         sc->it += 1;
         if (!__builtin_isfinite(tot)) {
             sc->status = NEK_ERR_BREAKDOWN;
@@ -187,26 +249,67 @@ cg_update_kernel(int64_t P, double *__restrict__ x, double *__restrict__ r,
     }
 }
 
-// reliable update: r = b - w (w = mask(dssum(A64 x))), rho = (r, r)
-__global__ void __launch_bounds__(RED_THREADS)
-cg_replace_kernel(int64_t P, const double *__restrict__ b, const double *__restrict__ w,
-                  double *__restrict__ r, const uint8_t *__restrict__ own, double *partials,
-                  CgScalars *sc) {
-    __shared__ double lds[RED_THREADS / 64];
-    double acc = 0.0;
-    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < P; t += stride) {
-        const double rv = b[t] - w[t];
-        r[t] = rv;
-        if (own[t]) acc += rv * rv;
+// x += alpha p when the last alpha has not reached x yet (end of a solve,
+// or before a true-residual evaluation)
+__global__ void __launch_bounds__(VEC_THREADS)
+cg_finish_kernel(int64_t P, double *__restrict__ x, const double *__restrict__ p,
+                 const CgScalars *sc) {
+    if (sc->lag_applied) return;
+    const double alpha = sc->alpha;
+    const int64_t npairs = P >> 1;
+    NEK_CHUNKS {
+#pragma unroll
+        for (int m = 0; m < VEC_PAIRS; ++m) {
+            const int64_t q = base + threadIdx.x + (int64_t)m * VEC_THREADS;
+            if (q < npairs) {
+                double2 xv = ((double2 *)x)[q];
+                const double2 pv = ((const double2 *)p)[q];
+                xv.x += alpha * pv.x;
+                xv.y += alpha * pv.y;
+                ((double2 *)x)[q] = xv;
+            }
+        }
     }
-    double s = block_sum(acc, lds);
+    if (owns_tail(P)) x[P - 1] += alpha * p[P - 1];
+}
+
+// reliable update: r = b - w (w = mask(dssum(A64 x)) with x current), rho = (r, r)
+__global__ void __launch_bounds__(VEC_THREADS)
+cg_replace_kernel(int64_t P, const double *__restrict__ b, const double *__restrict__ w,
+                  double *__restrict__ r, const uint32_t *__restrict__ own, RedSite red,
+                  CgScalars *sc) {
+    __shared__ double lds[VEC_THREADS / 64];
+    const int64_t npairs = P >> 1;
+    double acc = 0.0;
+    NEK_CHUNKS {
+#pragma unroll
+        for (int m = 0; m < VEC_PAIRS; ++m) {
+            const int64_t q = base + threadIdx.x + (int64_t)m * VEC_THREADS;
+            if (q < npairs) {
+                const double2 bv = ((const double2 *)b)[q];
+                const double2 wv = ((const double2 *)w)[q];
+                const double2 nr = make_double2(bv.x - wv.x, bv.y - wv.y);
+                ((double2 *)r)[q] = nr;
+                const unsigned o = own_pair(own, 2 * q);
+                if (o & 1u) acc += nr.x * nr.x;
+                if (o & 2u) acc += nr.y * nr.y;
+            }
+        }
+    }
+    if (owns_tail(P)) {
+        const int64_t t = P - 1;
+        const double nr = b[t] - w[t];
+        r[t] = nr;
+        if (own_bit(own, t)) acc += nr * nr;
+    }
+    const double s = block_sum<VEC_THREADS>(acc, lds);
     double tot;
-    if (finish_partials(s, partials, &sc->ticket[3], &tot, lds) && threadIdx.x == 0) {
+    if (grid_finish<VEC_THREADS>(s, red, &tot, lds) && threadIdx.x == 0) {
         sc->rho = tot;
         sc->rho_last_true = tot;
         sc->need_replace = 0;
         sc->n_replace += 1;
+        sc->lag_applied = 1;          // the caller brought x up to date before this
         if (!__builtin_isfinite(tot)) {
             sc->status = NEK_ERR_BREAKDOWN;
             sc->done = 1;
@@ -216,92 +319,108 @@ cg_replace_kernel(int64_t P, const double *__restrict__ b, const double *__restr
     }
 }
 
-__global__ void __launch_bounds__(RED_THREADS)
+template <bool DIFF>
+__global__ void __launch_bounds__(VEC_THREADS)
 gdot_kernel(int64_t P, const double *__restrict__ a, const double *__restrict__ b,
-            const uint8_t *__restrict__ own, double *partials, unsigned int *ticket,
-            double *result) {
-    __shared__ double lds[RED_THREADS / 64];
+            const uint32_t *__restrict__ own, RedSite red, double *result) {
+    __shared__ double lds[VEC_THREADS / 64];
+    const int64_t npairs = P >> 1;
     double acc = 0.0;
-    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < P; t += stride)
-        if (own[t]) acc += a[t] * b[t];
-    double s = block_sum(acc, lds);
-    double tot;
-    if (finish_partials(s, partials, ticket, &tot, lds) && threadIdx.x == 0) *result = tot;
-}
-
-__global__ void __launch_bounds__(RED_THREADS)
-gdiff2_kernel(int64_t P, const double *__restrict__ a, const double *__restrict__ b,
-              const uint8_t *__restrict__ own, double *partials, unsigned int *ticket,
-              double *result) {
-    __shared__ double lds[RED_THREADS / 64];
-    double acc = 0.0;
-    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < P; t += stride)
-        if (own[t]) {
-            const double d = a[t] - b[t];
-            acc += d * d;
+    NEK_CHUNKS {
+#pragma unroll
+        for (int m = 0; m < VEC_PAIRS; ++m) {
+            const int64_t q = base + threadIdx.x + (int64_t)m * VEC_THREADS;
+            if (q < npairs) {
+                const double2 av = ((const double2 *)a)[q];
+                const double2 bv = ((const double2 *)b)[q];
+                const unsigned o = own_pair(own, 2 * q);
+                const double t0 = DIFF ? (av.x - bv.x) * (av.x - bv.x) : av.x * bv.x;
+                const double t1 = DIFF ? (av.y - bv.y) * (av.y - bv.y) : av.y * bv.y;
+                if (o & 1u) acc += t0;
+                if (o & 2u) acc += t1;
+            }
         }
-    double s = block_sum(acc, lds);
+    }
+    if (owns_tail(P)) {
+        const int64_t t = P - 1;
+        const double t0 = DIFF ? (a[t] - b[t]) * (a[t] - b[t]) : a[t] * b[t];
+        if (own_bit(own, t)) acc += t0;
+    }
+    const double s = block_sum<VEC_THREADS>(acc, lds);
     double tot;
-    if (finish_partials(s, partials, ticket, &tot, lds) && threadIdx.x == 0) *result = tot;
+    if (grid_finish<VEC_THREADS>(s, red, &tot, lds) && threadIdx.x == 0) *result = tot;
 }
 
 }  // namespace
 
-hipError_t launch_gdiff2(int64_t P, const double *a, const double *b, const uint8_t *own,
-                         double *partials, unsigned int *ticket, double *result, hipStream_t s) {
-    hipLaunchKernelGGL(gdiff2_kernel, dim3(RED_BLOCKS), dim3(RED_THREADS), 0, s, P, a, b, own,
-                       partials, ticket, result);
+int64_t vec_blocks(int64_t P) {
+    const int64_t per = (int64_t)VEC_THREADS * VEC_PAIRS * 2;
+    int64_t nb = (P + per - 1) / per;
+    if (nb > RED_MAX_BLOCKS) nb = RED_MAX_BLOCKS;
+    return nb < 1 ? 1 : nb;
+}
+
+int64_t gs_grid(const GsDevice &gs) {
+    return gs.args.nblocks < RED_MAX_BLOCKS ? gs.args.nblocks : RED_MAX_BLOCKS;
+}
+
+hipError_t launch_gs(const GsDevice &gs, double *w, const double *p, const RedSite &red,
+                     CgScalars *sc, hipStream_t s) {
+    if (gs.args.nblocks == 0) {
+        if (sc == nullptr) return hipSuccess;
+        // nothing is shared or masked: the (p, w) product is all interior, but
+        // a launch is still needed to turn it into alpha
+    }
+    const int64_t grid = gs.args.nblocks > 0 ? gs_grid(gs) : 1;
+    hipLaunchKernelGGL(gs_kernel, dim3((unsigned)grid), dim3(GS_THREADS), 0, s, gs.args, w, p, red, sc);
     return hipGetLastError();
 }
 
-hipError_t launch_gs(const GsDevice &gs, double *w, const int *done, hipStream_t s) {
-    if (gs.n_rows == 0) return hipSuccess;
-    int64_t blocks = (gs.n_rows + 255) / 256;
-    if (blocks > 8192) blocks = 8192;
-    hipLaunchKernelGGL(gs_kernel, dim3((unsigned)blocks), dim3(256), 0, s, gs.n_rows, gs.row_off,
-                       gs.row_idx, gs.row_keep, w, done);
-    return hipGetLastError();
-}
-
-hipError_t launch_cg_reset(CgScalars *sc, int max_iter, double rel_tol, double drop, hipStream_t s) {
-    hipLaunchKernelGGL(cg_reset_kernel, dim3(1), dim3(1), 0, s, sc, max_iter, rel_tol, drop);
+hipError_t launch_cg_reset(CgScalars *sc, unsigned int *tickets, int nticket, int max_iter,
+                           double rel_tol, double drop, hipStream_t s) {
+    hipLaunchKernelGGL(cg_reset_kernel, dim3(1), dim3(256), 0, s, sc, tickets, nticket, max_iter,
+                       rel_tol, drop);
     return hipGetLastError();
 }
 
 hipError_t launch_cg_init(int64_t P, const double *b, double *x, double *r, double *p,
-                          const uint8_t *own, double *partials, CgScalars *sc, hipStream_t s) {
-    hipLaunchKernelGGL(cg_init_kernel, dim3(RED_BLOCKS), dim3(RED_THREADS), 0, s, P, b, x, r, p,
-                       own, partials, sc);
+                          const uint32_t *own, const RedSite &red, CgScalars *sc, hipStream_t s) {
+    hipLaunchKernelGGL(cg_init_kernel, dim3((unsigned)vec_blocks(P)), dim3(VEC_THREADS), 0, s, P, b, x,
+                       r, p, own, red, sc);
     return hipGetLastError();
 }
 
-hipError_t launch_cg_dot_pw(int64_t P, const double *p, const double *w, const uint8_t *own,
-                            double *partials, CgScalars *sc, hipStream_t s) {
-    hipLaunchKernelGGL(cg_dot_pw_kernel, dim3(RED_BLOCKS), dim3(RED_THREADS), 0, s, P, p, w, own,
-                       partials, sc);
+hipError_t launch_cg_update(int64_t P, double *r, const double *w, const uint32_t *own,
+                            const RedSite &red, CgScalars *sc, hipStream_t s) {
+    hipLaunchKernelGGL(cg_update_kernel, dim3((unsigned)vec_blocks(P)), dim3(VEC_THREADS), 0, s, P, r,
+                       w, own, red, sc);
     return hipGetLastError();
 }
 
-hipError_t launch_cg_update(int64_t P, double *x, double *r, const double *p, const double *w,
-                            const uint8_t *own, double *partials, CgScalars *sc, hipStream_t s) {
-    hipLaunchKernelGGL(cg_update_kernel, dim3(RED_BLOCKS), dim3(RED_THREADS), 0, s, P, x, r, p, w,
-                       own, partials, sc);
+hipError_t launch_cg_finish(int64_t P, double *x, const double *p, const CgScalars *sc, hipStream_t s) {
+    hipLaunchKernelGGL(cg_finish_kernel, dim3((unsigned)vec_blocks(P)), dim3(VEC_THREADS), 0, s, P, x,
+                       p, sc);
     return hipGetLastError();
 }
 
 hipError_t launch_cg_replace(int64_t P, const double *b, const double *w, double *r,
-                             const uint8_t *own, double *partials, CgScalars *sc, hipStream_t s) {
-    hipLaunchKernelGGL(cg_replace_kernel, dim3(RED_BLOCKS), dim3(RED_THREADS), 0, s, P, b, w, r,
-                       own, partials, sc);
+                             const uint32_t *own, const RedSite &red, CgScalars *sc, hipStream_t s) {
+    hipLaunchKernelGGL(cg_replace_kernel, dim3((unsigned)vec_blocks(P)), dim3(VEC_THREADS), 0, s, P, b,
+                       w, r, own, red, sc);
     return hipGetLastError();
 }
 
-hipError_t launch_gdot(int64_t P, const double *a, const double *b, const uint8_t *own,
-                       double *partials, unsigned int *ticket, double *result, hipStream_t s) {
-    hipLaunchKernelGGL(gdot_kernel, dim3(RED_BLOCKS), dim3(RED_THREADS), 0, s, P, a, b, own,
-                       partials, ticket, result);
+hipError_t launch_gdot(int64_t P, const double *a, const double *b, const uint32_t *own,
+                       const RedSite &red, double *result, hipStream_t s) {
+    hipLaunchKernelGGL(gdot_kernel<false>, dim3((unsigned)vec_blocks(P)), dim3(VEC_THREADS), 0, s, P, a,
+                       b, own, red, result);
+    return hipGetLastError();
+}
+
+hipError_t launch_gdiff2(int64_t P, const double *a, const double *b, const uint32_t *own,
+                         const RedSite &red, double *result, hipStream_t s) {
+    hipLaunchKernelGGL(gdot_kernel<true>, dim3((unsigned)vec_blocks(P)), dim3(VEC_THREADS), 0, s, P, a,
+                       b, own, red, result);
     return hipGetLastError();
 }
 

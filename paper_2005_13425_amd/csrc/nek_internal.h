@@ -8,6 +8,7 @@
 #include <string>
 
 #include "nek.h"
+#include "reduce.h"
 
 namespace nek {
 
@@ -26,80 +27,120 @@ inline bool aligned8(const void *p) { return ((uintptr_t)p & 7u) == 0; }
 
 inline int64_t n3_of(int N) { return (int64_t)(N + 1) * (N + 1) * (N + 1); }
 
-// ---------------------------------------------------------------- ax_e
-// FP64 local operator, optionally fused with the CG direction update
-// p <- r + beta * p (beta read on the device from *beta; r == nullptr means
-// no fusion and p is only read).
-hipError_t launch_ax_f64(int64_t E, int N, const double *D, const double *g,
-                         const double *r, double *p, const double *beta,
-                         double *w, const int *done, hipStream_t s);
+// ---------------------------------------------------------------- CG scalars
+// Device-side CG state (one struct in device memory, written only by the
+// last workgroup of a reduction kernel or by single-thread kernels).
+struct CgScalars {
+    double bb;            // (b, b)
+    double rho;           // (r, r) of the current residual
+    double pw;            // (p, w)
+    double alpha;
+    double beta;
+    double rel_tol2;      // rel_tol^2 * bb, 0 for fixed iterations
+    double rho_last_true; // rho at the last reliable replacement
+    double drop2;         // reliable_drop^2 (0: FP64 mode)
+    int it;               // iterations completed
+    int max_iter;
+    int done;             // 1: converged, breakdown or max_iter reached
+    int status;           // NEK_OK / NEK_ERR_BREAKDOWN
+    int need_replace;     // mixed precision: r should be replaced by b - A64 x
+    int n_replace;
+    int lag_applied;      // 0: x still lacks alpha * p of the last (p, w)
+    int pad_;
+};
 
-// FP32 operator: p read in FP64, computed in FP32, w written FP64.
+// ---------------------------------------------------------------- ax_e
+// Optional CG fusion of the local-operator launch (all device pointers):
+//   r != null : p <- r + beta p on the way in (beta from sc);
+//   x != null : x += alpha p_old first, if sc->lag_applied == 0;
+//   partials != null : per-workgroup sum of p * w over element-interior
+//                      points, at partials[blockIdx];
+//   sc != null : skip everything once sc->done is set.
+struct AxFuse {
+    const double *r = nullptr;
+    double *x = nullptr;
+    double *partials = nullptr;
+    const CgScalars *sc = nullptr;
+};
+
+hipError_t launch_ax_f64(int64_t E, int N, const double *D, const double *g, double *p, double *w,
+                         const AxFuse &fz, hipStream_t s);
 hipError_t launch_ax_f32(int64_t E, int N, const float *D32, const void *g_lo, int g_dtype,
-                         const double *r, double *p, const double *beta,
-                         double *w, const int *done, hipStream_t s);
+                         double *p, double *w, const AxFuse &fz, hipStream_t s);
+// number of workgroups of an ax launch (one partial each)
+int64_t ax_blocks(int64_t E, int N);
 
 hipError_t launch_convert_g(int64_t count, const double *g, int g_dtype, void *out, hipStream_t s);
 
 // ---------------------------------------------------------------- gather-scatter
+// Nodes handled by the gather-scatter are grouped by their number of copies.
+// A group of c copies stores its rows as structure-of-arrays indices:
+// idx[m * rows + row] is the m-th copy (ascending local index) of the row.
+// Group kind 0 lists the copies of masked nodes (written as 0).  Rows with
+// more than GS_MAXC copies go to a CSR group.
+constexpr int GS_MAXC = 8;
+constexpr int GS_THREADS = 256;
+
+struct GsGroup {
+    int kind;           // 0: zero list; 1..GS_MAXC: copies per row; -1: CSR
+    int32_t rows;       // rows (or entries of the zero list)
+    int32_t block0;     // first workgroup of this group
+    const int32_t *idx; // SoA indices / zero list / CSR entries
+    const int32_t *off; // CSR offsets (kind -1)
+};
+
+constexpr int GS_MAXG = GS_MAXC + 2;
+
+struct GsArgs {
+    int ngroups;
+    int nblocks;
+    GsGroup grp[GS_MAXG];
+};
+
 struct GsDevice {
     int64_t E = 0;
     int N = 0;
     int64_t P = 0;
     int64_t n_unique = 0;
-    int64_t n_rows = 0;     // CSR rows: shared-or-masked nodes
-    int64_t n_entries = 0;  // CSR entries
-    int64_t n_masked = 0;   // masked unique nodes
-    int32_t *row_off = nullptr;   // n_rows + 1
-    int32_t *row_idx = nullptr;   // n_entries, ascending within a row
-    uint8_t *row_keep = nullptr;  // n_rows: 0 = masked (write 0), 1 = keep sum
-    uint8_t *own = nullptr;       // P: 1 on the first copy of every node
+    int64_t n_rows = 0;      // unmasked rows summed by the gather-scatter
+    int64_t n_entries = 0;   // copies in those rows
+    int64_t n_masked = 0;    // masked unique nodes
+    int64_t n_zero = 0;      // copies of masked nodes
+    bool interior_dot = false;  // element-interior points are unshared and unmasked
+    GsArgs args{};
+    void *arena = nullptr;   // one allocation holding every index array
+    uint32_t *own_bits = nullptr;  // P bits: first copy of every node
 };
 
-hipError_t launch_gs(const GsDevice &gs, double *w, const int *done, hipStream_t s);
+// dssum + mask in place; with sc != null also the (p, w) contributions of the
+// rows, reduced (with red.extra, the interior partials of the ax launch) into
+// sc->alpha.
+hipError_t launch_gs(const GsDevice &gs, double *w, const double *p, const RedSite &red,
+                     CgScalars *sc, hipStream_t s);
+int64_t gs_grid(const GsDevice &gs);
 
-// ---------------------------------------------------------------- reductions / CG
-// Device-side CG scalars (one struct in device memory).
-struct CgScalars {
-    double bb;         // (b, b)
-    double rho;        // (r, r) of the current residual
-    double pw;         // (p, w)
-    double alpha;
-    double beta;
-    double rel_tol2;   // rel_tol^2 * bb, 0 for fixed iterations
-    double rho_last_true; // rho at the last reliable replacement
-    double drop2;      // reliable_drop^2
-    int it;            // iterations completed
-    int max_iter;
-    int done;          // 1: converged, breakdown or max_iter reached
-    int status;        // NEK_OK / NEK_ERR_BREAKDOWN
-    int need_replace;  // mixed precision: r must be replaced by b - A64 x
-    int n_replace;
-    unsigned int ticket[4];  // last-block tickets of the reduction kernels
-};
+// ---------------------------------------------------------------- CG vector steps
+constexpr int VEC_THREADS = 256;
+constexpr int VEC_PAIRS = 4;            // double2 per thread per chunk
+int64_t vec_blocks(int64_t P);          // workgroups of the vector kernels (<= RED_MAX_BLOCKS)
 
-constexpr int RED_BLOCKS = 1024;   // blocks of the grid-stride reduction kernels
-constexpr int RED_THREADS = 256;
-
-hipError_t launch_cg_reset(CgScalars *sc, int max_iter, double rel_tol, double drop, hipStream_t s);
+hipError_t launch_cg_reset(CgScalars *sc, unsigned int *tickets, int nticket, int max_iter,
+                           double rel_tol, double drop, hipStream_t s);
 hipError_t launch_cg_init(int64_t P, const double *b, double *x, double *r, double *p,
-                          const uint8_t *own, double *partials, CgScalars *sc,
-                          hipStream_t s);
-hipError_t launch_cg_dot_pw(int64_t P, const double *p, const double *w, const uint8_t *own,
-                            double *partials, CgScalars *sc, hipStream_t s);
-hipError_t launch_cg_update(int64_t P, double *x, double *r, const double *p, const double *w,
-                            const uint8_t *own, double *partials, CgScalars *sc,
-                            hipStream_t s);
-// r <- b - w (w = A64 x already gathered), rho <- (r, r); mixed-precision replacement.
+                          const uint32_t *own, const RedSite &red, CgScalars *sc, hipStream_t s);
+hipError_t launch_cg_update(int64_t P, double *r, const double *w, const uint32_t *own,
+                            const RedSite &red, CgScalars *sc, hipStream_t s);
+hipError_t launch_cg_finish(int64_t P, double *x, const double *p, const CgScalars *sc, hipStream_t s);
 hipError_t launch_cg_replace(int64_t P, const double *b, const double *w, double *r,
-                             const uint8_t *own, double *partials, CgScalars *sc,
-                             hipStream_t s);
-// result <- sum own * (a - b)^2 (deterministic), one double in device memory
-hipError_t launch_gdiff2(int64_t P, const double *a, const double *b, const uint8_t *own,
-                         double *partials, unsigned int *ticket, double *result, hipStream_t s);
-// result <- sum own * a * b (deterministic), one double in device memory
-hipError_t launch_gdot(int64_t P, const double *a, const double *b, const uint8_t *own,
-                       double *partials, unsigned int *ticket, double *result, hipStream_t s);
+                             const uint32_t *own, const RedSite &red, CgScalars *sc, hipStream_t s);
+// result <- sum own * a * b / sum own * (a - b)^2, deterministic, one device double
+hipError_t launch_gdot(int64_t P, const double *a, const double *b, const uint32_t *own,
+                       const RedSite &red, double *result, hipStream_t s);
+hipError_t launch_gdiff2(int64_t P, const double *a, const double *b, const uint32_t *own,
+                         const RedSite &red, double *result, hipStream_t s);
+
+// storage of one reduction site inside a workspace
+constexpr size_t RED_SITE_DOUBLES = RED_MAX_BLOCKS + RED_MAX_GROUPS;
 
 // ---------------------------------------------------------------- geometry
 // GLL nodes, weights and derivative matrix passed by value to kernels

@@ -1,0 +1,121 @@
+// Deterministic workgroup and grid reductions for gfx950 (wave64).
+//
+// A grid reduction writes one partial per workgroup.  Workgroups are grouped
+// by RED_GROUP; the workgroup that takes the last ticket of its group sums the
+// group's partials in index order, and the workgroup that finishes the last
+// group sums the group sums (and any partials left by an earlier launch) in
+// index order.  The order of every sum is fixed by the launch shape, so the
+// result is bitwise reproducible, and no counter sees more than a few dozen
+// atomic increments per launch.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+namespace nek {
+
+constexpr int RED_GROUP = 32;          // workgroups per first-level ticket
+constexpr int RED_MAX_BLOCKS = 2048;   // grid cap of the reduction kernels
+constexpr int RED_MAX_GROUPS = RED_MAX_BLOCKS / RED_GROUP;
+constexpr int RED_TICKETS = 1 + RED_MAX_GROUPS;   // counters per reduction site
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
+}
+
+// Sum over a workgroup of NT threads (multiple of 64); valid in thread 0.
+// lds must hold NT/64 doubles.
+template <int NT>
+__device__ __forceinline__ double block_sum(double v, double *lds) {
+    v = wave_sum(v);
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    if (lane == 0) lds[wave] = v;
+    __syncthreads();
+    double s = 0.0;
+    if (threadIdx.x == 0) {
+#pragma unroll
+        for (int q = 0; q < NT / 64; ++q) s += lds[q];
+    }
+    __syncthreads();
+    return s;
+}
+
+__device__ __forceinline__ double load_coherent(const double *p) {
+    unsigned long long bits =
+        __hip_atomic_load((const unsigned long long *)p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    return __longlong_as_double((long long)bits);
+}
+
+__device__ __forceinline__ void store_coherent(double *p, double v) {
+    __hip_atomic_store((unsigned long long *)p, (unsigned long long)__double_as_longlong(v),
+                       __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Agent-scope ticket: the caller's coherent stores have completed first.
+__device__ __forceinline__ unsigned int take_ticket(unsigned int *t) {
+    __builtin_amdgcn_s_waitcnt(0);
+    return __hip_atomic_fetch_add(t, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Storage of one reduction site (all device memory):
+//   part[gridDim.x]   per-workgroup partials
+//   gpart[groups]     per-group sums
+//   tk[RED_TICKETS]   zero-initialised counters (reset after use)
+//   extra[nextra]     partials written by an earlier launch, added last
+struct RedSite {
+    double *part;
+    double *gpart;
+    unsigned int *tk;
+    const double *extra;
+    long nextra;
+};
+
+// Publish s (valid in thread 0).  Returns true in every thread of the one
+// workgroup that completes the reduction; thread 0 of it has the total in *out.
+//
+// Partials go out with agent-scope atomic stores (through the per-XCD L2 to
+// the device-coherent level) and each thread waits for its stores before it
+// takes a ticket; readers use agent-scope atomic loads.  No agent-scope fence
+// is used: on gfx950 such a fence writes back the whole L2 of the XCD.
+template <int NT>
+__device__ bool grid_finish(double s, const RedSite &r, double *out, double *lds) {
+    __shared__ int stage;   // 0: not last, 1: last of its group, 2: last overall
+    const unsigned int nb = gridDim.x;
+    const unsigned int grp = blockIdx.x / RED_GROUP;
+    const unsigned int ngroups = (nb + RED_GROUP - 1) / RED_GROUP;
+    const unsigned int gsize = (grp + 1 == ngroups) ? nb - grp * RED_GROUP : RED_GROUP;
+    if (threadIdx.x == 0) {
+        store_coherent(&r.part[blockIdx.x], s);
+        const unsigned int t = take_ticket(&r.tk[1 + grp]);
+        stage = (t == gsize - 1u) ? 1 : 0;
+    }
+    __syncthreads();
+    if (stage == 0) return false;
+    // last workgroup of the group: ordered group sum
+    double v = 0.0;
+    if (threadIdx.x < gsize) v = load_coherent(&r.part[grp * RED_GROUP + threadIdx.x]);
+    v = block_sum<NT>(v, lds);
+    if (threadIdx.x == 0) {
+        r.tk[1 + grp] = 0u;
+        store_coherent(&r.gpart[grp], v);
+        const unsigned int t = take_ticket(&r.tk[0]);
+        stage = (t == ngroups - 1u) ? 2 : 0;
+    }
+    __syncthreads();
+    if (stage != 2) return false;
+    // last group: ordered sum of the group sums, then the extra partials
+    double u = 0.0;
+    for (long q = threadIdx.x; q < (long)ngroups; q += NT) u += load_coherent(&r.gpart[q]);
+    double e = 0.0;
+    for (long q = threadIdx.x; q < r.nextra; q += NT) e += load_coherent(&r.extra[q]);
+    u = block_sum<NT>(u, lds);
+    e = block_sum<NT>(e, lds);
+    if (threadIdx.x == 0) {
+        r.tk[0] = 0u;
+        *out = e + u;
+    }
+    return true;
+}
+
+}  // namespace nek

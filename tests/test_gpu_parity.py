@@ -213,3 +213,38 @@ def test_ax_argument_errors_on_device(nek):
     assert ei.value.code == nek.NEK_ERR_ARG
     with pytest.raises(TypeError):
         nek.ax(u.float(), _dev(m.D), _dev(m.g), 3)
+
+
+def test_cg_odd_point_count_and_interior_mask(nek):
+    # N=2, 3x3x3 box: P = 27 * 27 is odd (vector tail); pin one element-interior
+    # node with a Dirichlet flag, so element interiors are no longer exclusive
+    # and the (p, w) product runs entirely through the gather-scatter
+    for pin in (False, True):
+        m = _mesh((3, 3, 3), 2)
+        dr = m.dirichlet.copy()
+        if pin:
+            n = 3
+            L = 13 * n ** 3 + 1 + n * (1 + n * 1)     # point (1,1,1) of element 13
+            dr[L] = 1
+        b = oracle.lattice_to_local(m, synth.lattice_uniform(3, 3, 3, 2))
+        b = oracle.mask(dr, b)
+        gs = nek.GatherScatter(m.E, 2, m.glo, dr)
+        x, res = nek.cg_solve(_dev(m.D), _dev(m.g), gs, _dev(b), max_iter=30, true_residual=True)
+        torch.cuda.synchronize()
+        mm = oracle.BoxMesh(m.Ex, m.Ey, m.Ez, m.N, m.z, m.wq, m.D, m.X, m.g, m.bm, m.glo, dr, m.detmin)
+        ref = oracle.cg(mm, b, max_iter=30)
+        assert m.P % 2 == 1
+        assert _rel(x, ref.x) <= TOL, pin
+        gs.close()
+
+
+def test_gs_dot_odd_and_unaligned_rejected(nek):
+    m = _mesh((3, 1, 1), 2)
+    gs = nek.GatherScatter(m.E, 2, m.glo, m.dirichlet)
+    a = oracle.dssum(m.glo, synth.local_uniform(m.P, 1), m.U) / oracle.dssum(m.glo, np.ones(m.P), m.U)
+    d = gs.dot(_dev(a), _dev(a)).item()
+    assert abs(d - oracle.gdot(m.glo, a, a, m.U)) <= 1e-13 * d
+    big = _dev(np.concatenate([[0.0], a]))
+    with pytest.raises(nek.NekError):
+        gs.dot(big[1:], big[1:])
+    gs.close()
