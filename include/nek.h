@@ -131,16 +131,19 @@ typedef struct nek_gs nek_gs;
  * glo[P] global id of each local point (any non-negative ids), dirichlet[P]
  * 1 where the node carries the zero Dirichlet condition (NULL = none).  A
  * node is masked when any of its copies is flagged.  The handle owns device
- * copies of the map (CSR over the shared or masked nodes, in ascending local
- * index), and of the dot-product weights.  P must be < 2^31.
+ * copies of the map: the copies of every shared node grouped by copy count
+ * (ascending local index within a node), the list of copies of masked nodes,
+ * and one bit per point marking the first copy of every node (the weights of
+ * the inner products).  P must be < 2^31.
  * Synchronous (allocates device memory and uploads). */
 int nek_gs_create(int64_t E, int N, const int64_t *glo, const uint8_t *dirichlet, nek_gs **out);
 
 /* Free the handle (synchronises the device first).  NULL is accepted. */
 int nek_gs_destroy(nek_gs *gs);
 
-/* Sizes of a handle: unique nodes, shared-or-masked nodes handled by the
- * CSR, CSR entries, masked unique nodes.  Any output may be NULL. */
+/* Sizes of a handle: unique nodes, unmasked nodes summed by the
+ * gather-scatter (shared nodes, plus single-copy nodes on element faces),
+ * their copies, masked unique nodes.  Any output may be NULL. */
 int nek_gs_info(const nek_gs *gs, int64_t *n_unique, int64_t *n_rows, int64_t *n_entries,
                 int64_t *n_masked);
 
@@ -152,7 +155,9 @@ int nek_dssum(const nek_gs *gs, double *w, void *stream);
 
 /* Inner product of two continuous local vectors over unique global nodes
  * (each node counted once): *result (device, one double) = sum a_G b_G.
- * Deterministic.  Allocates nothing.  Asynchronous. */
+ * a and b 16-byte aligned.  Deterministic.  Allocates nothing; calls that
+ * share a handle must be ordered on one stream (they share its reduction
+ * scratch).  Asynchronous. */
 int nek_gs_dot(const nek_gs *gs, const double *a, const double *b, double *result, void *stream);
 
 /* --------------------------------------------------------------------- CG */
@@ -187,7 +192,7 @@ void nek_cg_default_opts(nek_cg_opts *opts);
 size_t nek_cg_workspace_bytes(int64_t E, int N);
 
 /* Solve mask(dssum(A_L x)) = b by unpreconditioned CG with x_0 = 0 (Sec. III,
- * Sec. V).  b and x are device vectors in the local layout; b must be
+ * Sec. V).  b and x are device vectors in the local layout (16-byte aligned); b must be
  * continuous (copies equal) and zero at masked nodes; x receives a vector of
  * the same kind.  D, g device.  gs from nek_gs_create for the same mesh.
  * Every step runs on the device; the host only polls a status word every
@@ -198,6 +203,18 @@ size_t nek_cg_workspace_bytes(int64_t E, int N);
 int nek_cg_solve(int64_t E, int N, const double *D, const double *g, const nek_gs *gs,
                  const double *b, double *x, const nek_cg_opts *opts, nek_cg_stats *stats,
                  void *stream);
+
+/* ------------------------------------------------------------ measurement */
+
+/* Streaming bandwidth probe for the measured roofline (Sec. V: the
+ * computation replaced by copies of every load and store).  Computes
+ * dst[i] = sum_{k < nread} src[k*n + i] for i < n: nread coalesced read
+ * streams and one write stream of n doubles.  nread in 1..8 (1 = copy,
+ * 7 = the 7:1 read:write mix of the FP64 local operator).  src: device,
+ * nread*n doubles, 16-byte aligned; dst: device, n doubles, 16-byte aligned,
+ * not overlapping src.  grid_cap > 0 caps the number of workgroups (0: one
+ * pass).  Allocates nothing.  Asynchronous. */
+int nek_bw_probe(int64_t n, int nread, const double *src, double *dst, int grid_cap, void *stream);
 
 #ifdef __cplusplus
 }

@@ -83,6 +83,7 @@ _sig("nek_gs_destroy", _ci, [_vp])
 _sig("nek_gs_info", _ci, [_vp] + [ctypes.POINTER(_i64)] * 4)
 _sig("nek_dssum", _ci, [_vp, _vp, _vp])
 _sig("nek_gs_dot", _ci, [_vp, _vp, _vp, _vp, _vp])
+_sig("nek_bw_probe", _ci, [_i64, _ci, _vp, _vp, _ci, _vp])
 _sig("nek_cg_default_opts", None, [ctypes.POINTER(CgOpts)])
 _sig("nek_cg_workspace_bytes", ctypes.c_size_t, [_i64, _ci])
 _sig("nek_cg_solve", _ci, [_i64, _ci, _vp, _vp, _vp, _vp, _vp, ctypes.POINTER(CgOpts),
@@ -220,6 +221,16 @@ def ax_f32(u, D32, g_lo, g_dtype: int, N: int, out=None, stream=None):
                            _dev(g_lo, gdt, "g_lo", 6 * E * n3), int(g_dtype),
                            _dev(out, torch.float64, "w", E * n3), _stream_ptr(stream)), "nek_ax_f32")
     return out
+
+
+def bw_probe(src, dst, nread: int, grid_cap: int = 0, stream=None):
+    """dst[i] = sum_k src[k*n + i] (nread read streams, one write stream)."""
+    torch = _torch()
+    n = dst.numel()
+    _check(_lib.nek_bw_probe(n, int(nread), _dev(src, torch.float64, "src", nread * n),
+                             _dev(dst, torch.float64, "dst", n), int(grid_cap), _stream_ptr(stream)),
+           "nek_bw_probe")
+    return dst
 
 
 # ------------------------------------------------------------------ gather-scatter

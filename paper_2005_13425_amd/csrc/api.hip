@@ -231,6 +231,20 @@ int nek_convert_g(int64_t E, int N, const double *g, int g_dtype, void *g_lo, vo
     return NEK_OK;
 }
 
+// ---------------------------------------------------------------- measurement
+int nek_bw_probe(int64_t n, int nread, const double *src, double *dst, int grid_cap, void *stream) {
+    clear_error();
+    if (n < 1) return fail(NEK_ERR_ARG, "nek_bw_probe: n must be >= 1");
+    if (nread < 1 || nread > 8) return fail(NEK_ERR_ARG, "nek_bw_probe: nread must be in 1..8");
+    if (!src || !dst || ((uintptr_t)src & 15u) || ((uintptr_t)dst & 15u))
+        return fail(NEK_ERR_ARG, "nek_bw_probe: null or misaligned pointer");
+    const uintptr_t sb = (uintptr_t)src, db = (uintptr_t)dst;
+    if (db < sb + (uintptr_t)(nread * n) * 8 && sb < db + (uintptr_t)n * 8)
+        return fail(NEK_ERR_ARG, "nek_bw_probe: src and dst overlap");
+    NEK_HIP(launch_probe(n, nread, src, dst, grid_cap, (hipStream_t)stream));
+    return NEK_OK;
+}
+
 // ---------------------------------------------------------------- gather-scatter
 static void gs_free(nek_gs *h) {
     if (!h) return;

@@ -44,7 +44,17 @@ struct AxShape {
     static constexpr int BUF = NX * LS;                                // one n^3 buffer
     // waves per SIMD the register budget is held to: the LDS of one workgroup
     // (3 BUF values per element) allows about this many on a 160 KB CU
+#ifdef NEK_AX_MINW
+    static constexpr int MINW = NEK_AX_MINW;
+#else
     static constexpr int MINW = (sizeof(T) == 8 && NX <= 10) ? 3 : 1;
+#endif
+    // layers of geometric factors held in registers ahead of their use
+#ifdef NEK_AX_PF
+    static constexpr int PF = NEK_AX_PF < NX ? NEK_AX_PF : NX;
+#else
+    static constexpr int PF = 4 < NX ? 4 : NX;
+#endif
 };
 
 template <typename GT>
@@ -67,20 +77,26 @@ __device__ __forceinline__ float load_g<float, uint16_t>(const uint16_t *p) {
     return g_to_f32<uint16_t>(*p);
 }
 
-// T: compute type (double or float); GT: storage type of g; FUSE: p <- r + beta p.
+// T: compute type (double or float); GT: storage type of g; FUSE: CG fusion.
 //
-// Per element, three LDS buffers B0, B1, B2 of n^3 (padded) values:
-//   1. column threads (i,j) load u(i,j,:) into registers and store it in B0;
-//   2. pencil threads: r-pencil (j,k) computes wr(:,j,k) = D u(:,j,k) -> B1,
-//      s-pencil (i,k) computes ws(i,:,k) -> B2 (dxm1 uniform: scalar path);
-//   3. column threads: wt from the register column, the symmetric g multiply,
-//      ur -> B1, us -> B2 in place, and the transposed t contraction is
-//      accumulated in a register column of w;
-//   4. r-pencils: dxtm1 applied to ur(:,j,k) -> B0;
-//   5. s-pencils: dxtm1 applied to us(i,:,k) -> B1;
-//   6. column threads: w = t part + B0 + B1, stored to HBM.
-// Five workgroup barriers per element; every LDS value is written once and
-// read once or twice.
+// Per element, three LDS buffers B0, B1, B2 of n^3 (padded) values.  Thread
+// (a, b) of an element plays three roles: the column (i,j) = (a,b), the
+// r-pencil (j,k) = (a,b) and the s-pencil (i,k) = (a,b).
+//   1. the column u(a,b,:) goes from HBM to B0;
+//   2. forward contractions, one dxm1 column l at a time (outer products):
+//      wr(:,a,b) += dxm1(:,l) u(l,a,b), ws(a,:,b) += dxm1(:,l) u(a,l,b) and
+//      wt(a,b,:) += dxm1(:,l) u(a,b,l); wr -> B1, ws -> B2, wt stays in
+//      registers;
+//   3. column: the symmetric g multiply gives ur -> B1, us -> B2 (in place)
+//      and ut in registers;
+//   4. the ur pencil (:,a,b) and the us pencil (a,:,b) are read into registers;
+//   5. transposed contractions, one dxtm1 row i at a time (inner products):
+//      the r part at (i,a,b) -> B0, the s part at (a,i,b) -> B1 and the t part
+//      at (a,b,i) -> B2;
+//   6. w(a,b,:) = B0 + B1 + B2 at the column, stored to HBM.
+// Only one column or row of the derivative matrix (n values, uniform across
+// the workgroup) is live at a time, so it stays in scalar registers.  Five
+// workgroup barriers per element.
 template <int NX, typename T, typename GT, bool FUSE>
 __global__ void __launch_bounds__((AxShape<NX, T>::THREADS), (AxShape<NX, T>::MINW))
 ax_kernel(int64_t E, const T *__restrict__ D, const GT *__restrict__ g, double *__restrict__ p,
@@ -93,6 +109,7 @@ ax_kernel(int64_t E, const T *__restrict__ D, const GT *__restrict__ g, double *
     constexpr int RS = S::RS;
     constexpr int LS = S::LS;
     constexpr int BUF = S::BUF;
+    constexpr int PF = S::PF;
 
     if (FUSE && fz.sc->done) return;   // uniform: CG already finished
 
@@ -101,8 +118,8 @@ ax_kernel(int64_t E, const T *__restrict__ D, const GT *__restrict__ g, double *
     const int tid = threadIdx.x;
     const int eb = tid / NN;
     const int c = tid - eb * NN;
-    const int a = c % NX;      // i for columns / r-pencils' j / s-pencils' i
-    const int b = c / NX;      // j for columns / pencils' k
+    const int a = c % NX;
+    const int b = c / NX;
     const bool in_slab = tid < EPB * NN;
     const int64_t e = (int64_t)blockIdx.x * EPB + eb;
     const bool active = in_slab && e < E;
@@ -110,177 +127,161 @@ ax_kernel(int64_t E, const T *__restrict__ D, const GT *__restrict__ g, double *
     T *B0 = lds + (in_slab ? eb : 0) * 3 * BUF;
     T *B1 = B0 + BUF;
     T *B2 = B1 + BUF;
+    const int col = b * RS + a;       // column (a,b) within a layer
+    const int rpen = b * LS + a * RS; // start of r-pencil (:,a,b)
+    const int spen = b * LS + a;      // start of s-pencil (a,:,b), stride RS
 
     // ---- 1. u column (in the CG: x += alpha p_old and p <- r + beta p_old first)
-    T ucol[NX];
-    double pcol[NX];   // FP64 p of this column, kept for the interior (p, w) sum
     const int64_t base = e * N3 + c;
-    if (active) {
+    double pcol[FUSE ? NX : 1];       // FP64 p of this column, for the interior (p, w) sum
+    {
+        double pv[NX];
+        if (active) {
 #pragma unroll
-        for (int k = 0; k < NX; ++k) pcol[k] = p[base + k * NN];
-        if constexpr (FUSE) {
-            if (fz.x != nullptr && fz.sc->lag_applied == 0) {
-                const double al = fz.sc->alpha;
-                double xx[NX];
+            for (int k = 0; k < NX; ++k) pv[k] = p[base + k * NN];
+            if constexpr (FUSE) {
+                if (fz.x != nullptr && fz.sc->lag_applied == 0) {
+                    const double al = fz.sc->alpha;
+                    double xx[NX];
 #pragma unroll
-                for (int k = 0; k < NX; ++k) xx[k] = fz.x[base + k * NN];
+                    for (int k = 0; k < NX; ++k) xx[k] = fz.x[base + k * NN];
 #pragma unroll
-                for (int k = 0; k < NX; ++k) fz.x[base + k * NN] = xx[k] + al * pcol[k];
-            }
-            if (fz.r != nullptr) {
-                const double bt = fz.sc->beta;
-                double rr[NX];
+                    for (int k = 0; k < NX; ++k) fz.x[base + k * NN] = xx[k] + al * pv[k];
+                }
+                if (fz.r != nullptr) {
+                    const double bt = fz.sc->beta;
+                    double rr[NX];
 #pragma unroll
-                for (int k = 0; k < NX; ++k) rr[k] = fz.r[base + k * NN];
+                    for (int k = 0; k < NX; ++k) rr[k] = fz.r[base + k * NN];
 #pragma unroll
-                for (int k = 0; k < NX; ++k) {
-                    pcol[k] = rr[k] + bt * pcol[k];
-                    p[base + k * NN] = pcol[k];
+                    for (int k = 0; k < NX; ++k) {
+                        pv[k] = rr[k] + bt * pv[k];
+                        p[base + k * NN] = pv[k];
+                    }
                 }
             }
+        } else {
+#pragma unroll
+            for (int k = 0; k < NX; ++k) pv[k] = 0.0;
         }
+        if constexpr (FUSE) {
 #pragma unroll
-        for (int k = 0; k < NX; ++k) ucol[k] = (T)pcol[k];
-    } else {
+            for (int k = 0; k < NX; ++k) pcol[k] = pv[k];
+        }
+        if (in_slab) {
 #pragma unroll
-        for (int k = 0; k < NX; ++k) {
-            ucol[k] = T(0);
-            pcol[k] = 0.0;
+            for (int k = 0; k < NX; ++k) B0[k * LS + col] = (T)pv[k];
         }
     }
 
-    // geometric factors of the first two layers go out now, the rest one
-    // layer ahead of use
+    // geometric factors of the first PF layers go out now, each later layer
+    // PF layers ahead of its use
     const GT *ge = g + e * (6 * N3) + c;
-    T gq[2][6];
+    T gq[PF][6];
 #pragma unroll
-    for (int k = 0; k < 2 && k < NX; ++k)
+    for (int k = 0; k < PF; ++k)
 #pragma unroll
         for (int q = 0; q < 6; ++q) gq[k][q] = active ? load_g<T, GT>(ge + q * N3 + k * NN) : T(0);
-
-    const int col = b * RS + a;   // (i,j) of this column within a layer
-    if (in_slab) {
-#pragma unroll
-        for (int k = 0; k < NX; ++k) B0[k * LS + col] = ucol[k];
-    }
     __syncthreads();
 
-    // ---- 2. forward pencils
-    if (in_slab) {
-        // r-pencil (j = a, k = b): wr(i) = sum_l dxm1(i,l) u(l,j,k)
-        {
-            T v[NX], o[NX];
-            const T *src = B0 + b * LS + a * RS;
+    // ---- 2. forward contractions: outer products with dxm1(:, l) = D[n l .. n l + n)
+    T wt[NX];
+    {
+        T wr[NX], ws[NX];
 #pragma unroll
-            for (int l = 0; l < NX; ++l) v[l] = src[l];
-#pragma unroll
-            for (int i = 0; i < NX; ++i) {
-                T acc = T(0);
-#pragma unroll
-                for (int l = 0; l < NX; ++l) acc += D[i + NX * l] * v[l];
-                o[i] = acc;
-            }
-            T *dst = B1 + b * LS + a * RS;
-#pragma unroll
-            for (int i = 0; i < NX; ++i) dst[i] = o[i];
+        for (int q = 0; q < NX; ++q) {
+            wr[q] = T(0);
+            ws[q] = T(0);
+            wt[q] = T(0);
         }
-        // s-pencil (i = a, k = b): ws(j) = sum_l dxm1(j,l) u(i,l,k)
-        {
-            T v[NX], o[NX];
-            const T *src = B0 + b * LS + a;
+        if (in_slab) {
+#pragma unroll 2
+            for (int l = 0; l < NX; ++l) {
+                const T vr = B0[rpen + l];          // u(l, a, b)
+                const T vs = B0[spen + l * RS];     // u(a, l, b)
+                const T vt = B0[l * LS + col];      // u(a, b, l)
+                const T *Dl = D + NX * l;
 #pragma unroll
-            for (int l = 0; l < NX; ++l) v[l] = src[l * RS];
-#pragma unroll
-            for (int j = 0; j < NX; ++j) {
-                T acc = T(0);
-#pragma unroll
-                for (int l = 0; l < NX; ++l) acc += D[j + NX * l] * v[l];
-                o[j] = acc;
+                for (int q = 0; q < NX; ++q) {
+                    const T d = Dl[q];
+                    wr[q] += d * vr;
+                    ws[q] += d * vs;
+                    wt[q] += d * vt;
+                }
             }
-            T *dst = B2 + b * LS + a;
 #pragma unroll
-            for (int j = 0; j < NX; ++j) dst[j * RS] = o[j];
-        }
-    }
-    __syncthreads();
-
-    // ---- 3. column: g multiply, ur/us back to LDS, transposed t contraction
-    T wcol[NX];
-#pragma unroll
-    for (int k = 0; k < NX; ++k) wcol[k] = T(0);
-    if (in_slab) {
-#pragma unroll
-        for (int k = 0; k < NX; ++k) {
-            const T *gc = gq[k & 1];
-            T wt = T(0);
-#pragma unroll
-            for (int l = 0; l < NX; ++l) wt += D[k + NX * l] * ucol[l];
-            const T wr = B1[k * LS + col];
-            const T ws = B2[k * LS + col];
-            const T ur = gc[0] * wr + gc[1] * ws + gc[2] * wt;
-            const T us = gc[1] * wr + gc[3] * ws + gc[4] * wt;
-            const T ut = gc[2] * wr + gc[4] * ws + gc[5] * wt;
-            B1[k * LS + col] = ur;
-            B2[k * LS + col] = us;
-            // w(i,j,m) += dxtm1(m,k) ut(i,j,k) = dxm1(k,m) ut
-#pragma unroll
-            for (int m = 0; m < NX; ++m) wcol[m] += D[k + NX * m] * ut;
-            if (k + 2 < NX) {
-#pragma unroll
-                for (int q = 0; q < 6; ++q)
-                    gq[k & 1][q] = active ? load_g<T, GT>(ge + q * N3 + (k + 2) * NN) : T(0);
+            for (int q = 0; q < NX; ++q) {
+                B1[rpen + q] = wr[q];               // wr(q, a, b)
+                B2[spen + q * RS] = ws[q];          // ws(a, q, b)
             }
         }
     }
     __syncthreads();
 
-    // ---- 4. r-pencils of dxtm1: sum_l dxtm1(i,l) ur(l,j,k), dxtm1(i,l) = D[l + n i]
+    // ---- 3. column: symmetric geometric multiply
+    T ut[NX];
+#pragma unroll
+    for (int k = 0; k < NX; ++k) {
+        const T *gc = gq[k % PF];
+        T urv = T(0), usv = T(0), utv = T(0);
+        if (in_slab) {
+            const T wrv = B1[k * LS + col];
+            const T wsv = B2[k * LS + col];
+            urv = gc[0] * wrv + gc[1] * wsv + gc[2] * wt[k];
+            usv = gc[1] * wrv + gc[3] * wsv + gc[4] * wt[k];
+            utv = gc[2] * wrv + gc[4] * wsv + gc[5] * wt[k];
+            B1[k * LS + col] = urv;
+            B2[k * LS + col] = usv;
+        }
+        ut[k] = utv;
+        if (k + PF < NX) {
+#pragma unroll
+            for (int q = 0; q < 6; ++q)
+                gq[k % PF][q] = active ? load_g<T, GT>(ge + q * N3 + (k + PF) * NN) : T(0);
+        }
+    }
+    __syncthreads();
+
+    // ---- 4. ur and us pencils into registers
+    T vr[NX], vs[NX];
+#pragma unroll
+    for (int l = 0; l < NX; ++l) {
+        vr[l] = in_slab ? B1[rpen + l] : T(0);          // ur(l, a, b)
+        vs[l] = in_slab ? B2[spen + l * RS] : T(0);     // us(a, l, b)
+    }
+    __syncthreads();
+
+    // ---- 5. transposed contractions: inner products with dxtm1(i, :) = D[n i .. n i + n)
     if (in_slab) {
-        T v[NX], o[NX];
-        const T *src = B1 + b * LS + a * RS;
-#pragma unroll
-        for (int l = 0; l < NX; ++l) v[l] = src[l];
-#pragma unroll
+#pragma unroll 2
         for (int i = 0; i < NX; ++i) {
-            T acc = T(0);
+            const T *Di = D + NX * i;
+            T pr = T(0), ps = T(0), pt = T(0);
 #pragma unroll
-            for (int l = 0; l < NX; ++l) acc += D[l + NX * i] * v[l];
-            o[i] = acc;
+            for (int l = 0; l < NX; ++l) {
+                const T d = Di[l];
+                pr += d * vr[l];
+                ps += d * vs[l];
+                pt += d * ut[l];
+            }
+            B0[rpen + i] = pr;              // r part at (i, a, b)
+            B1[spen + i * RS] = ps;         // s part at (a, i, b)
+            B2[i * LS + col] = pt;          // t part at (a, b, i)
         }
-        T *dst = B0 + b * LS + a * RS;
-#pragma unroll
-        for (int i = 0; i < NX; ++i) dst[i] = o[i];
     }
     __syncthreads();
 
-    // ---- 5. s-pencils of dxtm1: sum_l dxtm1(j,l) us(i,l,k) -> B1
-    if (in_slab) {
-        T v[NX], o[NX];
-        const T *src = B2 + b * LS + a;
-#pragma unroll
-        for (int l = 0; l < NX; ++l) v[l] = src[l * RS];
-#pragma unroll
-        for (int j = 0; j < NX; ++j) {
-            T acc = T(0);
-#pragma unroll
-            for (int l = 0; l < NX; ++l) acc += D[l + NX * j] * v[l];
-            o[j] = acc;
-        }
-        T *dst = B1 + b * LS + a;
-#pragma unroll
-        for (int j = 0; j < NX; ++j) dst[j * RS] = o[j];
-    }
-    __syncthreads();
-
-    // ---- 6. w = t part + r part + s part
+    // ---- 6. w = r part + s part + t part
     double pw = 0.0;
     if (active) {
         const bool inner_col = a > 0 && a < NX - 1 && b > 0 && b < NX - 1;
 #pragma unroll
         for (int k = 0; k < NX; ++k) {
-            const double wv = (double)(wcol[k] + B0[k * LS + col] + B1[k * LS + col]);
+            const double wv = (double)(B0[k * LS + col] + B1[k * LS + col] + B2[k * LS + col]);
             w[base + k * NN] = wv;
-            if (FUSE && inner_col && k > 0 && k < NX - 1) pw += pcol[k] * wv;
+            if constexpr (FUSE) {
+                if (inner_col && k > 0 && k < NX - 1) pw += pcol[k] * wv;
+            }
         }
     }
     // ---- 7. CG: per-workgroup sum of p w over element-interior points

@@ -154,6 +154,8 @@ hipError_t launch_box_geometry(int Ex, int Ey, int Ez, int N, double amp, double
                                double a2, const GllTable &tab, double *g, double *bm, double *X,
                                hipStream_t s);
 
+hipError_t launch_probe(int64_t n, int nread, const double *src, double *dst, int grid, hipStream_t s);
+
 // host GLL routine shared by the setup entry points
 int gll_host(int N, double *z, double *w, double *D);
 
