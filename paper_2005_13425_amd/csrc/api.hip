@@ -311,22 +311,10 @@ int nek_gs_create(int64_t E, int N, const int64_t *glo, const uint8_t *dirichlet
     std::vector<int32_t> copies((size_t)P), fillpos(start.begin(), start.end() - 1);
     for (int64_t L = 0; L < P; ++L) copies[(size_t)fillpos[(size_t)dense[(size_t)L]]++] = (int32_t)L;
 
-    // element-interior points (1 <= i,j,k <= n-2) unshared and unmasked?
-    auto interior = [&](int64_t L) {
-        const int64_t q = L % n3;
-        const int i = (int)(q % n), j = (int)((q / n) % n), k = (int)(q / ((int64_t)n * n));
-        return i > 0 && i < n - 1 && j > 0 && j < n - 1 && k > 0 && k < n - 1;
-    };
-    bool interior_dot = true;
-    for (int64_t L = 0; L < P && interior_dot; ++L) {
-        if (!interior(L)) continue;
-        const int32_t G = dense[(size_t)L];
-        if (start[(size_t)G + 1] - start[(size_t)G] != 1 || masked[(size_t)G]) interior_dot = false;
-    }
-
-    // groups
-    std::vector<int32_t> zero;                       // copies of masked nodes
-    std::vector<std::vector<int32_t>> rows(GS_MAXC + 1);  // first copy ids per copy count
+    // groups: copies of masked nodes are zeroed; unmasked nodes with two or
+    // more copies are summed; unmasked single-copy nodes need nothing
+    std::vector<int32_t> zero;                            // copies of masked nodes
+    std::vector<std::vector<int32_t>> rows(GS_MAXC + 1);  // node ids per copy count
     std::vector<int32_t> csr_nodes;
     int64_t n_masked = 0, n_rows = 0, n_entries = 0;
     for (int64_t G = 0; G < U; ++G) {
@@ -337,7 +325,7 @@ int nek_gs_create(int64_t E, int N, const int64_t *glo, const uint8_t *dirichlet
             for (int32_t q = c0; q < c1; ++q) zero.push_back(copies[(size_t)q]);
             continue;
         }
-        if (c == 1 && interior_dot && interior(copies[(size_t)c0])) continue;   // left to ax
+        if (c == 1) continue;
         ++n_rows;
         n_entries += c;
         if (c <= GS_MAXC) rows[(size_t)c].push_back((int32_t)G);
@@ -353,7 +341,7 @@ int nek_gs_create(int64_t E, int N, const int64_t *glo, const uint8_t *dirichlet
         pend.push_back({0, (int32_t)zero.size(), host.size(), 0});
         host.insert(host.end(), zero.begin(), zero.end());
     }
-    for (int c = 1; c <= GS_MAXC; ++c) {
+    for (int c = 2; c <= GS_MAXC; ++c) {
         const auto &R = rows[(size_t)c];
         if (R.empty()) continue;
         const size_t at = host.size();
@@ -396,7 +384,6 @@ int nek_gs_create(int64_t E, int N, const int64_t *glo, const uint8_t *dirichlet
     d.n_entries = n_entries;
     d.n_masked = n_masked;
     d.n_zero = (int64_t)zero.size();
-    d.interior_dot = interior_dot;
     const size_t idx_bytes = align256(host.size() * sizeof(int32_t) + 4);
     const size_t bytes = idx_bytes + words * sizeof(uint32_t);
     hipError_t e = hipMalloc(&d.arena, bytes);
@@ -453,7 +440,7 @@ int nek_dssum(const nek_gs *gs, double *w, void *stream) {
     clear_error();
     if (!gs || !w) return fail(NEK_ERR_ARG, "nek_dssum: null argument");
     if (!aligned8(w)) return fail(NEK_ERR_ARG, "nek_dssum: misaligned w");
-    NEK_HIP(launch_gs(gs->d, w, nullptr, RedSite{}, nullptr, (hipStream_t)stream));
+    NEK_HIP(launch_gs(gs->d, w, nullptr, 0, nullptr, (hipStream_t)stream));
     return NEK_OK;
 }
 
@@ -481,9 +468,9 @@ void nek_cg_default_opts(nek_cg_opts *o) {
     o->reliable_drop = 0.0;
 }
 
-// Workspace layout: r, p, w | interior partials of ax | reduction sites |
+// Workspace layout: r, p, w | (p, A_L p) partials of ax | reduction sites |
 // their counters | CG scalars | one scratch double.
-enum { SITE_INIT, SITE_GS, SITE_UPDATE, SITE_REPLACE, SITE_RESID, N_SITES };
+enum { SITE_INIT, SITE_UPDATE, SITE_REPLACE, SITE_RESID, N_SITES };
 
 struct CgLayout {
     size_t vec, axp, sites, tickets, scalars, scratch, total;
@@ -590,16 +577,14 @@ int nek_cg_solve(int64_t E, int N, const double *D, const double *g, const nek_g
     }
     CgScalars *snap = g_snap.buf;
     const uint32_t *own = gs->d.own_bits;
-    const bool idot = gs->d.interior_dot;
-    const int64_t ax_parts = idot ? ax_blocks(E, N) : 0;
+    const int64_t ax_parts = ax_blocks(E, N);
 
     // one CG iteration; `first` uses p = b as set by the init kernel
-    const RedSite red_gs = site(SITE_GS, axp, (long)ax_parts);
     const RedSite red_upd = site(SITE_UPDATE, nullptr, 0);
     auto iterate = [&](bool first) -> hipError_t {
         AxFuse fz;
         fz.sc = sc;
-        fz.partials = idot ? axp : nullptr;
+        fz.partials = axp;
         if (!first) {
             fz.r = r;
             fz.x = x;
@@ -607,7 +592,7 @@ int nek_cg_solve(int64_t E, int N, const double *D, const double *g, const nek_g
         hipError_t e = mixed ? launch_ax_f32(E, N, opts.D32, opts.g_lo, g_dtype, p, w, fz, s)
                              : launch_ax_f64(E, N, D, g, p, w, fz, s);
         if (e != hipSuccess) return e;
-        e = launch_gs(gs->d, w, p, red_gs, sc, s);
+        e = launch_gs(gs->d, w, axp, ax_parts, sc, s);
         if (e != hipSuccess) return e;
         return launch_cg_update(P, r, w, own, red_upd, sc, s);
     };
@@ -617,7 +602,7 @@ int nek_cg_solve(int64_t E, int N, const double *D, const double *g, const nek_g
         if (e != hipSuccess) return e;
         e = launch_ax_f64(E, N, D, g, x, w, AxFuse{}, s);
         if (e != hipSuccess) return e;
-        return launch_gs(gs->d, w, nullptr, RedSite{}, nullptr, s);
+        return launch_gs(gs->d, w, nullptr, 0, nullptr, s);
     };
 
     int rc = NEK_OK;
@@ -661,7 +646,7 @@ int nek_cg_solve(int64_t E, int N, const double *D, const double *g, const nek_g
             // the finish kernel above ran; running it again is a no-op only if the
             // lag flag says so, so evaluate A x directly)
             CG_TRY(launch_ax_f64(E, N, D, g, x, w, AxFuse{}, s));
-            CG_TRY(launch_gs(gs->d, w, nullptr, RedSite{}, nullptr, s));
+            CG_TRY(launch_gs(gs->d, w, nullptr, 0, nullptr, s));
             CG_TRY(launch_gdiff2(P, b, w, own, site(SITE_RESID, nullptr, 0), scratch1, s));
             CG_TRY(hipMemcpyAsync(&snap[1].bb, scratch1, sizeof(double), hipMemcpyDeviceToHost, s));
             CG_TRY(hipStreamSynchronize(s));

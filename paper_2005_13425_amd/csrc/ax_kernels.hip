@@ -274,17 +274,16 @@ ax_kernel(int64_t E, const T *__restrict__ D, const GT *__restrict__ g, double *
     // ---- 6. w = r part + s part + t part
     double pw = 0.0;
     if (active) {
-        const bool inner_col = a > 0 && a < NX - 1 && b > 0 && b < NX - 1;
 #pragma unroll
         for (int k = 0; k < NX; ++k) {
             const double wv = (double)(B0[k * LS + col] + B1[k * LS + col] + B2[k * LS + col]);
             w[base + k * NN] = wv;
-            if constexpr (FUSE) {
-                if (inner_col && k > 0 && k < NX - 1) pw += pcol[k] * wv;
-            }
+            if constexpr (FUSE) pw += pcol[k] * wv;
         }
     }
-    // ---- 7. CG: per-workgroup sum of p w over element-interior points
+    // ---- 7. CG: per-workgroup sum of p (A_L p) over all local points.  For a
+    // continuous p that vanishes on masked nodes this is (p, mask(dssum(A_L p)))
+    // over unique nodes, so the gather-scatter needs no product of its own.
     if constexpr (FUSE) {
         if (fz.partials != nullptr) {
             __shared__ double red[S::THREADS / 64];

@@ -5,9 +5,8 @@
 // structure-of-arrays indices, so a thread handles one node with a fixed trip
 // count and lanes load their indices coalesced.  Copies are summed in
 // ascending local index (the oracle's order), masked nodes are written as 0.
-// In the CG the same launch also accumulates the (p, w) contributions of the
-// shared nodes; the element-interior part comes from the ax launch before it,
-// and the last workgroup turns the total into alpha.
+// In the CG its first workgroup also turns the (p, A_L p) partials of the
+// preceding ax launch into alpha.
 //
 // Vector steps: double2 loads, VEC_PAIRS pairs per thread issued together;
 // the first-copy mask is one bit per point.
@@ -24,67 +23,66 @@ __device__ __forceinline__ unsigned own_pair(const uint32_t *own, int64_t pt) {
 
 // ---------------------------------------------------------------- dssum + mask
 template <int C>
-__device__ __forceinline__ double gs_row(const GsGroup &G, int32_t row, double *__restrict__ w,
-                                         const double *__restrict__ p) {
+__device__ __forceinline__ void gs_row(const GsGroup &G, int32_t row, double *__restrict__ w) {
     int32_t id[C];
 #pragma unroll
     for (int m = 0; m < C; ++m) id[m] = G.idx[(int64_t)m * G.rows + row];
     double v[C];
 #pragma unroll
     for (int m = 0; m < C; ++m) v[m] = w[id[m]];
-    double pv = p ? p[id[0]] : 0.0;
     double s = 0.0;
 #pragma unroll
     for (int m = 0; m < C; ++m) s += v[m];
-    if (C > 1) {
 #pragma unroll
-        for (int m = 0; m < C; ++m) w[id[m]] = s;
-    }
-    return pv * s;
+    for (int m = 0; m < C; ++m) w[id[m]] = s;
 }
 
-__device__ __forceinline__ double gs_vblock(const GsArgs &a, int vb, double *__restrict__ w,
-                                            const double *__restrict__ p) {
+__device__ __forceinline__ void gs_vblock(const GsArgs &a, int vb, double *__restrict__ w) {
     int g = 0;
     while (g + 1 < a.ngroups && vb >= a.grp[g + 1].block0) ++g;
     const GsGroup &G = a.grp[g];
     const int32_t row = (vb - G.block0) * GS_THREADS + (int32_t)threadIdx.x;
-    double contrib = 0.0;
-    if (row < G.rows) {
-        switch (G.kind) {
-        case 0: w[G.idx[row]] = 0.0; break;
-        case 1: contrib = gs_row<1>(G, row, w, p); break;
-        case 2: contrib = gs_row<2>(G, row, w, p); break;
-        case 3: contrib = gs_row<3>(G, row, w, p); break;
-        case 4: contrib = gs_row<4>(G, row, w, p); break;
-        case 5: contrib = gs_row<5>(G, row, w, p); break;
-        case 6: contrib = gs_row<6>(G, row, w, p); break;
-        case 7: contrib = gs_row<7>(G, row, w, p); break;
-        case 8: contrib = gs_row<8>(G, row, w, p); break;
-        default: {   // CSR rows with many copies
-            const int32_t o0 = G.off[row], o1 = G.off[row + 1];
-            double s = 0.0;
-            for (int32_t o = o0; o < o1; ++o) s += w[G.idx[o]];
-            for (int32_t o = o0; o < o1; ++o) w[G.idx[o]] = s;
-            if (p) contrib = p[G.idx[o0]] * s;
-        }
-        }
+    if (row >= G.rows) return;
+    switch (G.kind) {
+    case 0: w[G.idx[row]] = 0.0; break;
+    case 2: gs_row<2>(G, row, w); break;
+    case 3: gs_row<3>(G, row, w); break;
+    case 4: gs_row<4>(G, row, w); break;
+    case 5: gs_row<5>(G, row, w); break;
+    case 6: gs_row<6>(G, row, w); break;
+    case 7: gs_row<7>(G, row, w); break;
+    case 8: gs_row<8>(G, row, w); break;
+    default: {   // CSR rows with many copies
+        const int32_t o0 = G.off[row], o1 = G.off[row + 1];
+        double s = 0.0;
+        for (int32_t o = o0; o < o1; ++o) s += w[G.idx[o]];
+        for (int32_t o = o0; o < o1; ++o) w[G.idx[o]] = s;
     }
-    return contrib;
+    }
 }
 
-// Workgroup b handles virtual blocks b, b + grid, ... of the group table.
+constexpr int N_XCD = 8;   // gfx950: workgroups are dealt round-robin to 8 XCDs
+
+// XCD-aware work split: the workgroups that land on one XCD (blockIdx % 8)
+// walk one contiguous eighth of the virtual blocks, so the copies a row
+// touches and the rows next to it share that XCD's L2.  Workgroup 0 also
+// turns the (p, A_L p) partials of the preceding ax launch into alpha.
 __global__ void __launch_bounds__(GS_THREADS)
-gs_kernel(GsArgs a, double *__restrict__ w, const double *__restrict__ p, RedSite red,
+gs_kernel(GsArgs a, double *__restrict__ w, const double *__restrict__ axparts, long nparts,
           CgScalars *sc) {
     if (sc != nullptr && sc->done) return;
+    const int xcd = blockIdx.x % N_XCD;
+    const int per = gridDim.x / N_XCD;           // the grid is a multiple of N_XCD
+    const int lb = blockIdx.x / N_XCD;
+    const int v0 = (int)(((long)a.nblocks * xcd) / N_XCD);
+    const int v1 = (int)(((long)a.nblocks * (xcd + 1)) / N_XCD);
+    for (int vb = v0 + lb; vb < v1; vb += per) gs_vblock(a, vb, w);
+    if (sc == nullptr || blockIdx.x != 0) return;
     __shared__ double lds[GS_THREADS / 64];
-    double contrib = 0.0;
-    for (int vb = blockIdx.x; vb < a.nblocks; vb += gridDim.x) contrib += gs_vblock(a, vb, w, p);
-    if (sc == nullptr) return;
-    const double bs = block_sum<GS_THREADS>(contrib, lds);
-    double tot;
-    if (grid_finish<GS_THREADS>(bs, red, &tot, lds) && threadIdx.x == 0) {
+    double v = 0.0;
+    for (long q = threadIdx.x; q < nparts; q += GS_THREADS) v += axparts[q];
+    const double tot = block_sum<GS_THREADS>(v, lds);
+    if (threadIdx.x == 0) {
         sc->pw = tot;
         if (!(tot > 0.0) || !__builtin_isfinite(tot)) {
             sc->status = NEK_ERR_BREAKDOWN;
@@ -361,18 +359,16 @@ int64_t vec_blocks(int64_t P) {
 }
 
 int64_t gs_grid(const GsDevice &gs) {
-    return gs.args.nblocks < RED_MAX_BLOCKS ? gs.args.nblocks : RED_MAX_BLOCKS;
+    int64_t g = gs.args.nblocks < RED_MAX_BLOCKS ? gs.args.nblocks : RED_MAX_BLOCKS;
+    g = (g + N_XCD - 1) / N_XCD * N_XCD;
+    return g < N_XCD ? N_XCD : g;
 }
 
-hipError_t launch_gs(const GsDevice &gs, double *w, const double *p, const RedSite &red,
+hipError_t launch_gs(const GsDevice &gs, double *w, const double *axparts, int64_t nparts,
                      CgScalars *sc, hipStream_t s) {
-    if (gs.args.nblocks == 0) {
-        if (sc == nullptr) return hipSuccess;
-        // nothing is shared or masked: the (p, w) product is all interior, but
-        // a launch is still needed to turn it into alpha
-    }
-    const int64_t grid = gs.args.nblocks > 0 ? gs_grid(gs) : 1;
-    hipLaunchKernelGGL(gs_kernel, dim3((unsigned)grid), dim3(GS_THREADS), 0, s, gs.args, w, p, red, sc);
+    if (gs.args.nblocks == 0 && sc == nullptr) return hipSuccess;
+    hipLaunchKernelGGL(gs_kernel, dim3((unsigned)gs_grid(gs)), dim3(GS_THREADS), 0, s, gs.args, w,
+                       axparts, (long)nparts, sc);
     return hipGetLastError();
 }
 

@@ -53,7 +53,7 @@ struct CgScalars {
 // Optional CG fusion of the local-operator launch (all device pointers):
 //   r != null : p <- r + beta p on the way in (beta from sc);
 //   x != null : x += alpha p_old first, if sc->lag_applied == 0;
-//   partials != null : per-workgroup sum of p * w over element-interior
+//   partials != null : per-workgroup sum of p * (A_L p) over all local
 //                      points, at partials[blockIdx];
 //   sc != null : skip everything once sc->done is set.
 struct AxFuse {
@@ -77,12 +77,13 @@ hipError_t launch_convert_g(int64_t count, const double *g, int g_dtype, void *o
 // A group of c copies stores its rows as structure-of-arrays indices:
 // idx[m * rows + row] is the m-th copy (ascending local index) of the row.
 // Group kind 0 lists the copies of masked nodes (written as 0).  Rows with
-// more than GS_MAXC copies go to a CSR group.
+// more than GS_MAXC copies go to a CSR group.  Unmasked nodes with a single
+// copy need no work and are not listed.
 constexpr int GS_MAXC = 8;
 constexpr int GS_THREADS = 256;
 
 struct GsGroup {
-    int kind;           // 0: zero list; 1..GS_MAXC: copies per row; -1: CSR
+    int kind;           // 0: zero list; 2..GS_MAXC: copies per row; -1: CSR
     int32_t rows;       // rows (or entries of the zero list)
     int32_t block0;     // first workgroup of this group
     const int32_t *idx; // SoA indices / zero list / CSR entries
@@ -102,20 +103,19 @@ struct GsDevice {
     int N = 0;
     int64_t P = 0;
     int64_t n_unique = 0;
-    int64_t n_rows = 0;      // unmasked rows summed by the gather-scatter
-    int64_t n_entries = 0;   // copies in those rows
+    int64_t n_rows = 0;      // unmasked shared nodes summed by the gather-scatter
+    int64_t n_entries = 0;   // copies of those nodes
     int64_t n_masked = 0;    // masked unique nodes
     int64_t n_zero = 0;      // copies of masked nodes
-    bool interior_dot = false;  // element-interior points are unshared and unmasked
     GsArgs args{};
     void *arena = nullptr;   // one allocation holding every index array
     uint32_t *own_bits = nullptr;  // P bits: first copy of every node
 };
 
-// dssum + mask in place; with sc != null also the (p, w) contributions of the
-// rows, reduced (with red.extra, the interior partials of the ax launch) into
-// sc->alpha.
-hipError_t launch_gs(const GsDevice &gs, double *w, const double *p, const RedSite &red,
+// dssum + mask in place.  With sc != null, workgroup 0 also sums the nparts
+// partials of (p, A_L p) left by the ax launch, in index order, into
+// sc->pw and sc->alpha (or flags a breakdown).
+hipError_t launch_gs(const GsDevice &gs, double *w, const double *axparts, int64_t nparts,
                      CgScalars *sc, hipStream_t s);
 int64_t gs_grid(const GsDevice &gs);
 
