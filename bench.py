@@ -177,7 +177,8 @@ def main():
                      "unit": "GB/s", "frac": round(ax_gbs / HBM_PEAK_GBS, 4),
                      "traffic": traffic_bytes(N, E),
                      "kernel": f"ax_kernel<{n},double,double,false> (nek_ax)",
-                     "bytes_per_launch": ax_bytes, "launches": reps},
+                     "bytes_per_launch": ax_bytes, "launches": reps,
+                     "duration_us": round(ax_us_cold, 2)},
         "ax_e": {"us_per_call_cold": round(ax_us_cold, 2), "us_per_call_warm": round(ax_us_warm, 2),
                  "gflops_cold": round(ax_flops / (ax_us_cold * 1e-6) / 1e9, 1),
                  "gflops_warm": round(ax_flops / (ax_us_warm * 1e-6) / 1e9, 1),
