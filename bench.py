@@ -42,6 +42,7 @@ def parse():
     ap.add_argument("--iters", type=int, default=100)
     ap.add_argument("--ax-reps", type=int, default=200)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-mixed", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     return ap.parse_args()
 
@@ -195,10 +196,66 @@ def main():
         "measured_copy_gbs": round(copy_gbs, 1),
     }
 
+    if not args.no_mixed:
+        out["mixed"] = mixed_leg(nek, torch, dev, Ex, Ey, Ez, N, D, g, gs, ws)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(Ex, Ey, Ez, N, args.cpu_seconds)
     gs.close()
     print(json.dumps(out), flush=True)
+
+
+def mixed_leg(nek, torch, dev, Ex, Ey, Ez, N, D, g, gs, ws, tol=1e-10):
+    """Time to a true relative residual of 1e-10 on the manufactured solution
+    sin(pi x) sin(pi y) sin(pi z): FP64 CG against the FP32 operator with g in
+    FP32 and in BF16 inside FP64 reliable-update CG, on the same mesh."""
+    import numpy as np
+    E = Ex * Ey * Ez
+    g2, bm, X = nek.box_geometry(Ex, Ey, Ez, N, synth_amp(), synth_coeffs(), want_mass=True,
+                                 want_coords=True)
+    P = bm.numel()
+    x0, y0, z0 = X[:P], X[P:2 * P], X[2 * P:]
+    f = 3.0 * np.pi ** 2 * torch.sin(np.pi * x0) * torch.sin(np.pi * y0) * torch.sin(np.pi * z0)
+    b = (bm * f).contiguous()
+    gs.dssum(b)
+    ustar = torch.sin(np.pi * x0) * torch.sin(np.pi * y0) * torch.sin(np.pi * z0)
+    D32 = D.float().contiguous()
+    res = {}
+    x64 = None
+    for name, prec, code in (("fp64", nek.NEK_PREC_F64, None),
+                             ("f32_g32", nek.NEK_PREC_F32G32, nek.NEK_G_F32),
+                             ("f32_gbf16", nek.NEK_PREC_F32GBF16, nek.NEK_G_BF16)):
+        glo = nek.convert_g(g, N, code) if code else None
+        x = torch.empty_like(b)
+        nek.cg_solve(D, g, gs, b, x, max_iter=5000, rel_tol=tol, precision=prec, D32=D32, g_lo=glo,
+                     true_residual=True, workspace=ws)      # warm-up
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        _, r = nek.cg_solve(D, g, gs, b, x, max_iter=5000, rel_tol=tol, precision=prec, D32=D32,
+                            g_lo=glo, true_residual=True, workspace=ws)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        if x64 is None:
+            x64 = x.clone()
+        res[name] = {"ms": round(dt * 1e3, 3), "iters": r.iters, "replacements": r.n_replacements,
+                     "true_rel_res": r.rel_res_true,
+                     "rel_err_vs_fp64_solve": float(torch.linalg.norm(x - x64) / torch.linalg.norm(x64)),
+                     "rel_err_vs_exact_u": float(torch.linalg.norm(x - ustar) / torch.linalg.norm(ustar))}
+        del glo
+    for name in ("f32_g32", "f32_gbf16"):
+        res[name]["speedup_vs_fp64"] = round(res["fp64"]["ms"] / res[name]["ms"], 3)
+    res["workload"] = (f"manufactured sin solution, E={E} ({Ex}x{Ey}x{Ez}) N={N}, stop at true "
+                       f"||b-Ax||/||b|| <= {tol}; FP64 residual/dots/axpy, reliable updates")
+    return res
+
+
+def synth_amp():
+    import synth
+    return synth.AMP
+
+
+def synth_coeffs():
+    import synth
+    return synth.geom_coeffs()
 
 
 def traffic_bytes(N, E):
