@@ -112,15 +112,19 @@ int nek_ax(int64_t E, int N, const double *u, const double *D, const double *g,
 
 /* The same operator computed in FP32: u is read in FP64 and rounded, the
  * contractions and the geometric multiply run in FP32 with D32 (FP32 copy of
- * D) and g_lo (the factors stored as FP32 or BF16, g_dtype = NEK_G_F32 or
- * NEK_G_BF16, same gxyz layout), and w is written in FP64.  Used inside the
- * FP64 reliable-update CG (NEK_PREC_F32G*).  Allocates nothing.
+ * D, 4-byte aligned) and g_lo (the factors as FP32 or BF16, g_dtype =
+ * NEK_G_F32 or NEK_G_BF16, in the paired layout written by nek_convert_g;
+ * 8-byte aligned for FP32, 4-byte for BF16), and w is written in FP64.  Used
+ * inside the FP64 reliable-update CG (NEK_PREC_F32G*).  Allocates nothing.
  * Asynchronous. */
 int nek_ax_f32(int64_t E, int N, const double *u, const float *D32, const void *g_lo,
                int g_dtype, double *w, void *stream);
 
-/* Round g (6*P FP64 values, device) to FP32 or BF16 (round to nearest even)
- * into g_lo (device, 6*P elements of the chosen type).  Asynchronous. */
+/* Round g (6*P FP64 values, device) to FP32 or BF16 (round to nearest even;
+ * BF16 through FP32) into g_lo (device, 6*P values of the chosen type).
+ * Paired layout of g_lo: per element, three planes q = 0, 1, 2 of n^3 pairs
+ * (gxyz(.,2q), gxyz(.,2q+1)) in point order, so that the FP32 operator loads
+ * one pair per load.  Asynchronous. */
 int nek_convert_g(int64_t E, int N, const double *g, int g_dtype, void *g_lo, void *stream);
 
 /* ---------------------------------------------------- gather-scatter (dssum) */

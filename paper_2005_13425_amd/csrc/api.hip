@@ -211,8 +211,8 @@ int nek_ax_f32(int64_t E, int N, const double *u, const float *D32, const void *
     if (rc) return rc;
     if (g_dtype != NEK_G_F32 && g_dtype != NEK_G_BF16)
         return fail(NEK_ERR_UNSUPPORTED, "nek_ax_f32: g_dtype must be NEK_G_F32 or NEK_G_BF16");
-    if (g_dtype == NEK_G_F32 && ((uintptr_t)g_lo & 3u))
-        return fail(NEK_ERR_ARG, "nek_ax_f32: misaligned g");
+    if (((uintptr_t)g_lo & (g_dtype == NEK_G_F32 ? 7u : 3u)) || ((uintptr_t)D32 & 3u))
+        return fail(NEK_ERR_ARG, "nek_ax_f32: misaligned g_lo (8 bytes for FP32, 4 for BF16) or D32");
     NEK_HIP(launch_ax_f32(E, N, D32, g_lo, g_dtype, const_cast<double *>(u), w, AxFuse{},
                           (hipStream_t)stream));
     return NEK_OK;
@@ -225,9 +225,9 @@ int nek_convert_g(int64_t E, int N, const double *g, int g_dtype, void *g_lo, vo
     if (!g || !g_lo) return fail(NEK_ERR_ARG, "nek_convert_g: null pointer");
     if (g_dtype != NEK_G_F32 && g_dtype != NEK_G_BF16)
         return fail(NEK_ERR_UNSUPPORTED, "nek_convert_g: g_dtype must be NEK_G_F32 or NEK_G_BF16");
-    if (!aligned8(g) || ((uintptr_t)g_lo & (g_dtype == NEK_G_F32 ? 3u : 1u)))
+    if (!aligned8(g) || ((uintptr_t)g_lo & (g_dtype == NEK_G_F32 ? 7u : 3u)))
         return fail(NEK_ERR_ARG, "nek_convert_g: misaligned pointer");
-    NEK_HIP(launch_convert_g(6 * E * n3_of(N), g, g_dtype, g_lo, (hipStream_t)stream));
+    NEK_HIP(launch_convert_g(E, N, g, g_dtype, g_lo, (hipStream_t)stream));
     return NEK_OK;
 }
 
@@ -531,6 +531,9 @@ int nek_cg_solve(int64_t E, int N, const double *D, const double *g, const nek_g
         return fail(NEK_ERR_UNSUPPORTED, "nek_cg_solve: unknown precision");
     if (mixed && (!opts.D32 || !opts.g_lo))
         return fail(NEK_ERR_ARG, "nek_cg_solve: mixed precision needs D32 and g_lo");
+    if (mixed && (((uintptr_t)opts.g_lo & (opts.precision == NEK_PREC_F32G32 ? 7u : 3u)) ||
+                  ((uintptr_t)opts.D32 & 3u)))
+        return fail(NEK_ERR_ARG, "nek_cg_solve: misaligned g_lo or D32");
     const int g_dtype = opts.precision == NEK_PREC_F32G32 ? NEK_G_F32 : NEK_G_BF16;
     const double drop = mixed ? (opts.reliable_drop > 0.0 ? opts.reliable_drop : 0.1) : 0.0;
     if (mixed && !(drop < 1.0)) return fail(NEK_ERR_ARG, "nek_cg_solve: reliable_drop must be < 1");
@@ -569,7 +572,7 @@ int nek_cg_solve(int64_t E, int N, const double *D, const double *g, const nek_g
     };
 
     if (!g_snap.buf) {
-        hipError_t e = hipHostMalloc((void **)&g_snap.buf, 2 * sizeof(CgScalars), hipHostMallocDefault);
+        hipError_t e = hipHostMalloc((void **)&g_snap.buf, 4 * sizeof(CgScalars), hipHostMallocDefault);
         if (e != hipSuccess) {
             if (own_ws) (void)hipFreeAsync(ws, s);
             return check_hip(e, "nek_cg_solve: hipHostMalloc");
@@ -615,10 +618,20 @@ int nek_cg_solve(int64_t E, int N, const double *D, const double *g, const nek_g
         he = (call);                                                     \
         if (he != hipSuccess) { rc = check_hip(he, #call); goto out; }   \
     } while (0)
+    hipEvent_t ev[2] = {nullptr, nullptr};
     {
         CG_TRY(launch_cg_reset(sc, tickets, N_SITES * RED_TICKETS, opts.max_iter, opts.rel_tol, drop, s));
         CG_TRY(launch_cg_init(P, b, x, r, p, own, site(SITE_INIT, nullptr, 0), sc, s));
-        int enq = 0;
+        if (poll) {
+            CG_TRY(hipEventCreateWithFlags(&ev[0], hipEventDisableTiming));
+            CG_TRY(hipEventCreateWithFlags(&ev[1], hipEventDisableTiming));
+        }
+        // The host polls a snapshot of the device scalars after every chunk of
+        // check_every iterations, one chunk behind: chunk c+1 is already queued
+        // while the host waits for the snapshot of chunk c, so the device never
+        // idles on the poll.  Kernels queued after the solve has finished exit
+        // at once.
+        int enq = 0, chunks = 0, prev = -1, replacements = 0;
         bool first = true;
         while (enq < opts.max_iter) {
             const int chunk = std::min(check_every, opts.max_iter - enq);
@@ -628,19 +641,27 @@ int nek_cg_solve(int64_t E, int N, const double *D, const double *g, const nek_g
             }
             enq += chunk;
             if (!poll) continue;
-            CG_TRY(hipMemcpyAsync(snap, sc, sizeof(CgScalars), hipMemcpyDeviceToHost, s));
-            CG_TRY(hipStreamSynchronize(s));
-            if (snap->done) break;
-            if (mixed && snap->need_replace) {
-                // reliable update: r <- b - mask(dssum(A64 x)) in FP64
-                CG_TRY(true_ax());
-                CG_TRY(launch_cg_replace(P, b, w, r, own, site(SITE_REPLACE, nullptr, 0), sc, s));
+            const int slot = chunks++ & 1;
+            CG_TRY(hipMemcpyAsync(&snap[slot], sc, sizeof(CgScalars), hipMemcpyDeviceToHost, s));
+            CG_TRY(hipEventRecord(ev[slot], s));
+            if (prev >= 0) {
+                CG_TRY(hipEventSynchronize(ev[prev]));
+                const CgScalars &v = snap[prev];
+                if (v.done) break;
+                // reliable update: r <- b - mask(dssum(A64 x)) in FP64, at most one
+                // per snapshot that asked for it
+                if (mixed && v.need_replace && v.n_replace >= replacements) {
+                    CG_TRY(true_ax());
+                    CG_TRY(launch_cg_replace(P, b, w, r, own, site(SITE_REPLACE, nullptr, 0), sc, s));
+                    ++replacements;
+                }
             }
+            prev = slot;
         }
         CG_TRY(launch_cg_finish(P, x, p, sc, s));
-        CG_TRY(hipMemcpyAsync(snap, sc, sizeof(CgScalars), hipMemcpyDeviceToHost, s));
+        CG_TRY(hipMemcpyAsync(&snap[2], sc, sizeof(CgScalars), hipMemcpyDeviceToHost, s));
         CG_TRY(hipStreamSynchronize(s));
-        S = *snap;
+        S = snap[2];
         if (opts.true_residual || mixed) {
             // ||b - mask(dssum(A64 x))|| over unique nodes, in FP64 (x is up to date:
             // the finish kernel above ran; running it again is a no-op only if the
@@ -648,14 +669,19 @@ int nek_cg_solve(int64_t E, int N, const double *D, const double *g, const nek_g
             CG_TRY(launch_ax_f64(E, N, D, g, x, w, AxFuse{}, s));
             CG_TRY(launch_gs(gs->d, w, nullptr, 0, nullptr, s));
             CG_TRY(launch_gdiff2(P, b, w, own, site(SITE_RESID, nullptr, 0), scratch1, s));
-            CG_TRY(hipMemcpyAsync(&snap[1].bb, scratch1, sizeof(double), hipMemcpyDeviceToHost, s));
+            CG_TRY(hipMemcpyAsync(&snap[3].bb, scratch1, sizeof(double), hipMemcpyDeviceToHost, s));
             CG_TRY(hipStreamSynchronize(s));
-            true_rel = S.bb > 0.0 ? sqrt(snap[1].bb / S.bb) : 0.0;
+            true_rel = S.bb > 0.0 ? sqrt(snap[3].bb / S.bb) : 0.0;
         }
     }
 out:
 #undef CG_TRY
-    if (own_ws) (void)hipFreeAsync(ws, s);
+    for (hipEvent_t e : ev)
+        if (e) (void)hipEventDestroy(e);
+    if (own_ws) {
+        if (rc != NEK_OK) (void)hipStreamSynchronize(s);
+        (void)hipFreeAsync(ws, s);
+    }
     if (rc != NEK_OK) {
         if (st) st->status = rc;
         return rc;

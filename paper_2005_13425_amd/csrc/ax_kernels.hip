@@ -57,25 +57,48 @@ struct AxShape {
 #endif
 };
 
-template <typename GT>
-__device__ __forceinline__ float g_to_f32(GT v);
-template <>
-__device__ __forceinline__ float g_to_f32<float>(float v) { return v; }
-template <>
-__device__ __forceinline__ float g_to_f32<uint16_t>(uint16_t v) {
-    return __uint_as_float(((uint32_t)v) << 16);
-}
+// Loading the six geometric factors of one point of layer k.
+//   FP64 g: the layout of Listing 1, six planes of n^3 per element (six loads).
+//   FP32 / BF16 g (the mixed form's own copy, written by nek_convert_g): per
+//   element three planes q = 0..2 of n^3 pairs (g_2q, g_2q+1), so a point
+//   needs three 8-byte (FP32) or three 4-byte (BF16) loads, coalesced across
+//   the lanes of a layer.
+template <typename T, typename GT, int N3>
+struct GLoad;
 
-template <typename T, typename GT>
-__device__ __forceinline__ T load_g(const GT *p);
-template <>
-__device__ __forceinline__ double load_g<double, double>(const double *p) { return *p; }
-template <>
-__device__ __forceinline__ float load_g<float, float>(const float *p) { return *p; }
-template <>
-__device__ __forceinline__ float load_g<float, uint16_t>(const uint16_t *p) {
-    return g_to_f32<uint16_t>(*p);
-}
+template <int N3>
+struct GLoad<double, double, N3> {
+    __device__ static __forceinline__ void load(const double *ge, int off, double *o) {
+#pragma unroll
+        for (int q = 0; q < 6; ++q) o[q] = ge[q * N3 + off];
+    }
+};
+
+template <int N3>
+struct GLoad<float, float, N3> {
+    __device__ static __forceinline__ void load(const float *ge, int off, float *o) {
+        const float2 *pp = (const float2 *)ge;
+#pragma unroll
+        for (int q = 0; q < 3; ++q) {
+            const float2 v = pp[q * N3 + off];
+            o[2 * q] = v.x;
+            o[2 * q + 1] = v.y;
+        }
+    }
+};
+
+template <int N3>
+struct GLoad<float, uint16_t, N3> {
+    __device__ static __forceinline__ void load(const uint16_t *ge, int off, float *o) {
+        const uint32_t *pp = (const uint32_t *)ge;
+#pragma unroll
+        for (int q = 0; q < 3; ++q) {
+            const uint32_t v = pp[q * N3 + off];
+            o[2 * q] = __uint_as_float(v << 16);
+            o[2 * q + 1] = __uint_as_float(v & 0xffff0000u);
+        }
+    }
+};
 
 // T: compute type (double or float); GT: storage type of g; FUSE: CG fusion.
 //
@@ -176,12 +199,16 @@ ax_kernel(int64_t E, const T *__restrict__ D, const GT *__restrict__ g, double *
 
     // geometric factors of the first PF layers go out now, each later layer
     // PF layers ahead of its use
-    const GT *ge = g + e * (6 * N3) + c;
+    const GT *ge = g + e * (6 * N3);   // this element's factors
     T gq[PF][6];
 #pragma unroll
-    for (int k = 0; k < PF; ++k)
+    for (int k = 0; k < PF; ++k) {
+        if (active) GLoad<T, GT, N3>::load(ge, k * NN + c, gq[k]);
+        else {
 #pragma unroll
-        for (int q = 0; q < 6; ++q) gq[k][q] = active ? load_g<T, GT>(ge + q * N3 + k * NN) : T(0);
+            for (int q = 0; q < 6; ++q) gq[k][q] = T(0);
+        }
+    }
     __syncthreads();
 
     // ---- 2. forward contractions: outer products with dxm1(:, l) = D[n l .. n l + n)
@@ -234,11 +261,7 @@ ax_kernel(int64_t E, const T *__restrict__ D, const GT *__restrict__ g, double *
             B2[k * LS + col] = usv;
         }
         ut[k] = utv;
-        if (k + PF < NX) {
-#pragma unroll
-            for (int q = 0; q < 6; ++q)
-                gq[k % PF][q] = active ? load_g<T, GT>(ge + q * N3 + (k + PF) * NN) : T(0);
-        }
+        if (k + PF < NX && active) GLoad<T, GT, N3>::load(ge, (k + PF) * NN + c, gq[k % PF]);
     }
     __syncthreads();
 
@@ -334,15 +357,23 @@ __device__ __forceinline__ uint16_t f64_to_bf16(double v) {
     return (uint16_t)(b >> 16);
 }
 
-__global__ void convert_g_kernel(int64_t count, const double *__restrict__ g, int dtype,
-                                 void *__restrict__ out)
-{
+// g (six planes of n^3 per element) -> three planes of pairs (g_2q, g_2q+1)
+__global__ void convert_g_kernel(int64_t E, int64_t n3, const double *__restrict__ g, int dtype,
+                                 void *__restrict__ out) {
+    const int64_t npairs = E * 3 * n3;
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < count; t += stride) {
-        if (dtype == NEK_G_F32)
-            ((float *)out)[t] = (float)g[t];
-        else
-            ((uint16_t *)out)[t] = f64_to_bf16(g[t]);
+    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < npairs; t += stride) {
+        const int64_t e = t / (3 * n3);
+        const int64_t rem = t - e * 3 * n3;
+        const int64_t q = rem / n3;
+        const int64_t pt = rem - q * n3;
+        const double lo = g[(e * 6 + 2 * q) * n3 + pt];
+        const double hi = g[(e * 6 + 2 * q + 1) * n3 + pt];
+        if (dtype == NEK_G_F32) {
+            ((float2 *)out)[t] = make_float2((float)lo, (float)hi);
+        } else {
+            ((uint32_t *)out)[t] = (uint32_t)f64_to_bf16(lo) | ((uint32_t)f64_to_bf16(hi) << 16);
+        }
     }
 }
 
@@ -371,13 +402,13 @@ int64_t ax_blocks(int64_t E, int N)
     return (E + epb - 1) / epb;
 }
 
-hipError_t launch_convert_g(int64_t count, const double *g, int g_dtype, void *out, hipStream_t s)
+hipError_t launch_convert_g(int64_t E, int N, const double *g, int g_dtype, void *out, hipStream_t s)
 {
-    int64_t blocks = (count + 255) / 256;
+    const int64_t n3 = n3_of(N);
+    int64_t blocks = (E * 3 * n3 + 255) / 256;
     if (blocks > 65536) blocks = 65536;
     if (blocks < 1) blocks = 1;
-    hipLaunchKernelGGL(convert_g_kernel, dim3((unsigned)blocks), dim3(256), 0, s, count, g,
-                       g_dtype, out);
+    hipLaunchKernelGGL(convert_g_kernel, dim3((unsigned)blocks), dim3(256), 0, s, E, n3, g, g_dtype, out);
     return hipGetLastError();
 }
 

@@ -70,7 +70,7 @@ hipError_t launch_ax_f32(int64_t E, int N, const float *D32, const void *g_lo, i
 // number of workgroups of an ax launch (one partial each)
 int64_t ax_blocks(int64_t E, int N);
 
-hipError_t launch_convert_g(int64_t count, const double *g, int g_dtype, void *out, hipStream_t s);
+hipError_t launch_convert_g(int64_t E, int N, const double *g, int g_dtype, void *out, hipStream_t s);
 
 // ---------------------------------------------------------------- gather-scatter
 // Nodes handled by the gather-scatter are grouped by their number of copies.

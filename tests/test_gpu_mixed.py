@@ -52,13 +52,19 @@ def _bf16_to_f64(bits):
     return (bits.astype(np.uint32) << 16).view(np.float32).astype(np.float64)
 
 
+def _paired(a, E, n3):
+    """[e][c][pt] -> [e][q][pt][2] with (c = 2q, 2q+1): the paired layout."""
+    return a.reshape(E, 3, 2, n3).transpose(0, 1, 3, 2).reshape(-1)
+
+
 def test_convert_g_bit_exact(nek):
     m = oracle.box_mesh(3, 2, 2, 5, synth.AMP, synth.geom_coeffs())
     g = _dev(m.g)
+    n3 = 6 ** 3
     g32 = nek.convert_g(g, 5, nek.NEK_G_F32)
-    np.testing.assert_array_equal(g32.cpu().numpy(), m.g.astype(np.float32))
+    np.testing.assert_array_equal(g32.cpu().numpy(), _paired(m.g.astype(np.float32), m.E, n3))
     g16 = nek.convert_g(g, 5, nek.NEK_G_BF16)
-    np.testing.assert_array_equal(g16.cpu().numpy().view(np.uint16), _bf16_rne(m.g))
+    np.testing.assert_array_equal(g16.cpu().numpy().view(np.uint16), _paired(_bf16_rne(m.g), m.E, n3))
 
 
 @pytest.mark.parametrize("N", [1, 3, 5, 7, 9, 11, 15])
