@@ -73,10 +73,12 @@ def test_ax_parity_paper_shapes(nek, E_box):
     assert _rel(w, ref) <= TOL
 
 
-def test_ax_sampled_sweep_shape(nek):
-    # the degree-sweep box at N=9 (32^3 elements): compare sampled elements
-    N = 9
+@pytest.mark.parametrize("N", sorted(synth.SWEEP_BOXES))
+def test_ax_sampled_sweep_shape(nek, N):
+    # the degree-sweep boxes (about 32.8 M local points each, the launch the
+    # sweep times): compare sampled elements, including the first and the last
     Ex, Ey, Ez = synth.SWEEP_BOXES[N]
+    print(f"sweep N={N} box {Ex}x{Ey}x{Ez}", flush=True)
     E = Ex * Ey * Ez
     n3 = (N + 1) ** 3
     z, wq = oracle.gll(N)
@@ -94,6 +96,8 @@ def test_ax_sampled_sweep_shape(nek):
     wh = w.view(E, n3)[torch.from_numpy(sample).cuda()].cpu().numpy().reshape(-1)
     ref = oracle.ax(len(sample), N, D, gh, uh)
     assert _rel(wh, ref) <= TOL
+    del g, X, u, w
+    torch.cuda.empty_cache()
 
 
 def test_geometry_parity(nek):
