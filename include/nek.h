@@ -208,6 +208,83 @@ int nek_cg_solve(int64_t E, int N, const double *D, const double *g, const nek_g
                  const double *b, double *x, const nek_cg_opts *opts, nek_cg_stats *stats,
                  void *stream);
 
+/* ------------------------------------------------------------ served solves */
+
+/* A solve service: requests (box meshes of any size and degree) arrive over
+ * time; each is admitted when its whole device footprint fits in the HBM
+ * budget, its CG state then stays resident, and every server step advances
+ * all admitted solves by CG iterations in shared launches (one operator,
+ * one gather-scatter and one update launch per (degree, precision) group).
+ * Each solve's arithmetic is the same as when it runs alone.  The method is
+ * the one of nek_cg_solve (Sec. III, Sec. V); the service around it is not
+ * in the paper. */
+
+typedef struct nek_server nek_server;
+
+typedef struct {
+    int Ex, Ey, Ez, N;   /* box of Ex x Ey x Ez elements of degree N (geometry as
+                            in nek_box_geometry, numbering and Dirichlet faces as in
+                            nek_box_numbering); built on the device at admission */
+    double amp;          /* displacement amplitude */
+    double a[3];         /* displacement coefficients */
+    const double *b;     /* host, P doubles, local layout, continuous and zero on
+                            the box faces; copied by nek_server_submit */
+    int precision;       /* NEK_PREC_* */
+    double rel_tol;      /* stop at ||r||/||b|| <= rel_tol (true residual in the
+                            mixed precisions); <= 0: run max_iter iterations */
+    int max_iter;
+} nek_request;
+
+typedef struct {
+    uint64_t id;
+    int status;          /* NEK_OK, NEK_ERR_BREAKDOWN, NEK_ERR_NOCONV, NEK_ERR_DEVICE */
+    int iters;
+    int n_replacements;
+    double rel_res;      /* recurrence residual */
+    double rel_res_true; /* ||b - A x|| / ||b|| evaluated in FP64 */
+    double t_submit;     /* seconds on the server clock */
+    double t_admit;
+    double t_done;       /* when a server step saw the finished solve */
+    int64_t E;
+    int N;
+    size_t footprint;    /* device bytes held while admitted */
+} nek_result;
+
+/* Create a server on the current device with a device-memory budget in
+ * bytes.  Starts one host thread that prepares submitted requests (their
+ * numbering and gather-scatter tables).  Synchronous. */
+int nek_server_create(size_t hbm_budget, nek_server **out);
+
+/* Queue a request; *id receives its id.  NEK_ERR_NOMEM if its footprint can
+ * never fit the budget.  Copies req->b.  Returns at once. */
+int nek_server_submit(nek_server *srv, const nek_request *req, uint64_t *id);
+
+/* Footprint in device bytes of a request (what admission charges). */
+size_t nek_server_footprint(int Ex, int Ey, int Ez, int N, int precision);
+
+/* One step: admit prepared requests in arrival order while they fit, run
+ * `iters` CG iterations of every admitted solve, and retire solves whose
+ * completion the step observed.  active / queued (may be NULL) receive the
+ * number of admitted and waiting requests after the step.  Returns after
+ * queueing the device work (it waits only for the device work of the step
+ * before). */
+int nek_server_step(nek_server *srv, int iters, int *active, int *queued);
+
+/* Finished solves not reported yet: up to max results into out[], *n their
+ * number. */
+int nek_server_poll(nek_server *srv, nek_result *out, int max, int *n);
+
+/* Copy the solution of finished request id to x_host (P doubles) and release
+ * its device memory.  Synchronous. */
+int nek_server_fetch(nek_server *srv, uint64_t id, double *x_host);
+
+/* Seconds on the server clock (the time base of nek_result). */
+double nek_server_clock(const nek_server *srv);
+
+/* Stop the preparation thread, wait for the device, free everything.
+ * NULL is accepted. */
+int nek_server_destroy(nek_server *srv);
+
 /* ------------------------------------------------------------ measurement */
 
 /* Streaming bandwidth probe for the measured roofline (Sec. V: the

@@ -62,6 +62,20 @@ class CgStats(ctypes.Structure):
                 ("rel_res_true", ctypes.c_double), ("n_replacements", ctypes.c_int)]
 
 
+class Request(ctypes.Structure):
+    _fields_ = [("Ex", ctypes.c_int), ("Ey", ctypes.c_int), ("Ez", ctypes.c_int), ("N", ctypes.c_int),
+                ("amp", ctypes.c_double), ("a", ctypes.c_double * 3), ("b", _vp),
+                ("precision", ctypes.c_int), ("rel_tol", ctypes.c_double), ("max_iter", ctypes.c_int)]
+
+
+class Result(ctypes.Structure):
+    _fields_ = [("id", ctypes.c_uint64), ("status", ctypes.c_int), ("iters", ctypes.c_int),
+                ("n_replacements", ctypes.c_int), ("rel_res", ctypes.c_double),
+                ("rel_res_true", ctypes.c_double), ("t_submit", ctypes.c_double),
+                ("t_admit", ctypes.c_double), ("t_done", ctypes.c_double), ("E", ctypes.c_int64),
+                ("N", ctypes.c_int), ("footprint", ctypes.c_size_t)]
+
+
 def _sig(name, res, args):
     f = getattr(_lib, name)
     f.restype = res
@@ -84,6 +98,14 @@ _sig("nek_gs_info", _ci, [_vp] + [ctypes.POINTER(_i64)] * 4)
 _sig("nek_dssum", _ci, [_vp, _vp, _vp])
 _sig("nek_gs_dot", _ci, [_vp, _vp, _vp, _vp, _vp])
 _sig("nek_bw_probe", _ci, [_i64, _ci, _vp, _vp, _ci, _vp])
+_sig("nek_server_create", _ci, [ctypes.c_size_t, ctypes.POINTER(_vp)])
+_sig("nek_server_submit", _ci, [_vp, ctypes.POINTER(Request), ctypes.POINTER(ctypes.c_uint64)])
+_sig("nek_server_footprint", ctypes.c_size_t, [_ci, _ci, _ci, _ci, _ci])
+_sig("nek_server_step", _ci, [_vp, _ci, ctypes.POINTER(_ci), ctypes.POINTER(_ci)])
+_sig("nek_server_poll", _ci, [_vp, ctypes.POINTER(Result), _ci, ctypes.POINTER(_ci)])
+_sig("nek_server_fetch", _ci, [_vp, ctypes.c_uint64, _vp])
+_sig("nek_server_clock", ctypes.c_double, [_vp])
+_sig("nek_server_destroy", _ci, [_vp])
 _sig("nek_cg_default_opts", None, [ctypes.POINTER(CgOpts)])
 _sig("nek_cg_workspace_bytes", ctypes.c_size_t, [_i64, _ci])
 _sig("nek_cg_solve", _ci, [_i64, _ci, _vp, _vp, _vp, _vp, _vp, ctypes.POINTER(CgOpts),
@@ -342,3 +364,73 @@ def cg_workspace(E: int, N: int, device="cuda"):
     torch = _torch()
     nbytes = cg_workspace_bytes(E, N)
     return torch.empty(nbytes, dtype=torch.uint8, device=device)
+
+
+# ------------------------------------------------------------------ served solves
+def server_footprint(Ex: int, Ey: int, Ez: int, N: int, precision: int = NEK_PREC_F64) -> int:
+    return int(_lib.nek_server_footprint(Ex, Ey, Ez, N, precision))
+
+
+class Server:
+    """Served Poisson solves on the device (nek_server_*): submit box-mesh
+    requests as they arrive, call step() to admit and advance them, poll()
+    finished ones and fetch() their solutions."""
+
+    def __init__(self, hbm_budget: int):
+        h = ctypes.c_void_p()
+        _check(_lib.nek_server_create(int(hbm_budget), ctypes.byref(h)), "nek_server_create")
+        self._h = h
+        self._sizes = {}
+
+    def submit(self, Ex, Ey, Ez, N, b, amp=0.0, a=(0.0, 0.0, 0.0), precision=NEK_PREC_F64,
+               rel_tol=1e-10, max_iter=10000) -> int:
+        P = Ex * Ey * Ez * (N + 1) ** 3
+        b = _host_np(b, np.float64, "b", P)
+        r = Request(Ex, Ey, Ez, N, float(amp), (ctypes.c_double * 3)(*a), b.ctypes.data,
+                    int(precision), float(rel_tol), int(max_iter))
+        rid = ctypes.c_uint64()
+        _check(_lib.nek_server_submit(self._h, ctypes.byref(r), ctypes.byref(rid)), "nek_server_submit")
+        self._sizes[rid.value] = P
+        return rid.value
+
+    def step(self, iters: int = 1):
+        act, que = _ci(), _ci()
+        _check(_lib.nek_server_step(self._h, int(iters), ctypes.byref(act), ctypes.byref(que)),
+               "nek_server_step")
+        return act.value, que.value
+
+    def poll(self, max_results: int = 64):
+        buf = (Result * max_results)()
+        n = _ci()
+        _check(_lib.nek_server_poll(self._h, buf, max_results, ctypes.byref(n)), "nek_server_poll")
+        return [{f: getattr(buf[i], f) for f, _ in Result._fields_} for i in range(n.value)]
+
+    def fetch(self, rid: int):
+        x = np.empty(self._sizes[rid])
+        _check(_lib.nek_server_fetch(self._h, ctypes.c_uint64(rid), x.ctypes.data), "nek_server_fetch")
+        return x
+
+    def clock(self) -> float:
+        return float(_lib.nek_server_clock(self._h))
+
+    def run_until_done(self, ids, iters: int = 1, max_steps: int = 10 ** 7):
+        """Step until every id in ids has finished; returns {id: result}."""
+        want, got = set(ids), {}
+        for _ in range(max_steps):
+            self.step(iters)
+            for r in self.poll():
+                got[r["id"]] = r
+            if want <= set(got):
+                return got
+        raise RuntimeError("server did not finish")
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _lib.nek_server_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -254,27 +254,28 @@ static void gs_free(nek_gs *h) {
     delete h;
 }
 
-static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+}  // extern "C"
 
-int nek_gs_create(int64_t E, int N, const int64_t *glo, const uint8_t *dirichlet, nek_gs **out) {
-    clear_error();
-    if (!out) return fail(NEK_ERR_ARG, "nek_gs_create: out is null");
-    *out = nullptr;
-    if (E < 1) return fail(NEK_ERR_ARG, "nek_gs_create: E must be >= 1");
-    if (N < 1 || N > NEK_MAX_DEGREE) return fail(NEK_ERR_UNSUPPORTED, "nek_gs_create: degree must be in 1..15");
-    if (!glo) return fail(NEK_ERR_ARG, "nek_gs_create: glo is null");
-    const int n = N + 1;
+namespace nek {
+
+int gs_build_host(int64_t E, int N, const int64_t *glo, const uint8_t *dirichlet, GsHost &H,
+                  std::string &msg) {
     const int64_t n3 = n3_of(N);
     const int64_t P = E * n3;
-    if (P >= ((int64_t)1 << 31)) return fail(NEK_ERR_ARG, "nek_gs_create: E*(N+1)^3 must be < 2^31");
-
-    // dense renumbering of the ids: counting when the id range is compact
+    if (P >= ((int64_t)1 << 31)) {
+        msg = "E*(N+1)^3 must be < 2^31";
+        return NEK_ERR_ARG;
+    }
+    // dense renumbering of the ids in order of first appearance
     int64_t gmin = glo[0], gmax = glo[0];
     for (int64_t L = 0; L < P; ++L) {
         gmin = std::min(gmin, glo[L]);
         gmax = std::max(gmax, glo[L]);
     }
-    if (gmin < 0) return fail(NEK_ERR_ARG, "nek_gs_create: negative global id");
+    if (gmin < 0) {
+        msg = "negative global id";
+        return NEK_ERR_ARG;
+    }
     std::vector<int32_t> dense((size_t)P);
     int64_t U = 0;
     if (gmax < 4 * P + 1024) {
@@ -297,9 +298,8 @@ int nek_gs_create(int64_t E, int N, const int64_t *glo, const uint8_t *dirichlet
             dense[(size_t)L] = first_seen[sid];
         }
     }
-    // copies of every node in ascending local index (counting sort); since the
-    // dense ids are assigned in order of first appearance, node order is the
-    // order of first copies
+    // copies of every node in ascending local index (counting sort); node
+    // order is the order of first copies
     std::vector<int32_t> start((size_t)U + 1, 0);
     std::vector<uint8_t> masked((size_t)U, 0);
     for (int64_t L = 0; L < P; ++L) {
@@ -313,8 +313,8 @@ int nek_gs_create(int64_t E, int N, const int64_t *glo, const uint8_t *dirichlet
 
     // groups: copies of masked nodes are zeroed; unmasked nodes with two or
     // more copies are summed; unmasked single-copy nodes need nothing
-    std::vector<int32_t> zero;                            // copies of masked nodes
-    std::vector<std::vector<int32_t>> rows(GS_MAXC + 1);  // node ids per copy count
+    std::vector<int32_t> zero;
+    std::vector<std::vector<int32_t>> rows(GS_MAXC + 1);
     std::vector<int32_t> csr_nodes;
     int64_t n_masked = 0, n_rows = 0, n_entries = 0;
     for (int64_t G = 0; G < U; ++G) {
@@ -333,12 +333,18 @@ int nek_gs_create(int64_t E, int N, const int64_t *glo, const uint8_t *dirichlet
     }
     std::sort(zero.begin(), zero.end());
 
-    // one device arena: zero list | SoA groups | CSR offsets + entries | own bits
-    std::vector<int32_t> host;
-    struct Pending { int kind; int32_t rows; size_t idx_at; size_t off_at; };
-    std::vector<Pending> pend;
+    H = GsHost();
+    H.E = E;
+    H.N = N;
+    H.P = P;
+    H.U = U;
+    H.n_rows = n_rows;
+    H.n_entries = n_entries;
+    H.n_masked = n_masked;
+    H.n_zero = (int64_t)zero.size();
+    std::vector<int32_t> &host = H.idx;
     if (!zero.empty()) {
-        pend.push_back({0, (int32_t)zero.size(), host.size(), 0});
+        H.groups.push_back({0, (int32_t)zero.size(), host.size(), 0});
         host.insert(host.end(), zero.begin(), zero.end());
     }
     for (int c = 2; c <= GS_MAXC; ++c) {
@@ -349,7 +355,7 @@ int nek_gs_create(int64_t E, int N, const int64_t *glo, const uint8_t *dirichlet
         for (size_t rr = 0; rr < R.size(); ++rr)
             for (int m = 0; m < c; ++m)
                 host[at + (size_t)m * R.size() + rr] = copies[(size_t)start[(size_t)R[rr]] + m];
-        pend.push_back({c, (int32_t)R.size(), at, 0});
+        H.groups.push_back({c, (int32_t)R.size(), at, 0});
     }
     if (!csr_nodes.empty()) {
         const size_t off_at = host.size();
@@ -365,44 +371,32 @@ int nek_gs_create(int64_t E, int N, const int64_t *glo, const uint8_t *dirichlet
             }
         }
         host[off_at + csr_nodes.size()] = o;
-        pend.push_back({-1, (int32_t)csr_nodes.size(), idx_at, off_at});
+        H.groups.push_back({-1, (int32_t)csr_nodes.size(), idx_at, off_at});
     }
     const size_t words = (size_t)((P + 31) / 32);
-    std::vector<uint32_t> own(words, 0u);
+    H.own.assign(words, 0u);
     for (int64_t G = 0; G < U; ++G) {
         const int32_t L = copies[(size_t)start[(size_t)G]];
-        own[(size_t)L >> 5] |= 1u << (L & 31);
+        H.own[(size_t)L >> 5] |= 1u << (L & 31);
     }
+    return NEK_OK;
+}
 
-    nek_gs *h = new nek_gs();
-    GsDevice &d = h->d;
-    d.E = E;
-    d.N = N;
-    d.P = P;
-    d.n_unique = U;
-    d.n_rows = n_rows;
-    d.n_entries = n_entries;
-    d.n_masked = n_masked;
-    d.n_zero = (int64_t)zero.size();
-    const size_t idx_bytes = align256(host.size() * sizeof(int32_t) + 4);
-    const size_t bytes = idx_bytes + words * sizeof(uint32_t);
-    hipError_t e = hipMalloc(&d.arena, bytes);
-    if (e == hipSuccess && !host.empty())
-        e = hipMemcpy(d.arena, host.data(), host.size() * sizeof(int32_t), hipMemcpyHostToDevice);
-    d.own_bits = (uint32_t *)((char *)d.arena + idx_bytes);
-    if (e == hipSuccess) e = hipMemcpy(d.own_bits, own.data(), words * sizeof(uint32_t), hipMemcpyHostToDevice);
-    if (e == hipSuccess) e = hipMalloc((void **)&h->partials, RED_SITE_DOUBLES * sizeof(double));
-    if (e == hipSuccess) e = hipMalloc((void **)&h->ticket, RED_TICKETS * sizeof(unsigned int));
-    if (e == hipSuccess) e = hipMemset(h->ticket, 0, RED_TICKETS * sizeof(unsigned int));
-    if (e != hipSuccess) {
-        gs_free(h);
-        return fail(e == hipErrorOutOfMemory ? NEK_ERR_NOMEM : NEK_ERR_DEVICE,
-                    std::string("nek_gs_create: ") + hipGetErrorString(e));
-    }
-    const int32_t *base = (const int32_t *)d.arena;
+void gs_attach(const GsHost &H, void *arena, size_t own_offset, GsDevice &d) {
+    d.E = H.E;
+    d.N = H.N;
+    d.P = H.P;
+    d.n_unique = H.U;
+    d.n_rows = H.n_rows;
+    d.n_entries = H.n_entries;
+    d.n_masked = H.n_masked;
+    d.n_zero = H.n_zero;
+    d.arena = arena;
+    d.own_bits = (uint32_t *)((char *)arena + own_offset);
+    const int32_t *base = (const int32_t *)arena;
     d.args.ngroups = 0;
     int32_t blocks = 0;
-    for (const Pending &q : pend) {
+    for (const GsHostGroup &q : H.groups) {
         GsGroup &G = d.args.grp[d.args.ngroups++];
         G.kind = q.kind;
         G.rows = q.rows;
@@ -412,6 +406,41 @@ int nek_gs_create(int64_t E, int N, const int64_t *glo, const uint8_t *dirichlet
         blocks += (q.rows + GS_THREADS - 1) / GS_THREADS;
     }
     d.args.nblocks = blocks;
+}
+
+}  // namespace nek
+
+extern "C" {
+
+int nek_gs_create(int64_t E, int N, const int64_t *glo, const uint8_t *dirichlet, nek_gs **out) {
+    clear_error();
+    if (!out) return fail(NEK_ERR_ARG, "nek_gs_create: out is null");
+    *out = nullptr;
+    if (E < 1) return fail(NEK_ERR_ARG, "nek_gs_create: E must be >= 1");
+    if (N < 1 || N > NEK_MAX_DEGREE) return fail(NEK_ERR_UNSUPPORTED, "nek_gs_create: degree must be in 1..15");
+    if (!glo) return fail(NEK_ERR_ARG, "nek_gs_create: glo is null");
+    GsHost H;
+    std::string msg;
+    int rc = gs_build_host(E, N, glo, dirichlet, H, msg);
+    if (rc != NEK_OK) return fail(rc, "nek_gs_create: " + msg);
+    nek_gs *h = new nek_gs();
+    void *arena = nullptr;
+    hipError_t e = hipMalloc(&arena, H.arena_bytes());
+    if (e == hipSuccess && !H.idx.empty())
+        e = hipMemcpy(arena, H.idx.data(), H.idx.size() * sizeof(int32_t), hipMemcpyHostToDevice);
+    if (e == hipSuccess)
+        e = hipMemcpy((char *)arena + H.idx_bytes(), H.own.data(), H.own.size() * sizeof(uint32_t),
+                      hipMemcpyHostToDevice);
+    h->d.arena = arena;
+    if (e == hipSuccess) e = hipMalloc((void **)&h->partials, RED_SITE_DOUBLES * sizeof(double));
+    if (e == hipSuccess) e = hipMalloc((void **)&h->ticket, RED_TICKETS * sizeof(unsigned int));
+    if (e == hipSuccess) e = hipMemset(h->ticket, 0, RED_TICKETS * sizeof(unsigned int));
+    if (e != hipSuccess) {
+        gs_free(h);
+        return fail(e == hipErrorOutOfMemory ? NEK_ERR_NOMEM : NEK_ERR_DEVICE,
+                    std::string("nek_gs_create: ") + hipGetErrorString(e));
+    }
+    gs_attach(H, arena, H.idx_bytes(), h->d);
     *out = h;
     return NEK_OK;
 }
@@ -466,27 +495,6 @@ void nek_cg_default_opts(nek_cg_opts *o) {
     o->check_every = 0;
     o->true_residual = 0;
     o->reliable_drop = 0.0;
-}
-
-// Workspace layout: r, p, w | (p, A_L p) partials of ax | reduction sites |
-// their counters | CG scalars | one scratch double.
-enum { SITE_INIT, SITE_UPDATE, SITE_REPLACE, SITE_RESID, N_SITES };
-
-struct CgLayout {
-    size_t vec, axp, sites, tickets, scalars, scratch, total;
-};
-
-static CgLayout cg_layout(int64_t E, int N) {
-    const size_t P = (size_t)(E * n3_of(N));
-    CgLayout L;
-    L.vec = 0;
-    L.axp = 3 * align256(P * sizeof(double));
-    L.sites = L.axp + align256((size_t)ax_blocks(E, N) * sizeof(double));
-    L.tickets = L.sites + align256(N_SITES * RED_SITE_DOUBLES * sizeof(double));
-    L.scalars = L.tickets + align256(N_SITES * RED_TICKETS * sizeof(unsigned int));
-    L.scratch = L.scalars + align256(sizeof(CgScalars));
-    L.total = L.scratch + align256(sizeof(double));
-    return L;
 }
 
 size_t nek_cg_workspace_bytes(int64_t E, int N) {
@@ -556,20 +564,11 @@ int nek_cg_solve(int64_t E, int N, const double *D, const double *g, const nek_g
                         std::string("nek_cg_solve: workspace allocation: ") + hipGetErrorString(e));
         own_ws = true;
     }
-    const CgLayout lay = cg_layout(E, N);
-    const size_t vb = align256((size_t)P * sizeof(double));
-    double *r = (double *)ws;
-    double *p = (double *)(ws + vb);
-    double *w = (double *)(ws + 2 * vb);
-    double *axp = (double *)(ws + lay.axp);
-    double *site_mem = (double *)(ws + lay.sites);
-    unsigned int *tickets = (unsigned int *)(ws + lay.tickets);
-    CgScalars *sc = (CgScalars *)(ws + lay.scalars);
-    double *scratch1 = (double *)(ws + lay.scratch);   // one double
-    auto site = [&](int k, const double *extra, long nextra) {
-        double *base = site_mem + (size_t)k * RED_SITE_DOUBLES;
-        return RedSite{base, base + RED_MAX_BLOCKS, tickets + (size_t)k * RED_TICKETS, extra, nextra};
-    };
+    const CgWs W = cg_ws(ws, E, N);
+    double *r = W.r, *p = W.p, *w = W.w, *axp = W.axp, *scratch1 = W.scratch;
+    unsigned int *tickets = W.tickets;
+    CgScalars *sc = W.sc;
+    auto site = [&](int k, const double *extra, long nextra) { return W.site(k, extra, nextra); };
 
     if (!g_snap.buf) {
         hipError_t e = hipHostMalloc((void **)&g_snap.buf, 4 * sizeof(CgScalars), hipHostMallocDefault);

@@ -121,9 +121,9 @@ struct GLoad<float, uint16_t, N3> {
 // the workgroup) is live at a time, so it stays in scalar registers.  Five
 // workgroup barriers per element.
 template <int NX, typename T, typename GT, bool FUSE>
-__global__ void __launch_bounds__((AxShape<NX, T>::THREADS), (AxShape<NX, T>::MINW))
-ax_kernel(int64_t E, const T *__restrict__ D, const GT *__restrict__ g, double *__restrict__ p,
-          double *__restrict__ w, AxFuse fz)
+__device__ __forceinline__ void ax_body(int64_t blk, int64_t E, const T *__restrict__ D,
+                                        const GT *__restrict__ g, double *__restrict__ p,
+                                        double *__restrict__ w, const AxFuse &fz)
 {
     using S = AxShape<NX, T>;
     constexpr int NN = S::NN;
@@ -144,7 +144,7 @@ ax_kernel(int64_t E, const T *__restrict__ D, const GT *__restrict__ g, double *
     const int a = c % NX;
     const int b = c / NX;
     const bool in_slab = tid < EPB * NN;
-    const int64_t e = (int64_t)blockIdx.x * EPB + eb;
+    const int64_t e = blk * EPB + eb;
     const bool active = in_slab && e < E;
 
     T *B0 = lds + (in_slab ? eb : 0) * 3 * BUF;
@@ -311,9 +311,41 @@ ax_kernel(int64_t E, const T *__restrict__ D, const GT *__restrict__ g, double *
         if (fz.partials != nullptr) {
             __shared__ double red[S::THREADS / 64];
             const double bs = block_sum<S::THREADS>(pw, red);
-            if (threadIdx.x == 0) fz.partials[blockIdx.x] = bs;
+            if (threadIdx.x == 0) fz.partials[blk] = bs;
         }
     }
+}
+
+template <int NX, typename T, typename GT, bool FUSE>
+__global__ void __launch_bounds__((AxShape<NX, T>::THREADS), (AxShape<NX, T>::MINW))
+ax_kernel(int64_t E, const T *__restrict__ D, const GT *__restrict__ g, double *__restrict__ p,
+          double *__restrict__ w, AxFuse fz)
+{
+    ax_body<NX, T, GT, FUSE>(blockIdx.x, E, D, g, p, w, fz);
+}
+
+// Several CG solves of the same degree and precision in one launch: slot s
+// owns workgroups [slots[s].block0, slots[s+1].block0) and runs exactly the
+// workgroups its own launch would, so its arithmetic does not depend on
+// which other solves share the launch.
+template <int NX, typename T, typename GT>
+__global__ void __launch_bounds__((AxShape<NX, T>::THREADS), (AxShape<NX, T>::MINW))
+ax_batch_kernel(const AxSlot *__restrict__ slots, int nslots)
+{
+    int sidx = 0;
+    while (sidx + 1 < nslots && (int64_t)blockIdx.x >= slots[sidx + 1].block0) ++sidx;
+    const AxSlot &S = slots[sidx];
+    ax_body<NX, T, GT, true>((int64_t)blockIdx.x - S.block0, S.E, (const T *)S.D, (const GT *)S.g,
+                             S.p, S.w, S.fz);
+}
+
+template <int NX, typename T, typename GT>
+hipError_t launch_batch(const AxSlot *slots, int nslots, int64_t blocks, hipStream_t s)
+{
+    using S = AxShape<NX, T>;
+    hipLaunchKernelGGL((ax_batch_kernel<NX, T, GT>), dim3((unsigned)blocks), dim3(S::THREADS), 0, s,
+                       slots, nslots);
+    return hipGetLastError();
 }
 
 template <int NX, typename T, typename GT>
@@ -378,6 +410,23 @@ __global__ void convert_g_kernel(int64_t E, int64_t n3, const double *__restrict
 }
 
 }  // namespace
+
+hipError_t launch_ax_batch(int N, int precision, const AxSlot *slots, int nslots, int64_t blocks,
+                           hipStream_t s)
+{
+    switch (N + 1) {
+#define NEK_BCASE(NX)                                                                          \
+    case NX:                                                                                   \
+        if (precision == NEK_PREC_F64) return launch_batch<NX, double, double>(slots, nslots, blocks, s); \
+        if (precision == NEK_PREC_F32G32) return launch_batch<NX, float, float>(slots, nslots, blocks, s); \
+        return launch_batch<NX, float, uint16_t>(slots, nslots, blocks, s);
+        NEK_BCASE(2) NEK_BCASE(3) NEK_BCASE(4) NEK_BCASE(5) NEK_BCASE(6) NEK_BCASE(7) NEK_BCASE(8)
+        NEK_BCASE(9) NEK_BCASE(10) NEK_BCASE(11) NEK_BCASE(12) NEK_BCASE(13) NEK_BCASE(14)
+        NEK_BCASE(15) NEK_BCASE(16)
+#undef NEK_BCASE
+    default: return hipErrorInvalidValue;
+    }
+}
 
 hipError_t launch_ax_f64(int64_t E, int N, const double *D, const double *g, double *p, double *w,
                          const AxFuse &fz, hipStream_t s)

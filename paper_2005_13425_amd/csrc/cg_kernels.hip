@@ -63,21 +63,23 @@ __device__ __forceinline__ void gs_vblock(const GsArgs &a, int vb, double *__res
 
 constexpr int N_XCD = 8;   // gfx950: workgroups are dealt round-robin to 8 XCDs
 
-// XCD-aware work split: the workgroups that land on one XCD (blockIdx % 8)
-// walk one contiguous eighth of the virtual blocks, so the copies a row
-// touches and the rows next to it share that XCD's L2.  Workgroup 0 also
-// turns the (p, A_L p) partials of the preceding ax launch into alpha.
-__global__ void __launch_bounds__(GS_THREADS)
-gs_kernel(GsArgs a, double *__restrict__ w, const double *__restrict__ axparts, long nparts,
-          CgScalars *sc) {
+// XCD-aware work split: the workgroups that land on one XCD (index % 8) walk
+// one contiguous eighth of the virtual blocks, so the copies a row touches
+// and the rows next to it share that XCD's L2.  Local workgroup 0 also turns
+// the (p, A_L p) partials of the preceding ax launch into alpha.
+// lb / nb: local workgroup index and count (nb a multiple of 8).
+__device__ __forceinline__ void gs_body(int lb, int nb, const GsArgs &a, double *__restrict__ w,
+                                        const double *__restrict__ axparts, long nparts,
+                                        CgScalars *sc) {
     if (sc != nullptr && sc->done) return;
-    const int xcd = blockIdx.x % N_XCD;
-    const int per = gridDim.x / N_XCD;           // the grid is a multiple of N_XCD
-    const int lb = blockIdx.x / N_XCD;
-    const int v0 = (int)(((long)a.nblocks * xcd) / N_XCD);
-    const int v1 = (int)(((long)a.nblocks * (xcd + 1)) / N_XCD);
-    for (int vb = v0 + lb; vb < v1; vb += per) gs_vblock(a, vb, w);
-    if (sc == nullptr || blockIdx.x != 0) return;
+    const int xcd = lb % N_XCD;
+    const int per = nb / N_XCD;
+    const int lq = lb / N_XCD;
+    const int nvb = a.nblocks;
+    const int v0 = (int)(((long)nvb * xcd) / N_XCD);
+    const int v1 = (int)(((long)nvb * (xcd + 1)) / N_XCD);
+    for (int vb = v0 + lq; vb < v1; vb += per) gs_vblock(a, vb, w);
+    if (sc == nullptr || lb != 0) return;
     __shared__ double lds[GS_THREADS / 64];
     double v = 0.0;
     for (long q = threadIdx.x; q < nparts; q += GS_THREADS) v += axparts[q];
@@ -94,6 +96,22 @@ gs_kernel(GsArgs a, double *__restrict__ w, const double *__restrict__ axparts, 
             sc->lag_applied = 0;
         }
     }
+}
+
+__global__ void __launch_bounds__(GS_THREADS)
+gs_kernel(GsArgs a, double *__restrict__ w, const double *__restrict__ axparts, long nparts,
+          CgScalars *sc) {
+    gs_body(blockIdx.x, gridDim.x, a, w, axparts, nparts, sc);
+}
+
+__global__ void __launch_bounds__(GS_THREADS)
+gs_batch_kernel(const GsSlot *__restrict__ slots, int nslots) {
+    int sidx = 0;
+    while (sidx + 1 < nslots && (int64_t)blockIdx.x >= slots[sidx + 1].block0) ++sidx;
+    const GsSlot &S = slots[sidx];
+    const int lb = (int)((int64_t)blockIdx.x - S.block0);
+    if (lb >= S.nblocks) return;
+    gs_body(lb, (int)S.nblocks, S.args, S.w, S.axparts, (long)S.nparts, S.sc);
 }
 
 // ---------------------------------------------------------------- CG steps
@@ -188,15 +206,16 @@ cg_init_kernel(int64_t P, const double *__restrict__ b, double *__restrict__ x,
 }
 
 // r -= alpha w; rho' = (r, r); beta = rho' / rho; convergence and iteration cap
-__global__ void __launch_bounds__(VEC_THREADS)
-cg_update_kernel(int64_t P, double *__restrict__ r, const double *__restrict__ w,
-                 const uint32_t *__restrict__ own, RedSite red, CgScalars *sc) {
+__device__ __forceinline__ void update_body(int lb, int nb, int64_t P, double *__restrict__ r,
+                                            const double *__restrict__ w,
+                                            const uint32_t *__restrict__ own, const RedSite &red,
+                                            CgScalars *sc) {
     if (sc->done) return;
     __shared__ double lds[VEC_THREADS / 64];
     const double alpha = sc->alpha;
     const int64_t npairs = P >> 1;
     double acc = 0.0;
-    NEK_CHUNKS {
+    for (int64_t base = (int64_t)lb * VEC_CHUNK; base < npairs; base += (int64_t)nb * VEC_CHUNK) {
         double2 rv[VEC_PAIRS], wv[VEC_PAIRS];
 #pragma unroll
         for (int m = 0; m < VEC_PAIRS; ++m) {
@@ -220,7 +239,7 @@ cg_update_kernel(int64_t P, double *__restrict__ r, const double *__restrict__ w
             }
         }
     }
-    if (owns_tail(P)) {
+    if ((P & 1) && lb == nb - 1 && threadIdx.x == VEC_THREADS - 1) {
         const int64_t t = P - 1;
         const double nr = r[t] - alpha * w[t];
         r[t] = nr;
@@ -228,7 +247,7 @@ cg_update_kernel(int64_t P, double *__restrict__ r, const double *__restrict__ w
     }
     const double s = block_sum<VEC_THREADS>(acc, lds);
     double tot;
-    if (grid_finish<VEC_THREADS>(s, red, &tot, lds) && threadIdx.x == 0) {
+    if (grid_finish<VEC_THREADS>(s, red, &tot, lds, lb, nb) && threadIdx.x == 0) {
         sc->it += 1;
         if (!__builtin_isfinite(tot)) {
             sc->status = NEK_ERR_BREAKDOWN;
@@ -245,6 +264,26 @@ cg_update_kernel(int64_t P, double *__restrict__ r, const double *__restrict__ w
             if (sc->it >= sc->max_iter) sc->done = 1;
         }
     }
+}
+
+__global__ void __launch_bounds__(VEC_THREADS)
+cg_update_kernel(int64_t P, double *__restrict__ r, const double *__restrict__ w,
+                 const uint32_t *__restrict__ own, RedSite red, CgScalars *sc) {
+    update_body(blockIdx.x, gridDim.x, P, r, w, own, red, sc);
+}
+
+__global__ void __launch_bounds__(VEC_THREADS)
+update_batch_kernel(const UpdSlot *__restrict__ slots, int nslots) {
+    int sidx = 0;
+    while (sidx + 1 < nslots && (int64_t)blockIdx.x >= slots[sidx + 1].block0) ++sidx;
+    const UpdSlot &S = slots[sidx];
+    update_body((int)((int64_t)blockIdx.x - S.block0), (int)S.nblocks, S.P, S.r, S.w, S.own, S.red,
+                S.sc);
+}
+
+__global__ void gather_scalars_kernel(CgScalars *const *src, int n, CgScalars *dst) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) dst[i] = *src[i];
 }
 
 // x += alpha p when the last alpha has not reached x yet (end of a solve,
@@ -369,6 +408,23 @@ hipError_t launch_gs(const GsDevice &gs, double *w, const double *axparts, int64
     if (gs.args.nblocks == 0 && sc == nullptr) return hipSuccess;
     hipLaunchKernelGGL(gs_kernel, dim3((unsigned)gs_grid(gs)), dim3(GS_THREADS), 0, s, gs.args, w,
                        axparts, (long)nparts, sc);
+    return hipGetLastError();
+}
+
+hipError_t launch_gs_batch(const GsSlot *slots, int nslots, int64_t blocks, hipStream_t s) {
+    hipLaunchKernelGGL(gs_batch_kernel, dim3((unsigned)blocks), dim3(GS_THREADS), 0, s, slots, nslots);
+    return hipGetLastError();
+}
+
+hipError_t launch_update_batch(const UpdSlot *slots, int nslots, int64_t blocks, hipStream_t s) {
+    hipLaunchKernelGGL(update_batch_kernel, dim3((unsigned)blocks), dim3(VEC_THREADS), 0, s, slots,
+                       nslots);
+    return hipGetLastError();
+}
+
+hipError_t launch_gather_scalars(CgScalars *const *src, int n, CgScalars *dst, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(gather_scalars_kernel, dim3((n + 63) / 64), dim3(64), 0, s, src, n, dst);
     return hipGetLastError();
 }
 

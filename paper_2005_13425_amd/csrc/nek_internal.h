@@ -6,6 +6,7 @@
 #include <stdint.h>
 
 #include <string>
+#include <vector>
 
 #include "nek.h"
 #include "reduce.h"
@@ -70,6 +71,19 @@ hipError_t launch_ax_f32(int64_t E, int N, const float *D32, const void *g_lo, i
 // number of workgroups of an ax launch (one partial each)
 int64_t ax_blocks(int64_t E, int N);
 
+// One solve inside a launch that serves several (same degree and precision).
+struct AxSlot {
+    int64_t block0;      // first workgroup of this solve in the launch
+    int64_t E;
+    const void *D;       // double or float, by precision
+    const void *g;       // FP64 g, or the paired FP32 / BF16 copy
+    double *p;
+    double *w;
+    AxFuse fz;
+};
+hipError_t launch_ax_batch(int N, int precision, const AxSlot *slots, int nslots, int64_t blocks,
+                           hipStream_t s);
+
 hipError_t launch_convert_g(int64_t E, int N, const double *g, int g_dtype, void *out, hipStream_t s);
 
 // ---------------------------------------------------------------- gather-scatter
@@ -98,6 +112,35 @@ struct GsArgs {
     GsGroup grp[GS_MAXG];
 };
 
+// Host image of a gather-scatter map (built on the host, uploaded into one
+// device arena: the int32 index arrays, then the first-copy bits).
+struct GsHostGroup {
+    int kind;
+    int32_t rows;
+    size_t idx_at;   // offset of the group's indices in idx (int32 units)
+    size_t off_at;   // CSR offsets (kind -1)
+};
+struct GsHost {
+    int64_t E = 0;
+    int N = 0;
+    int64_t P = 0, U = 0, n_rows = 0, n_entries = 0, n_masked = 0, n_zero = 0;
+    std::vector<int32_t> idx;
+    std::vector<GsHostGroup> groups;
+    std::vector<uint32_t> own;
+    size_t idx_bytes() const { return ((idx.size() * sizeof(int32_t) + 4) + 255) & ~(size_t)255; }
+    size_t arena_bytes() const { return idx_bytes() + own.size() * sizeof(uint32_t); }
+};
+
+// Build the host image from glo[P] / dirichlet[P] (NULL = none); returns
+// NEK_OK or an error code with msg set.
+int gs_build_host(int64_t E, int N, const int64_t *glo, const uint8_t *dirichlet, GsHost &out,
+                  std::string &msg);
+
+struct GsDevice;
+// Point a device handle at an arena that holds (or will hold) h's image: the
+// index arrays at the start, the first-copy bits at own_offset.
+void gs_attach(const GsHost &h, void *arena, size_t own_offset, GsDevice &d);
+
 struct GsDevice {
     int64_t E = 0;
     int N = 0;
@@ -117,7 +160,18 @@ struct GsDevice {
 // sc->pw and sc->alpha (or flags a breakdown).
 hipError_t launch_gs(const GsDevice &gs, double *w, const double *axparts, int64_t nparts,
                      CgScalars *sc, hipStream_t s);
-int64_t gs_grid(const GsDevice &gs);
+int64_t gs_grid(const GsDevice &gs);   // a multiple of 8
+
+struct GsSlot {
+    int64_t block0;      // a multiple of 8, so a slot's workgroups keep their XCD order
+    int64_t nblocks;     // gs_grid of this solve
+    GsArgs args;
+    double *w;
+    const double *axparts;
+    int64_t nparts;
+    CgScalars *sc;
+};
+hipError_t launch_gs_batch(const GsSlot *slots, int nslots, int64_t blocks, hipStream_t s);
 
 // ---------------------------------------------------------------- CG vector steps
 constexpr int VEC_THREADS = 256;
@@ -130,6 +184,21 @@ hipError_t launch_cg_init(int64_t P, const double *b, double *x, double *r, doub
                           const uint32_t *own, const RedSite &red, CgScalars *sc, hipStream_t s);
 hipError_t launch_cg_update(int64_t P, double *r, const double *w, const uint32_t *own,
                             const RedSite &red, CgScalars *sc, hipStream_t s);
+
+struct UpdSlot {
+    int64_t block0;
+    int64_t nblocks;     // vec_blocks(P) of this solve
+    int64_t P;
+    double *r;
+    const double *w;
+    const uint32_t *own;
+    RedSite red;
+    CgScalars *sc;
+};
+hipError_t launch_update_batch(const UpdSlot *slots, int nslots, int64_t blocks, hipStream_t s);
+
+// copy the scalars of several solves into one contiguous array
+hipError_t launch_gather_scalars(CgScalars *const *src, int n, CgScalars *dst, hipStream_t s);
 hipError_t launch_cg_finish(int64_t P, double *x, const double *p, const CgScalars *sc, hipStream_t s);
 hipError_t launch_cg_replace(int64_t P, const double *b, const double *w, double *r,
                              const uint32_t *own, const RedSite &red, CgScalars *sc, hipStream_t s);
@@ -141,6 +210,56 @@ hipError_t launch_gdiff2(int64_t P, const double *a, const double *b, const uint
 
 // storage of one reduction site inside a workspace
 constexpr size_t RED_SITE_DOUBLES = RED_MAX_BLOCKS + RED_MAX_GROUPS;
+
+inline size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+// CG workspace: r, p, w | (p, A_L p) partials of ax | reduction sites |
+// their counters | CG scalars | one scratch double.
+enum { SITE_INIT, SITE_UPDATE, SITE_REPLACE, SITE_RESID, N_SITES };
+
+struct CgLayout {
+    size_t vec, axp, sites, tickets, scalars, scratch, total;
+};
+
+inline CgLayout cg_layout(int64_t E, int N) {
+    const size_t P = (size_t)(E * n3_of(N));
+    CgLayout L;
+    L.vec = 0;
+    L.axp = 3 * align256(P * sizeof(double));
+    L.sites = L.axp + align256((size_t)ax_blocks(E, N) * sizeof(double));
+    L.tickets = L.sites + align256(N_SITES * RED_SITE_DOUBLES * sizeof(double));
+    L.scalars = L.tickets + align256(N_SITES * RED_TICKETS * sizeof(unsigned int));
+    L.scratch = L.scalars + align256(sizeof(CgScalars));
+    L.total = L.scratch + align256(sizeof(double));
+    return L;
+}
+
+// Pointers into one CG workspace.
+struct CgWs {
+    double *r, *p, *w, *axp, *site_mem, *scratch;
+    unsigned int *tickets;
+    CgScalars *sc;
+    RedSite site(int k, const double *extra = nullptr, long nextra = 0) const {
+        double *base = site_mem + (size_t)k * RED_SITE_DOUBLES;
+        return RedSite{base, base + RED_MAX_BLOCKS, tickets + (size_t)k * RED_TICKETS, extra, nextra};
+    }
+};
+
+inline CgWs cg_ws(void *ws, int64_t E, int N) {
+    const CgLayout L = cg_layout(E, N);
+    char *c = (char *)ws;
+    const size_t vb = align256((size_t)(E * n3_of(N)) * sizeof(double));
+    CgWs W;
+    W.r = (double *)c;
+    W.p = (double *)(c + vb);
+    W.w = (double *)(c + 2 * vb);
+    W.axp = (double *)(c + L.axp);
+    W.site_mem = (double *)(c + L.sites);
+    W.tickets = (unsigned int *)(c + L.tickets);
+    W.sc = (CgScalars *)(c + L.scalars);
+    W.scratch = (double *)(c + L.scratch);
+    return W;
+}
 
 // ---------------------------------------------------------------- geometry
 // GLL nodes, weights and derivative matrix passed by value to kernels

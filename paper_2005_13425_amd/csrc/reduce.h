@@ -78,15 +78,19 @@ struct RedSite {
 // the device-coherent level) and each thread waits for its stores before it
 // takes a ticket; readers use agent-scope atomic loads.  No agent-scope fence
 // is used: on gfx950 such a fence writes back the whole L2 of the XCD.
+//
+// lb / nb: this workgroup's index and the number of workgroups taking part
+// (blockIdx.x / gridDim.x for a plain launch, the slot-local values in a
+// launch that serves several solves).
 template <int NT>
-__device__ bool grid_finish(double s, const RedSite &r, double *out, double *lds) {
+__device__ bool grid_finish(double s, const RedSite &r, double *out, double *lds, unsigned int lb,
+                            unsigned int nb) {
     __shared__ int stage;   // 0: not last, 1: last of its group, 2: last overall
-    const unsigned int nb = gridDim.x;
-    const unsigned int grp = blockIdx.x / RED_GROUP;
+    const unsigned int grp = lb / RED_GROUP;
     const unsigned int ngroups = (nb + RED_GROUP - 1) / RED_GROUP;
     const unsigned int gsize = (grp + 1 == ngroups) ? nb - grp * RED_GROUP : RED_GROUP;
     if (threadIdx.x == 0) {
-        store_coherent(&r.part[blockIdx.x], s);
+        store_coherent(&r.part[lb], s);
         const unsigned int t = take_ticket(&r.tk[1 + grp]);
         stage = (t == gsize - 1u) ? 1 : 0;
     }
@@ -116,6 +120,11 @@ __device__ bool grid_finish(double s, const RedSite &r, double *out, double *lds
         *out = e + u;
     }
     return true;
+}
+
+template <int NT>
+__device__ __forceinline__ bool grid_finish(double s, const RedSite &r, double *out, double *lds) {
+    return grid_finish<NT>(s, r, out, lds, blockIdx.x, gridDim.x);
 }
 
 }  // namespace nek

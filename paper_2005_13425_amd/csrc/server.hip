@@ -1,0 +1,689 @@
+// server.hip -- served Poisson solves: requests arrive over time, are admitted
+// when their whole device footprint fits the budget, keep their CG state
+// resident, and advance together: every step runs CG iterations of all
+// admitted solves with one operator, one gather-scatter and one update launch
+// per (degree, precision) group.  A solve's workgroups do exactly what its own
+// launch would do (per-solve reductions and tickets), so its result does not
+// depend on which other solves share the launches.
+#include <math.h>
+#include <string.h>
+
+#include <algorithm>
+#include <atomic>
+#include <chrono>
+#include <condition_variable>
+#include <deque>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <thread>
+#include <vector>
+
+#include "nek_internal.h"
+
+extern "C" int nek_box_numbering(int Ex, int Ey, int Ez, int N, int64_t *glo, uint8_t *dirichlet);
+
+namespace nek {
+namespace {
+
+constexpr int MAX_SLOTS = 64;
+
+bool is_mixed(int prec) { return prec == NEK_PREC_F32G32 || prec == NEK_PREC_F32GBF16; }
+
+// Device bytes of one admitted request (arena + solution vector).  The
+// gather-scatter part is bounded by one int32 per local point plus the
+// first-copy bits (every local point appears in at most one group).
+struct Footprint {
+    size_t g, b, gs, D, D32, glo, ws, arena, x, total;
+};
+
+Footprint footprint_of(int64_t E, int N, int prec) {
+    const size_t P = (size_t)(E * n3_of(N));
+    const size_t n2 = (size_t)(N + 1) * (N + 1);
+    Footprint f;
+    f.g = align256(6 * P * sizeof(double));
+    f.b = align256(P * sizeof(double));
+    f.gs = align256(P * sizeof(int32_t) + 4) + align256((P + 31) / 32 * sizeof(uint32_t));
+    f.D = align256(n2 * sizeof(double));
+    f.D32 = align256(n2 * sizeof(float));
+    f.glo = prec == NEK_PREC_F32G32 ? align256(6 * P * sizeof(float))
+          : prec == NEK_PREC_F32GBF16 ? align256(6 * P * sizeof(uint16_t)) : 0;
+    f.ws = cg_layout(E, N).total;
+    f.arena = f.g + f.b + f.gs + f.D + f.D32 + f.glo + f.ws;
+    f.x = align256(P * sizeof(double));
+    f.total = f.arena + f.x;
+    return f;
+}
+
+struct Request {
+    uint64_t id = 0;
+    nek_request spec{};
+    int64_t E = 0, P = 0;
+    Footprint fp{};
+    std::vector<double> b;        // copied at submit, dropped once staged
+    double t_submit = 0.0;
+    // filled by the preparation thread
+    std::atomic<bool> prepared{false};
+    int prep_status = NEK_OK;
+    std::string prep_msg;
+    GsHost gs;                    // group metadata; index arrays dropped once staged
+    void *staging = nullptr;      // pinned: b | gs idx | own bits | D | D32
+    size_t staging_bytes = 0;
+    size_t off_idx = 0, off_own = 0, off_D = 0, off_D32 = 0;
+};
+
+// Pinned host buffers, reused once their upload has completed.
+struct PinnedPool {
+    struct Buf {
+        void *p;
+        size_t n;
+        bool busy;
+    };
+    std::mutex mu;
+    std::vector<Buf> bufs;
+    void *get(size_t n) {
+        {
+            std::lock_guard<std::mutex> lk(mu);
+            size_t best = (size_t)-1;
+            for (size_t i = 0; i < bufs.size(); ++i)
+                if (!bufs[i].busy && bufs[i].n >= n && (best == (size_t)-1 || bufs[i].n < bufs[best].n)) best = i;
+            if (best != (size_t)-1) {
+                bufs[best].busy = true;
+                return bufs[best].p;
+            }
+        }
+        void *p = nullptr;
+        if (hipHostMalloc(&p, n, hipHostMallocDefault) != hipSuccess) return nullptr;
+        std::lock_guard<std::mutex> lk(mu);
+        bufs.push_back({p, n, true});
+        return p;
+    }
+    void put(void *p) {
+        std::lock_guard<std::mutex> lk(mu);
+        for (auto &b : bufs)
+            if (b.p == p) b.busy = false;
+    }
+    void release_all() {
+        std::lock_guard<std::mutex> lk(mu);
+        for (auto &b : bufs) (void)hipHostFree(b.p);
+        bufs.clear();
+    }
+};
+
+enum SlotState { ACTIVE, FINISHING, DONE };
+
+struct FinArea {        // pinned landing area of a finishing solve
+    CgScalars sc;
+    double t2;
+};
+
+struct Slot {
+    std::unique_ptr<Request> req;
+    int index = -1;               // 0..MAX_SLOTS-1, for the pinned finishing area
+    SlotState state = ACTIVE;
+    char *arena = nullptr;
+    double *x = nullptr;
+    double *g = nullptr, *b = nullptr, *D = nullptr;
+    float *D32 = nullptr;
+    void *glo = nullptr;
+    CgWs W{};
+    GsDevice gsd;
+    int replacements = 0;
+    double t_admit = 0.0, t_done = 0.0;
+    hipEvent_t ev_upload = nullptr;
+    hipEvent_t ev_fin = nullptr;
+    nek_result res{};
+};
+
+struct TableSet {       // slot tables of one step, host (pinned) and device
+    char *host = nullptr;
+    char *dev = nullptr;
+    hipEvent_t ev = nullptr;     // after the last work that read this set
+    bool used = false;
+};
+
+struct Group {
+    int N, precision;
+    int first, count;            // range in the slot tables
+    int64_t ax_blocks, gs_blocks, upd_blocks;
+};
+
+constexpr size_t TABLE_BYTES =
+    MAX_SLOTS * (sizeof(AxSlot) + sizeof(GsSlot) + sizeof(UpdSlot) + sizeof(CgScalars *));
+
+}  // namespace
+}  // namespace nek
+
+using namespace nek;
+
+struct nek_server {
+    size_t budget = 0;
+    size_t used = 0;
+    hipStream_t stream = nullptr;
+    hipStream_t copy_stream = nullptr;
+    std::chrono::steady_clock::time_point t0;
+    uint64_t next_id = 1;
+
+    // preparation thread
+    std::thread worker;
+    std::mutex mu;
+    std::condition_variable cv;
+    std::deque<Request *> prep_queue;
+    bool stop = false;
+    PinnedPool pinned;
+
+    std::deque<std::unique_ptr<Request>> waiting;     // arrival order
+    std::vector<std::unique_ptr<Slot>> slots;         // admitted (ACTIVE / FINISHING)
+    std::map<uint64_t, std::unique_ptr<Slot>> done;   // finished, solution not fetched
+    std::deque<nek_result> results;                   // finished, not reported
+    std::vector<int> free_index;
+
+    // tables
+    TableSet tables[2];
+    int cur_table = 0;
+    bool dirty = true;
+    std::vector<Group> groups;
+    std::vector<Slot *> table_slots;                  // slots of the current tables, in order
+    // status snapshots, one step behind
+    CgScalars *status_dev[2] = {nullptr, nullptr};
+    CgScalars *status_host[2] = {nullptr, nullptr};
+    hipEvent_t ev_status[2] = {nullptr, nullptr};
+    std::vector<Slot *> status_slots[2];
+    bool status_pending[2] = {false, false};
+    int status_parity = 0;
+    FinArea *fin = nullptr;                           // pinned, MAX_SLOTS
+
+    double clock() const {
+        return std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    }
+
+    // ------------------------------------------------------------ preparation
+    void prepare(Request *R) {
+        const nek_request &q = R->spec;
+        const int64_t P = R->P;
+        std::vector<int64_t> glo((size_t)P);
+        std::vector<uint8_t> dr((size_t)P);
+        nek_box_numbering(q.Ex, q.Ey, q.Ez, q.N, glo.data(), dr.data());
+        R->prep_status = gs_build_host(R->E, q.N, glo.data(), dr.data(), R->gs, R->prep_msg);
+        if (R->prep_status == NEK_OK) {
+            const int n = q.N + 1;
+            R->off_idx = align256(P * sizeof(double));
+            R->off_own = R->off_idx + align256(R->gs.idx.size() * sizeof(int32_t) + 4);
+            R->off_D = R->off_own + align256(R->gs.own.size() * sizeof(uint32_t));
+            R->off_D32 = R->off_D + align256((size_t)n * n * sizeof(double));
+            R->staging_bytes = R->off_D32 + align256((size_t)n * n * sizeof(float));
+            R->staging = pinned.get(R->staging_bytes);
+            if (!R->staging) {
+                R->prep_status = NEK_ERR_NOMEM;
+                R->prep_msg = "pinned staging allocation failed";
+            } else {
+                char *st = (char *)R->staging;
+                memcpy(st, R->b.data(), (size_t)P * sizeof(double));
+                if (!R->gs.idx.empty()) memcpy(st + R->off_idx, R->gs.idx.data(), R->gs.idx.size() * sizeof(int32_t));
+                memcpy(st + R->off_own, R->gs.own.data(), R->gs.own.size() * sizeof(uint32_t));
+                double D[(NEK_MAX_DEGREE + 1) * (NEK_MAX_DEGREE + 1)];
+                gll_host(q.N, nullptr, nullptr, D);
+                memcpy(st + R->off_D, D, (size_t)n * n * sizeof(double));
+                float *D32 = (float *)(st + R->off_D32);
+                for (int t = 0; t < n * n; ++t) D32[t] = (float)D[t];
+            }
+        }
+        // b is in the staging buffer now (the gather-scatter image is dropped at admission)
+        std::vector<double>().swap(R->b);
+        R->prepared.store(true, std::memory_order_release);
+    }
+
+    void worker_loop() {
+        for (;;) {
+            Request *R = nullptr;
+            {
+                std::unique_lock<std::mutex> lk(mu);
+                cv.wait(lk, [&] { return stop || !prep_queue.empty(); });
+                if (stop) return;
+                R = prep_queue.front();
+                prep_queue.pop_front();
+            }
+            prepare(R);
+        }
+    }
+
+    // ------------------------------------------------------------ admission
+    int admit_one(std::unique_ptr<Request> R) {
+        const nek_request &q = R->spec;
+        const Footprint &f = R->fp;
+        auto S = std::make_unique<Slot>();
+        S->index = free_index.back();
+        free_index.pop_back();
+        hipError_t e = hipMallocAsync((void **)&S->arena, f.arena, stream);
+        if (e == hipSuccess) e = hipMallocAsync((void **)&S->x, f.x, stream);
+        if (e != hipSuccess) return check_hip(e, "server admission: hipMallocAsync");
+        char *a = S->arena;
+        S->g = (double *)a;
+        a += f.g;
+        S->b = (double *)a;
+        a += f.b;
+        char *gs_arena = a;
+        a += f.gs;
+        S->D = (double *)a;
+        a += f.D;
+        S->D32 = (float *)a;
+        a += f.D32;
+        S->glo = f.glo ? (void *)a : nullptr;
+        a += f.glo;
+        S->W = cg_ws(a, R->E, q.N);
+        // uploads (pinned staging) and device setup, all on the server stream
+        const char *st = (const char *)R->staging;
+        NEK_HIP(hipMemcpyAsync(S->b, st, (size_t)R->P * sizeof(double), hipMemcpyHostToDevice, stream));
+        const size_t own_off = R->gs.idx_bytes();   // == off_own - off_idx
+        NEK_HIP(hipMemcpyAsync(gs_arena, st + R->off_idx, own_off, hipMemcpyHostToDevice, stream));
+        NEK_HIP(hipMemcpyAsync(gs_arena + own_off, st + R->off_own, R->gs.own.size() * sizeof(uint32_t),
+                               hipMemcpyHostToDevice, stream));
+        NEK_HIP(hipMemcpyAsync(S->D, st + R->off_D, R->off_D32 - R->off_D, hipMemcpyHostToDevice, stream));
+        NEK_HIP(hipMemcpyAsync(S->D32, st + R->off_D32, R->staging_bytes - R->off_D32, hipMemcpyHostToDevice, stream));
+        NEK_HIP(hipEventCreateWithFlags(&S->ev_upload, hipEventDisableTiming));
+        NEK_HIP(hipEventRecord(S->ev_upload, stream));
+        gs_attach(R->gs, gs_arena, own_off, S->gsd);
+        std::vector<int32_t>().swap(R->gs.idx);
+        std::vector<uint32_t>().swap(R->gs.own);
+        GllTable tab;
+        memset(&tab, 0, sizeof(tab));
+        gll_host(q.N, tab.z, tab.w, tab.D);
+        NEK_HIP(launch_box_geometry(q.Ex, q.Ey, q.Ez, q.N, q.amp, q.a[0], q.a[1], q.a[2], tab, S->g,
+                                    nullptr, nullptr, stream));
+        if (is_mixed(q.precision))
+            NEK_HIP(launch_convert_g(R->E, q.N, S->g,
+                                     q.precision == NEK_PREC_F32G32 ? NEK_G_F32 : NEK_G_BF16, S->glo, stream));
+        const double drop = is_mixed(q.precision) ? 0.1 : 0.0;
+        NEK_HIP(launch_cg_reset(S->W.sc, S->W.tickets, N_SITES * RED_TICKETS, q.max_iter, q.rel_tol, drop,
+                                stream));
+        NEK_HIP(launch_cg_init(R->P, S->b, S->x, S->W.r, S->W.p, S->gsd.own_bits, S->W.site(SITE_INIT),
+                               S->W.sc, stream));
+        used += f.total;
+        S->t_admit = clock();
+        S->res.id = R->id;
+        S->res.t_submit = R->t_submit;
+        S->res.t_admit = S->t_admit;
+        S->res.E = R->E;
+        S->res.N = q.N;
+        S->res.footprint = f.total;
+        S->req = std::move(R);
+        slots.push_back(std::move(S));
+        dirty = true;
+        return NEK_OK;
+    }
+
+    int admit() {
+        while (!waiting.empty()) {
+            Request *R = waiting.front().get();
+            if (!R->prepared.load(std::memory_order_acquire)) break;
+            if (R->prep_status != NEK_OK) {
+                // report the failure as a finished request
+                nek_result r{};
+                r.id = R->id;
+                r.status = R->prep_status;
+                r.t_submit = R->t_submit;
+                r.t_admit = r.t_done = clock();
+                r.E = R->E;
+                r.N = R->spec.N;
+                if (R->staging) pinned.put(R->staging);
+                results.push_back(r);
+                waiting.pop_front();
+                continue;
+            }
+            if (used + R->fp.total > budget || free_index.empty()) break;
+            std::unique_ptr<Request> own = std::move(waiting.front());
+            waiting.pop_front();
+            int rc = admit_one(std::move(own));
+            if (rc != NEK_OK) return rc;
+        }
+        return NEK_OK;
+    }
+
+    // ------------------------------------------------------------ tables
+    int rebuild_tables() {
+        const int k = cur_table ^ 1;
+        TableSet &T = tables[k];
+        if (T.used) NEK_HIP(hipEventSynchronize(T.ev));   // its last reader has finished
+        std::vector<Slot *> act;
+        for (auto &s : slots)
+            if (s->state == ACTIVE) act.push_back(s.get());
+        std::stable_sort(act.begin(), act.end(), [](const Slot *a, const Slot *b) {
+            if (a->req->spec.N != b->req->spec.N) return a->req->spec.N < b->req->spec.N;
+            return a->req->spec.precision < b->req->spec.precision;
+        });
+        AxSlot *ax = (AxSlot *)T.host;
+        GsSlot *gsl = (GsSlot *)(T.host + MAX_SLOTS * sizeof(AxSlot));
+        UpdSlot *up = (UpdSlot *)(T.host + MAX_SLOTS * (sizeof(AxSlot) + sizeof(GsSlot)));
+        CgScalars **scp = (CgScalars **)(T.host + MAX_SLOTS * (sizeof(AxSlot) + sizeof(GsSlot) + sizeof(UpdSlot)));
+        groups.clear();
+        for (size_t i = 0; i < act.size(); ++i) {
+            Slot *S = act[i];
+            const nek_request &q = S->req->spec;
+            if (groups.empty() || groups.back().N != q.N || groups.back().precision != q.precision)
+                groups.push_back({q.N, q.precision, (int)i, 0, 0, 0, 0});
+            Group &G = groups.back();
+            const bool mixed = is_mixed(q.precision);
+            AxSlot &A = ax[i];
+            A.block0 = G.ax_blocks;
+            A.E = S->req->E;
+            A.D = mixed ? (const void *)S->D32 : (const void *)S->D;
+            A.g = mixed ? (const void *)S->glo : (const void *)S->g;
+            A.p = S->W.p;
+            A.w = S->W.w;
+            A.fz.r = S->W.r;
+            A.fz.x = S->x;
+            A.fz.partials = S->W.axp;
+            A.fz.sc = S->W.sc;
+            G.ax_blocks += ax_blocks(S->req->E, q.N);
+            GsSlot &Gs = gsl[i];
+            Gs.block0 = G.gs_blocks;
+            Gs.nblocks = gs_grid(S->gsd);
+            Gs.args = S->gsd.args;
+            Gs.w = S->W.w;
+            Gs.axparts = S->W.axp;
+            Gs.nparts = ax_blocks(S->req->E, q.N);
+            Gs.sc = S->W.sc;
+            G.gs_blocks += Gs.nblocks;
+            UpdSlot &U = up[i];
+            U.block0 = G.upd_blocks;
+            U.nblocks = vec_blocks(S->req->P);
+            U.P = S->req->P;
+            U.r = S->W.r;
+            U.w = S->W.w;
+            U.own = S->gsd.own_bits;
+            U.red = S->W.site(SITE_UPDATE);
+            U.sc = S->W.sc;
+            G.upd_blocks += U.nblocks;
+            scp[i] = S->W.sc;
+            G.count++;
+        }
+        NEK_HIP(hipMemcpyAsync(T.dev, T.host, TABLE_BYTES, hipMemcpyHostToDevice, stream));
+        // the set in use until now may be rewritten once the work queued so far is done
+        if (tables[cur_table].used) NEK_HIP(hipEventRecord(tables[cur_table].ev, stream));
+        T.used = true;
+        cur_table = k;
+        table_slots = act;
+        dirty = false;
+        return NEK_OK;
+    }
+
+    // ------------------------------------------------------------ finishing
+    // A solve that leaves ACTIVE must not be seen by a pending snapshot: it may
+    // finish, be fetched and be freed before that snapshot is read.
+    void forget_in_snapshots(Slot *S) {
+        for (int k = 0; k < 2; ++k)
+            for (auto &p : status_slots[k])
+                if (p == S) p = nullptr;
+    }
+
+    int start_finish(Slot *S) {
+        forget_in_snapshots(S);
+        const nek_request &q = S->req->spec;
+        const int64_t E = S->req->E, P = S->req->P;
+        NEK_HIP(launch_cg_finish(P, S->x, S->W.p, S->W.sc, stream));
+        NEK_HIP(launch_ax_f64(E, q.N, S->D, S->g, S->x, S->W.w, AxFuse{}, stream));
+        NEK_HIP(launch_gs(S->gsd, S->W.w, nullptr, 0, nullptr, stream));
+        NEK_HIP(launch_gdiff2(P, S->b, S->W.w, S->gsd.own_bits, S->W.site(SITE_RESID), S->W.scratch, stream));
+        NEK_HIP(hipMemcpyAsync(&fin[S->index].sc, S->W.sc, sizeof(CgScalars), hipMemcpyDeviceToHost, stream));
+        NEK_HIP(hipMemcpyAsync(&fin[S->index].t2, S->W.scratch, sizeof(double), hipMemcpyDeviceToHost, stream));
+        NEK_HIP(hipEventCreateWithFlags(&S->ev_fin, hipEventDisableTiming));
+        NEK_HIP(hipEventRecord(S->ev_fin, stream));
+        S->state = FINISHING;
+        dirty = true;
+        return NEK_OK;
+    }
+
+    int replace_residual(Slot *S) {
+        const nek_request &q = S->req->spec;
+        const int64_t E = S->req->E, P = S->req->P;
+        NEK_HIP(launch_cg_finish(P, S->x, S->W.p, S->W.sc, stream));
+        NEK_HIP(launch_ax_f64(E, q.N, S->D, S->g, S->x, S->W.w, AxFuse{}, stream));
+        NEK_HIP(launch_gs(S->gsd, S->W.w, nullptr, 0, nullptr, stream));
+        NEK_HIP(launch_cg_replace(P, S->b, S->W.w, S->W.r, S->gsd.own_bits, S->W.site(SITE_REPLACE),
+                                  S->W.sc, stream));
+        S->replacements++;
+        return NEK_OK;
+    }
+
+    void check_finishing() {
+        for (size_t i = 0; i < slots.size();) {
+            Slot *S = slots[i].get();
+            bool moved = false;
+            if (S->ev_upload && hipEventQuery(S->ev_upload) == hipSuccess) {
+                (void)hipEventDestroy(S->ev_upload);
+                S->ev_upload = nullptr;
+                pinned.put(S->req->staging);
+                S->req->staging = nullptr;
+            }
+            if (S->state == FINISHING && !S->ev_upload && hipEventQuery(S->ev_fin) == hipSuccess) {
+                const nek_request &q = S->req->spec;
+                const CgScalars &sc = fin[S->index].sc;
+                const double bb = sc.bb;
+                nek_result &r = S->res;
+                r.iters = sc.it;
+                r.n_replacements = sc.n_replace;
+                r.rel_res = bb > 0.0 ? sqrt(sc.rho / bb) : 0.0;
+                r.rel_res_true = bb > 0.0 ? sqrt(fin[S->index].t2 / bb) : 0.0;
+                int status = sc.status;
+                if (status == NEK_OK && q.rel_tol > 0.0) {
+                    const double judged = is_mixed(q.precision) ? r.rel_res_true : r.rel_res;
+                    if (!(judged <= q.rel_tol)) status = NEK_ERR_NOCONV;
+                }
+                r.status = status;
+                r.t_done = clock();
+                (void)hipEventDestroy(S->ev_fin);
+                S->ev_fin = nullptr;
+                (void)hipFreeAsync(S->arena, stream);
+                S->arena = nullptr;
+                used -= S->req->fp.arena;
+                free_index.push_back(S->index);
+                S->index = -1;
+                S->state = DONE;
+                forget_in_snapshots(S);
+                results.push_back(r);
+                done[r.id] = std::move(slots[i]);
+                slots.erase(slots.begin() + (long)i);
+                moved = true;
+            }
+            if (!moved) ++i;
+        }
+    }
+
+    // ------------------------------------------------------------ one step
+    int step(int iters, int *active, int *queued) {
+        int rc = admit();
+        if (rc != NEK_OK) return rc;
+        if (dirty) {
+            rc = rebuild_tables();
+            if (rc != NEK_OK) return rc;
+        }
+        if (!table_slots.empty()) {
+            const TableSet &T = tables[cur_table];
+            const AxSlot *ax = (const AxSlot *)T.dev;
+            const GsSlot *gsl = (const GsSlot *)(T.dev + MAX_SLOTS * sizeof(AxSlot));
+            const UpdSlot *up = (const UpdSlot *)(T.dev + MAX_SLOTS * (sizeof(AxSlot) + sizeof(GsSlot)));
+            CgScalars *const *scp = (CgScalars *const *)(T.dev + MAX_SLOTS * (sizeof(AxSlot) + sizeof(GsSlot) + sizeof(UpdSlot)));
+            for (int it = 0; it < std::max(1, iters); ++it) {
+                for (const Group &G : groups) {
+                    NEK_HIP(launch_ax_batch(G.N, G.precision, ax + G.first, G.count, G.ax_blocks, stream));
+                    NEK_HIP(launch_gs_batch(gsl + G.first, G.count, G.gs_blocks, stream));
+                    NEK_HIP(launch_update_batch(up + G.first, G.count, G.upd_blocks, stream));
+                }
+            }
+            // snapshot of every active solve's scalars into buffer q; the snapshot
+            // of the previous step (buffer q ^ 1) is inspected below, after this
+            // step's work is queued, so the device stays busy while the host waits
+            const int q = status_parity;
+            NEK_HIP(launch_gather_scalars(scp, (int)table_slots.size(), status_dev[q], stream));
+            NEK_HIP(hipMemcpyAsync(status_host[q], status_dev[q], table_slots.size() * sizeof(CgScalars),
+                                   hipMemcpyDeviceToHost, stream));
+            NEK_HIP(hipEventRecord(ev_status[q], stream));
+            status_slots[q] = table_slots;
+            status_pending[q] = true;
+            status_parity ^= 1;
+        }
+        const int pq = status_parity;   // the buffer written one step before
+        if (status_pending[pq]) {
+            NEK_HIP(hipEventSynchronize(ev_status[pq]));
+            status_pending[pq] = false;
+            for (size_t i = 0; i < status_slots[pq].size(); ++i) {
+                Slot *S = status_slots[pq][i];
+                if (S == nullptr || S->state != ACTIVE) continue;
+                const CgScalars &v = status_host[pq][i];
+                if (v.done) {
+                    rc = start_finish(S);
+                    if (rc != NEK_OK) return rc;
+                } else if (is_mixed(S->req->spec.precision) && v.need_replace && v.n_replace >= S->replacements) {
+                    rc = replace_residual(S);
+                    if (rc != NEK_OK) return rc;
+                }
+            }
+        }
+        check_finishing();
+        if (active) {
+            int a = 0;
+            for (auto &s : slots)
+                if (s->state == ACTIVE) ++a;
+            *active = a;
+        }
+        if (queued) *queued = (int)waiting.size();
+        return NEK_OK;
+    }
+};
+
+extern "C" {
+
+size_t nek_server_footprint(int Ex, int Ey, int Ez, int N, int precision) {
+    if (Ex < 1 || Ey < 1 || Ez < 1 || N < 1 || N > NEK_MAX_DEGREE) return 0;
+    return footprint_of((int64_t)Ex * Ey * Ez, N, precision).total;
+}
+
+int nek_server_create(size_t hbm_budget, nek_server **out) {
+    clear_error();
+    if (!out) return fail(NEK_ERR_ARG, "nek_server_create: out is null");
+    *out = nullptr;
+    if (hbm_budget == 0) return fail(NEK_ERR_ARG, "nek_server_create: budget must be > 0");
+    std::unique_ptr<nek_server> S(new nek_server());
+    S->budget = hbm_budget;
+    S->t0 = std::chrono::steady_clock::now();
+    NEK_HIP(hipStreamCreate(&S->stream));
+    NEK_HIP(hipStreamCreateWithFlags(&S->copy_stream, hipStreamNonBlocking));
+    for (int k = 0; k < 2; ++k) {
+        NEK_HIP(hipHostMalloc((void **)&S->tables[k].host, TABLE_BYTES, hipHostMallocDefault));
+        NEK_HIP(hipMalloc((void **)&S->tables[k].dev, TABLE_BYTES));
+        NEK_HIP(hipEventCreateWithFlags(&S->tables[k].ev, hipEventDisableTiming));
+        NEK_HIP(hipMalloc((void **)&S->status_dev[k], MAX_SLOTS * sizeof(CgScalars)));
+        NEK_HIP(hipHostMalloc((void **)&S->status_host[k], MAX_SLOTS * sizeof(CgScalars), hipHostMallocDefault));
+        NEK_HIP(hipEventCreateWithFlags(&S->ev_status[k], hipEventDisableTiming));
+    }
+    NEK_HIP(hipHostMalloc((void **)&S->fin, MAX_SLOTS * sizeof(FinArea), hipHostMallocDefault));
+    for (int i = MAX_SLOTS - 1; i >= 0; --i) S->free_index.push_back(i);
+    nek_server *raw = S.get();
+    S->worker = std::thread([raw] { raw->worker_loop(); });
+    *out = S.release();
+    return NEK_OK;
+}
+
+int nek_server_submit(nek_server *srv, const nek_request *req, uint64_t *id) {
+    clear_error();
+    if (!srv || !req || !req->b) return fail(NEK_ERR_ARG, "nek_server_submit: null argument");
+    if (req->Ex < 1 || req->Ey < 1 || req->Ez < 1) return fail(NEK_ERR_ARG, "nek_server_submit: box sizes must be >= 1");
+    if (req->N < 1 || req->N > NEK_MAX_DEGREE) return fail(NEK_ERR_UNSUPPORTED, "nek_server_submit: degree must be in 1..15");
+    if (req->precision != NEK_PREC_F64 && !is_mixed(req->precision))
+        return fail(NEK_ERR_UNSUPPORTED, "nek_server_submit: unknown precision");
+    if (req->max_iter < 0) return fail(NEK_ERR_ARG, "nek_server_submit: max_iter must be >= 0");
+    const int64_t E = (int64_t)req->Ex * req->Ey * req->Ez;
+    const int64_t P = E * n3_of(req->N);
+    if (P >= ((int64_t)1 << 31)) return fail(NEK_ERR_ARG, "nek_server_submit: E*(N+1)^3 must be < 2^31");
+    auto R = std::make_unique<Request>();
+    R->id = srv->next_id++;
+    R->spec = *req;
+    R->spec.b = nullptr;
+    R->E = E;
+    R->P = P;
+    R->fp = footprint_of(E, req->N, req->precision);
+    if (R->fp.total > srv->budget)
+        return fail(NEK_ERR_NOMEM, "nek_server_submit: the request alone exceeds the budget");
+    R->b.assign(req->b, req->b + P);
+    R->t_submit = srv->clock();
+    if (id) *id = R->id;
+    {
+        std::lock_guard<std::mutex> lk(srv->mu);
+        srv->prep_queue.push_back(R.get());
+    }
+    srv->cv.notify_one();
+    srv->waiting.push_back(std::move(R));
+    return NEK_OK;
+}
+
+int nek_server_step(nek_server *srv, int iters, int *active, int *queued) {
+    clear_error();
+    if (!srv) return fail(NEK_ERR_ARG, "nek_server_step: null server");
+    return srv->step(iters, active, queued);
+}
+
+int nek_server_poll(nek_server *srv, nek_result *out, int max, int *n) {
+    clear_error();
+    if (!srv || !n || (max > 0 && !out)) return fail(NEK_ERR_ARG, "nek_server_poll: null argument");
+    int k = 0;
+    while (k < max && !srv->results.empty()) {
+        out[k++] = srv->results.front();
+        srv->results.pop_front();
+    }
+    *n = k;
+    return NEK_OK;
+}
+
+int nek_server_fetch(nek_server *srv, uint64_t id, double *x_host) {
+    clear_error();
+    if (!srv || !x_host) return fail(NEK_ERR_ARG, "nek_server_fetch: null argument");
+    auto it = srv->done.find(id);
+    if (it == srv->done.end()) return fail(NEK_ERR_STATE, "nek_server_fetch: no finished solve with this id");
+    Slot *S = it->second.get();
+    NEK_HIP(hipMemcpyAsync(x_host, S->x, (size_t)S->req->P * sizeof(double), hipMemcpyDeviceToHost,
+                           srv->copy_stream));
+    NEK_HIP(hipStreamSynchronize(srv->copy_stream));
+    (void)hipFreeAsync(S->x, srv->stream);
+    srv->used -= S->req->fp.x;
+    srv->done.erase(it);
+    return NEK_OK;
+}
+
+double nek_server_clock(const nek_server *srv) { return srv ? srv->clock() : 0.0; }
+
+int nek_server_destroy(nek_server *srv) {
+    clear_error();
+    if (!srv) return NEK_OK;
+    {
+        std::lock_guard<std::mutex> lk(srv->mu);
+        srv->stop = true;
+    }
+    srv->cv.notify_all();
+    if (srv->worker.joinable()) srv->worker.join();
+    hipError_t e = hipStreamSynchronize(srv->stream);
+    for (auto &s : srv->slots) {
+        if (s->arena) (void)hipFree(s->arena);
+        if (s->x) (void)hipFree(s->x);
+        if (s->ev_upload) (void)hipEventDestroy(s->ev_upload);
+        if (s->ev_fin) (void)hipEventDestroy(s->ev_fin);
+    }
+    for (auto &kv : srv->done)
+        if (kv.second->x) (void)hipFree(kv.second->x);
+    for (int k = 0; k < 2; ++k) {
+        (void)hipHostFree(srv->tables[k].host);
+        (void)hipFree(srv->tables[k].dev);
+        (void)hipEventDestroy(srv->tables[k].ev);
+        (void)hipFree(srv->status_dev[k]);
+        (void)hipHostFree(srv->status_host[k]);
+        (void)hipEventDestroy(srv->ev_status[k]);
+    }
+    (void)hipHostFree(srv->fin);
+    srv->pinned.release_all();
+    (void)hipStreamDestroy(srv->copy_stream);
+    (void)hipStreamDestroy(srv->stream);
+    delete srv;
+    if (e != hipSuccess) return check_hip(e, "nek_server_destroy: hipStreamSynchronize");
+    return NEK_OK;
+}
+
+}  // extern "C"

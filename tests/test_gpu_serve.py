@@ -1,0 +1,145 @@
+"""Served solves: admission by device footprint, resident CG state, shared
+launches over all admitted solves (nek_server_*), against the oracle and
+against the same request served alone.
+
+* a served FP64 solve equals nek_cg_solve of the same system to 1e-12 and the
+  oracle's converged solution to 1e-9;
+* a request's solution is bitwise the same alone and in a mix with requests
+  of other sizes, degrees and precisions that arrive while it runs (every
+  solve's workgroups, reductions and tickets are its own);
+* with a budget that holds one request, the second waits for the first;
+  with room for both, they are admitted and run at the same time.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def nek():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2005_13425_amd as nek
+    return nek
+
+
+def _rhs(nek, box, N, seed):
+    glo, dr = nek.box_numbering(*box, N)
+    vals = synth.lattice_uniform(*box, N, seed=seed)
+    b = vals[glo]
+    b[dr == 1] = 0.0
+    return b
+
+
+GB = 1 << 30
+
+
+def test_served_solve_matches_cg_and_oracle(nek):
+    box, N = (4, 4, 4), 7
+    a = synth.geom_coeffs()
+    b = _rhs(nek, box, N, 5)
+    srv = nek.Server(4 * GB)
+    rid = srv.submit(*box, N, b, amp=synth.AMP, a=a, rel_tol=1e-10)
+    res = srv.run_until_done([rid])[rid]
+    x = srv.fetch(rid)
+    srv.close()
+    assert res["status"] == 0 and res["rel_res"] <= 1e-10 and res["rel_res_true"] <= 1e-9
+    # the same system through nek_cg_solve with the library's own setup
+    g, _, _ = nek.box_geometry(*box, N, synth.AMP, a)
+    _, _, D = nek.gll(N)
+    glo, dr = nek.box_numbering(*box, N)
+    gs = nek.GatherScatter(64, N, glo, dr)
+    xs, rs = nek.cg_solve(torch.from_numpy(D).cuda(), g, gs, torch.from_numpy(b).cuda(),
+                          max_iter=10000, rel_tol=1e-10)
+    assert rs.iters == res["iters"]
+    xs = xs.cpu().numpy()
+    assert np.linalg.norm(x - xs) / np.linalg.norm(xs) <= 1e-12
+    # the oracle's converged solution on its own setup
+    m = oracle.box_mesh(*box, N, synth.AMP, a)
+    ref = oracle.cg(m, oracle.lattice_to_local(m, synth.lattice_uniform(*box, N, seed=5)),
+                    max_iter=5000, rel_tol=1e-13)
+    assert np.linalg.norm(x - ref.x) / np.linalg.norm(ref.x) <= 1e-8
+    gs.close()
+
+
+def _serve(nek, reqs, budget=8 * GB, stagger=0):
+    """reqs: list of (box, N, precision, seed); request k is submitted after
+    k*stagger steps.  Returns ({k: x}, {k: result}, server clock trace)."""
+    srv = nek.Server(budget)
+    ids, xs, res = {}, {}, {}
+    a = synth.geom_coeffs()
+    pending = list(enumerate(reqs))
+    steps = 0
+    trace = []
+    while pending or len(res) < len(reqs):
+        while pending and pending[0][0] * stagger <= steps:
+            k, (box, N, prec, seed) = pending.pop(0)
+            ids[srv.submit(*box, N, _rhs(nek, box, N, seed), amp=synth.AMP, a=a, precision=prec,
+                           rel_tol=1e-10, max_iter=20000)] = k
+        act, que = srv.step(1)
+        trace.append((steps, act, que))
+        steps += 1
+        for r in srv.poll():
+            k = ids[r["id"]]
+            res[k] = r
+            xs[k] = srv.fetch(r["id"])
+        assert steps < 200000
+    srv.close()
+    return xs, res, trace
+
+
+def test_alone_equals_in_the_mix_bitwise(nek):
+    A = ((4, 4, 4), 7, nek.NEK_PREC_F64, 1)
+    B = ((3, 3, 2), 5, nek.NEK_PREC_F32G32, 2)
+    C = ((2, 2, 4), 9, nek.NEK_PREC_F64, 3)
+    Dq = ((4, 2, 2), 7, nek.NEK_PREC_F32GBF16, 4)
+    xa, ra, _ = _serve(nek, [A])
+    xb, rb, _ = _serve(nek, [B])
+    xm, rm, trace = _serve(nek, [A, C, B, Dq], stagger=7)
+    assert max(t[1] for t in trace) >= 2            # solves ran side by side
+    np.testing.assert_array_equal(xm[0], xa[0])
+    np.testing.assert_array_equal(xm[2], xb[0])
+    assert rm[0]["iters"] == ra[0]["iters"] and rm[2]["iters"] == rb[0]["iters"]
+    for k in rm:
+        assert rm[k]["status"] == 0, rm[k]
+        assert rm[k]["rel_res_true"] <= 1e-9
+    assert rm[2]["n_replacements"] >= 1 and rm[3]["n_replacements"] >= 1
+
+
+def test_admission_by_footprint(nek):
+    box, N = (4, 4, 4), 7
+    f = nek.server_footprint(*box, N)
+    assert f > 0
+    # room for one request: the second waits until the first has finished
+    xs, res, trace = _serve(nek, [(box, N, nek.NEK_PREC_F64, 1), (box, N, nek.NEK_PREC_F64, 2)],
+                            budget=int(1.5 * f))
+    assert max(t[1] for t in trace) == 1
+    assert any(t[2] >= 1 for t in trace)
+    assert res[1]["t_admit"] >= res[0]["t_done"] - 1e-9
+    # room for both: admitted together, their lifetimes overlap
+    xs2, res2, trace2 = _serve(nek, [(box, N, nek.NEK_PREC_F64, 1), (box, N, nek.NEK_PREC_F64, 2)],
+                               budget=int(2.5 * f))
+    assert max(t[1] for t in trace2) == 2
+    assert res2[1]["t_admit"] < res2[0]["t_done"]
+    np.testing.assert_array_equal(xs[0], xs2[0])
+    np.testing.assert_array_equal(xs[1], xs2[1])
+
+
+def test_server_errors(nek):
+    srv = nek.Server(1 << 20)
+    b = np.zeros(8 ** 3 * 64)
+    with pytest.raises(nek.NekError) as ei:
+        srv.submit(4, 4, 4, 7, b)
+    assert ei.value.code == nek.NEK_ERR_NOMEM
+    with pytest.raises(nek.NekError) as ei:
+        srv.submit(1, 1, 1, 16, np.zeros(17 ** 3))
+    assert ei.value.code == nek.NEK_ERR_UNSUPPORTED
+    with pytest.raises(nek.NekError):
+        srv.fetch(12345) if 12345 in srv._sizes else nek._check(
+            nek._lib.nek_server_fetch(srv._h, nek.ctypes.c_uint64(12345), b.ctypes.data), "fetch")
+    srv.close()
