@@ -13,6 +13,13 @@ uniform in [-1, 1] per global node, zero Dirichlet boundary.
   events on its own stream (back-to-back launches, rotating over buffer sets
   larger than the 256 MB last-level cache) and reported against the HBM
   roofline with its algorithmic bytes (u + 6 g + w = 64 B per point in FP64).
+* mixed: time to a true relative residual of 1e-10 on a manufactured
+  solution, FP64 CG against the FP32 operator (g in FP32 / BF16) inside FP64
+  reliable-update CG.
+* serve: a seeded stream of box-mesh solves of mixed sizes and degrees
+  (to 1e-10) through the served form, against the same solves one after
+  another with nek_cg_solve: capacity (solves/s) and p50/p99 latency under
+  Poisson arrivals, FP64 and mixed.
 * cpu_baseline: the FP64 oracle timed on this host on a bounded sample.
 
 Prints ONE JSON line.
@@ -44,6 +51,10 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-mixed", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--serve-requests", type=int, default=24)
+    ap.add_argument("--serve-budget-gb", type=float, default=64.0)
+    ap.add_argument("--serve-iters-per-step", type=int, default=4)
     return ap.parse_args()
 
 
@@ -198,6 +209,9 @@ def main():
 
     if not args.no_mixed:
         out["mixed"] = mixed_leg(nek, torch, dev, Ex, Ey, Ez, N, D, g, gs, ws)
+    if not args.no_serve:
+        out["serve"] = serve_leg(nek, torch, args.serve_requests, args.serve_budget_gb,
+                                 args.serve_iters_per_step)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(Ex, Ey, Ez, N, args.cpu_seconds)
     gs.close()
@@ -246,6 +260,121 @@ def mixed_leg(nek, torch, dev, Ex, Ey, Ez, N, D, g, gs, ws, tol=1e-10):
     res["workload"] = (f"manufactured sin solution, E={E} ({Ex}x{Ey}x{Ez}) N={N}, stop at true "
                        f"||b-Ax||/||b|| <= {tol}; FP64 residual/dots/axpy, reliable updates")
     return res
+
+
+def serve_leg(nek, torch, n_req, budget_gb, iters_per_step, tol=1e-10, max_iter=10000):
+    """Served solves.  Requests: box meshes with E uniform over {64, 512, 1024,
+    4096, 8192} and N over {5, 7, 9, 11}, perturbed geometry and rhs U[-1, 1]
+    per node with their own seeds, solved to ||r||/||b|| <= 1e-10.
+
+    1. plain FP64 CG: the requests solved one after another with nek_cg_solve
+       (their setup untimed) -- the reference throughput;
+    2. served, all requests arriving at once: the server's capacity (solves/s);
+    3. served under seeded Poisson arrivals at 0.5 and 0.9 of that capacity:
+       latency from submission to the step that saw the solve finish
+       (p50 / p99; with a few dozen requests p99 is close to the maximum).
+    2 and 3 run in FP64 and in the mixed form (FP32 operator, FP32 g)."""
+    import numpy as np
+    import synth
+
+    trace = synth.arrival_trace(n_req, rate=1.0)
+    reqs = []
+    for t in trace:
+        box = synth.box_for(t["E"])
+        glo, dr = nek.box_numbering(*box, t["N"])
+        b = synth.lattice_uniform(*box, t["N"], seed=t["rhs_seed"])[glo]
+        b[dr == 1] = 0.0
+        reqs.append({"box": box, "E": t["E"], "N": t["N"], "b": b, "t": t["t"],
+                     "a": synth.geom_coeffs(t["geom_seed"])})
+        del glo, dr
+
+    # 1. one after another with nek_cg_solve
+    seq_s, seq_iters = 0.0, []
+    for r in reqs:
+        E, N = r["E"], r["N"]
+        g, _, _ = nek.box_geometry(*r["box"], N, synth.AMP, r["a"])
+        D = torch.from_numpy(nek.gll(N)[2]).cuda()
+        glo, dr = nek.box_numbering(*r["box"], N)
+        gs = nek.GatherScatter(E, N, glo, dr)
+        b = torch.from_numpy(r["b"]).cuda()
+        x = torch.empty_like(b)
+        ws = nek.cg_workspace(E, N)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        _, res = nek.cg_solve(D, g, gs, b, x, max_iter=max_iter, rel_tol=tol, workspace=ws)
+        torch.cuda.synchronize()
+        seq_s += time.perf_counter() - t0
+        seq_iters.append(res.iters)
+        gs.close()
+        del g, D, b, x, ws
+    torch.cuda.empty_cache()
+    out = {
+        "workload": (f"{n_req} requests, E uniform over (64, 512, 1024, 4096, 8192) as boxes, N over "
+                     f"(5, 7, 9, 11), perturbed geometry and rhs U[-1,1] per node (own seeds), "
+                     f"stop at rel residual {tol}; Poisson arrivals (seeded)"),
+        "budget_gb": budget_gb, "iters_per_step": iters_per_step,
+        "requests": [[r["E"], r["N"]] for r in reqs],
+        "sequential_fp64": {"solves_per_s": round(n_req / seq_s, 3), "total_s": round(seq_s, 3),
+                            "iters": seq_iters},
+    }
+    budget = int(budget_gb * (1 << 30))
+    for name, prec in (("fp64", nek.NEK_PREC_F64), ("f32_g32", nek.NEK_PREC_F32G32)):
+        sat = _serve_run(nek, reqs, [0.0] * n_req, prec, budget, iters_per_step, tol, max_iter)
+        cap = sat["solves_per_s"]
+        leg = {"saturated": sat, "speedup_vs_sequential_fp64": round(cap * seq_s / n_req, 3)}
+        if prec == nek.NEK_PREC_F64:
+            leg["iters_equal_to_sequential"] = sat.pop("iters") == seq_iters
+        else:
+            sat.pop("iters")
+        pois = []
+        for frac in (0.5, 0.9):
+            rate = frac * cap
+            run = _serve_run(nek, reqs, [r["t"] / rate for r in reqs], prec, budget, iters_per_step,
+                             tol, max_iter)
+            run.pop("iters")
+            run["offered_rate"] = round(rate, 3)
+            pois.append(run)
+        leg["poisson"] = pois
+        out[name] = leg
+    return out
+
+
+def _serve_run(nek, reqs, times, precision, budget, iters_per_step, tol, max_iter):
+    """Submit request k at times[k] seconds on the server clock, step the
+    server until every request has finished, fetch each solution as it
+    finishes.  Returns latency / throughput figures."""
+    import numpy as np
+    import synth
+    n = len(reqs)
+    srv = nek.Server(budget)
+    ids, got = {}, {}
+    k = 0
+    t0 = srv.clock()
+    while len(got) < n:
+        now = srv.clock() - t0
+        while k < n and times[k] <= now:
+            r = reqs[k]
+            ids[srv.submit(*r["box"], r["N"], r["b"], amp=synth.AMP, a=r["a"], precision=precision,
+                           rel_tol=tol, max_iter=max_iter)] = k
+            k += 1
+        act, que = srv.step(iters_per_step)
+        for q in srv.poll():
+            got[ids[q["id"]]] = q
+            srv.fetch(q["id"])
+        if act == 0 and que == 0 and k < n and len(got) == k:
+            time.sleep(max(0.0, min(1e-3, times[k] - (srv.clock() - t0))))
+    srv.close()
+    res = [got[i] for i in range(n)]
+    lat = np.array([q["t_done"] - q["t_submit"] for q in res])
+    wait = np.array([q["t_admit"] - q["t_submit"] for q in res])
+    span = max(q["t_done"] for q in res) - min(q["t_submit"] for q in res)
+    return {"solves_per_s": round(n / span, 3), "makespan_s": round(span, 3),
+            "p50_ms": round(1e3 * float(np.percentile(lat, 50)), 2),
+            "p99_ms": round(1e3 * float(np.percentile(lat, 99)), 2),
+            "mean_admission_wait_ms": round(1e3 * float(wait.mean()), 2),
+            "all_ok": all(q["status"] == 0 for q in res),
+            "max_rel_res_true": max(q["rel_res_true"] for q in res),
+            "iters": [q["iters"] for q in res]}
 
 
 def synth_amp():

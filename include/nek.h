@@ -228,7 +228,10 @@ typedef struct {
     double amp;          /* displacement amplitude */
     double a[3];         /* displacement coefficients */
     const double *b;     /* host, P doubles, local layout, continuous and zero on
-                            the box faces; copied by nek_server_submit */
+                            the box faces.  Read by a preparation thread after
+                            nek_server_submit returns: it must stay valid and
+                            unchanged until nek_server_poll has reported the
+                            request or nek_server_destroy has returned */
     int precision;       /* NEK_PREC_* */
     double rel_tol;      /* stop at ||r||/||b|| <= rel_tol (true residual in the
                             mixed precisions); <= 0: run max_iter iterations */
@@ -251,18 +254,22 @@ typedef struct {
 } nek_result;
 
 /* Create a server on the current device with a device-memory budget in
- * bytes.  Starts one host thread that prepares submitted requests (their
- * numbering and gather-scatter tables).  Synchronous. */
+ * bytes.  Starts four host threads that prepare submitted requests (their
+ * numbering and gather-scatter tables) independently of one another;
+ * admission still follows arrival order.  Synchronous. */
 int nek_server_create(size_t hbm_budget, nek_server **out);
 
 /* Queue a request; *id receives its id.  NEK_ERR_NOMEM if its footprint can
- * never fit the budget.  Copies req->b.  Returns at once. */
+ * never fit the budget.  Copies *req but not the rhs req->b (see
+ * nek_request.b).  Returns at once. */
 int nek_server_submit(nek_server *srv, const nek_request *req, uint64_t *id);
 
 /* Footprint in device bytes of a request (what admission charges). */
 size_t nek_server_footprint(int Ex, int Ey, int Ez, int N, int precision);
 
-/* One step: admit prepared requests in arrival order while they fit, run
+/* One step: admit prepared requests in arrival order while they fit (a
+ * request still being prepared does not hold back prepared ones behind it; a
+ * prepared one that does not fit holds back all later ones), run
  * `iters` CG iterations of every admitted solve, and retire solves whose
  * completion the step observed.  active / queued (may be NULL) receive the
  * number of admitted and waiting requests after the step.  Returns after
@@ -281,7 +288,7 @@ int nek_server_fetch(nek_server *srv, uint64_t id, double *x_host);
 /* Seconds on the server clock (the time base of nek_result). */
 double nek_server_clock(const nek_server *srv);
 
-/* Stop the preparation thread, wait for the device, free everything.
+/* Stop the preparation threads, wait for the device, free everything.
  * NULL is accepted. */
 int nek_server_destroy(nek_server *srv);
 

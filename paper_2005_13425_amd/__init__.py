@@ -381,9 +381,13 @@ class Server:
         _check(_lib.nek_server_create(int(hbm_budget), ctypes.byref(h)), "nek_server_create")
         self._h = h
         self._sizes = {}
+        self._rhs = {}
 
     def submit(self, Ex, Ey, Ez, N, b, amp=0.0, a=(0.0, 0.0, 0.0), precision=NEK_PREC_F64,
                rel_tol=1e-10, max_iter=10000) -> int:
+        """Queue one solve; returns its id.  b is not copied: the server reads
+        it after this returns, so it must not be modified until poll() has
+        reported the request (the binding keeps it alive until then)."""
         P = Ex * Ey * Ez * (N + 1) ** 3
         b = _host_np(b, np.float64, "b", P)
         r = Request(Ex, Ey, Ez, N, float(amp), (ctypes.c_double * 3)(*a), b.ctypes.data,
@@ -391,6 +395,7 @@ class Server:
         rid = ctypes.c_uint64()
         _check(_lib.nek_server_submit(self._h, ctypes.byref(r), ctypes.byref(rid)), "nek_server_submit")
         self._sizes[rid.value] = P
+        self._rhs[rid.value] = b          # read by the server until the result is reported
         return rid.value
 
     def step(self, iters: int = 1):
@@ -403,7 +408,10 @@ class Server:
         buf = (Result * max_results)()
         n = _ci()
         _check(_lib.nek_server_poll(self._h, buf, max_results, ctypes.byref(n)), "nek_server_poll")
-        return [{f: getattr(buf[i], f) for f, _ in Result._fields_} for i in range(n.value)]
+        out = [{f: getattr(buf[i], f) for f, _ in Result._fields_} for i in range(n.value)]
+        for r in out:
+            self._rhs.pop(r["id"], None)
+        return out
 
     def fetch(self, rid: int):
         x = np.empty(self._sizes[rid])
@@ -428,6 +436,7 @@ class Server:
         if getattr(self, "_h", None):
             _lib.nek_server_destroy(self._h)
             self._h = None
+            self._rhs = {}
 
     def __del__(self):
         try:

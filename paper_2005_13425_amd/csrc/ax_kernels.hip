@@ -68,7 +68,7 @@ struct GLoad;
 
 template <int N3>
 struct GLoad<double, double, N3> {
-    __device__ static __forceinline__ void load(const double *ge, int off, double *o) {
+    __device__ static __forceinline__ void load(gptr<const double> ge, int off, double *o) {
 #pragma unroll
         for (int q = 0; q < 6; ++q) o[q] = ge[q * N3 + off];
     }
@@ -76,8 +76,8 @@ struct GLoad<double, double, N3> {
 
 template <int N3>
 struct GLoad<float, float, N3> {
-    __device__ static __forceinline__ void load(const float *ge, int off, float *o) {
-        const float2 *pp = (const float2 *)ge;
+    __device__ static __forceinline__ void load(gptr<const float> ge, int off, float *o) {
+        const gptr<const float2> pp = (gptr<const float2>)ge;
 #pragma unroll
         for (int q = 0; q < 3; ++q) {
             const float2 v = pp[q * N3 + off];
@@ -89,8 +89,8 @@ struct GLoad<float, float, N3> {
 
 template <int N3>
 struct GLoad<float, uint16_t, N3> {
-    __device__ static __forceinline__ void load(const uint16_t *ge, int off, float *o) {
-        const uint32_t *pp = (const uint32_t *)ge;
+    __device__ static __forceinline__ void load(gptr<const uint16_t> ge, int off, float *o) {
+        const gptr<const uint32_t> pp = (gptr<const uint32_t>)ge;
 #pragma unroll
         for (int q = 0; q < 3; ++q) {
             const uint32_t v = pp[q * N3 + off];
@@ -121,9 +121,8 @@ struct GLoad<float, uint16_t, N3> {
 // the workgroup) is live at a time, so it stays in scalar registers.  Five
 // workgroup barriers per element.
 template <int NX, typename T, typename GT, bool FUSE>
-__device__ __forceinline__ void ax_body(int64_t blk, int64_t E, const T *__restrict__ D,
-                                        const GT *__restrict__ g, double *__restrict__ p,
-                                        double *__restrict__ w, const AxFuse &fz)
+__device__ __forceinline__ void ax_body(int64_t blk, int64_t E, kptr<T> D, gptr<const GT> g,
+                                        gptr<double> p, gptr<double> w, const AxFuse &fz)
 {
     using S = AxShape<NX, T>;
     constexpr int NN = S::NN;
@@ -134,7 +133,11 @@ __device__ __forceinline__ void ax_body(int64_t blk, int64_t E, const T *__restr
     constexpr int BUF = S::BUF;
     constexpr int PF = S::PF;
 
-    if (FUSE && fz.sc->done) return;   // uniform: CG already finished
+    // the CG scalars are written only by other launches
+    const kptr<CgScalars> sc = (kptr<CgScalars>)fz.sc;
+    const gptr<const double> fr = (gptr<const double>)fz.r;
+    const gptr<double> fx = (gptr<double>)fz.x;
+    if (FUSE && sc->done) return;   // uniform: CG already finished
 
     __shared__ T lds[EPB * 3 * BUF];
 
@@ -163,19 +166,19 @@ __device__ __forceinline__ void ax_body(int64_t blk, int64_t E, const T *__restr
 #pragma unroll
             for (int k = 0; k < NX; ++k) pv[k] = p[base + k * NN];
             if constexpr (FUSE) {
-                if (fz.x != nullptr && fz.sc->lag_applied == 0) {
-                    const double al = fz.sc->alpha;
+                if (fx != nullptr && sc->lag_applied == 0) {
+                    const double al = sc->alpha;
                     double xx[NX];
 #pragma unroll
-                    for (int k = 0; k < NX; ++k) xx[k] = fz.x[base + k * NN];
+                    for (int k = 0; k < NX; ++k) xx[k] = fx[base + k * NN];
 #pragma unroll
-                    for (int k = 0; k < NX; ++k) fz.x[base + k * NN] = xx[k] + al * pv[k];
+                    for (int k = 0; k < NX; ++k) fx[base + k * NN] = xx[k] + al * pv[k];
                 }
-                if (fz.r != nullptr) {
-                    const double bt = fz.sc->beta;
+                if (fr != nullptr) {
+                    const double bt = sc->beta;
                     double rr[NX];
 #pragma unroll
-                    for (int k = 0; k < NX; ++k) rr[k] = fz.r[base + k * NN];
+                    for (int k = 0; k < NX; ++k) rr[k] = fr[base + k * NN];
 #pragma unroll
                     for (int k = 0; k < NX; ++k) {
                         pv[k] = rr[k] + bt * pv[k];
@@ -199,7 +202,7 @@ __device__ __forceinline__ void ax_body(int64_t blk, int64_t E, const T *__restr
 
     // geometric factors of the first PF layers go out now, each later layer
     // PF layers ahead of its use
-    const GT *ge = g + e * (6 * N3);   // this element's factors
+    const gptr<const GT> ge = g + e * (6 * N3);   // this element's factors
     T gq[PF][6];
 #pragma unroll
     for (int k = 0; k < PF; ++k) {
@@ -227,7 +230,7 @@ __device__ __forceinline__ void ax_body(int64_t blk, int64_t E, const T *__restr
                 const T vr = B0[rpen + l];          // u(l, a, b)
                 const T vs = B0[spen + l * RS];     // u(a, l, b)
                 const T vt = B0[l * LS + col];      // u(a, b, l)
-                const T *Dl = D + NX * l;
+                const kptr<T> Dl = D + NX * l;
 #pragma unroll
                 for (int q = 0; q < NX; ++q) {
                     const T d = Dl[q];
@@ -278,7 +281,7 @@ __device__ __forceinline__ void ax_body(int64_t blk, int64_t E, const T *__restr
     if (in_slab) {
 #pragma unroll 2
         for (int i = 0; i < NX; ++i) {
-            const T *Di = D + NX * i;
+            const kptr<T> Di = D + NX * i;
             T pr = T(0), ps = T(0), pt = T(0);
 #pragma unroll
             for (int l = 0; l < NX; ++l) {
@@ -311,7 +314,7 @@ __device__ __forceinline__ void ax_body(int64_t blk, int64_t E, const T *__restr
         if (fz.partials != nullptr) {
             __shared__ double red[S::THREADS / 64];
             const double bs = block_sum<S::THREADS>(pw, red);
-            if (threadIdx.x == 0) fz.partials[blk] = bs;
+            if (threadIdx.x == 0) ((gptr<double>)fz.partials)[blk] = bs;
         }
     }
 }
@@ -321,7 +324,8 @@ __global__ void __launch_bounds__((AxShape<NX, T>::THREADS), (AxShape<NX, T>::MI
 ax_kernel(int64_t E, const T *__restrict__ D, const GT *__restrict__ g, double *__restrict__ p,
           double *__restrict__ w, AxFuse fz)
 {
-    ax_body<NX, T, GT, FUSE>(blockIdx.x, E, D, g, p, w, fz);
+    ax_body<NX, T, GT, FUSE>(blockIdx.x, E, (kptr<T>)D, (gptr<const GT>)g, (gptr<double>)p,
+                             (gptr<double>)w, fz);
 }
 
 // Several CG solves of the same degree and precision in one launch: slot s
@@ -332,11 +336,9 @@ template <int NX, typename T, typename GT>
 __global__ void __launch_bounds__((AxShape<NX, T>::THREADS), (AxShape<NX, T>::MINW))
 ax_batch_kernel(const AxSlot *__restrict__ slots, int nslots)
 {
-    int sidx = 0;
-    while (sidx + 1 < nslots && (int64_t)blockIdx.x >= slots[sidx + 1].block0) ++sidx;
-    const AxSlot &S = slots[sidx];
-    ax_body<NX, T, GT, true>((int64_t)blockIdx.x - S.block0, S.E, (const T *)S.D, (const GT *)S.g,
-                             S.p, S.w, S.fz);
+    const AxSlot S = slots[batch_slot(slots, nslots, (int64_t)blockIdx.x)];
+    ax_body<NX, T, GT, true>((int64_t)blockIdx.x - S.block0, S.E, (kptr<T>)S.D, (gptr<const GT>)S.g,
+                             (gptr<double>)S.p, (gptr<double>)S.w, S.fz);
 }
 
 template <int NX, typename T, typename GT>
@@ -414,6 +416,8 @@ __global__ void convert_g_kernel(int64_t E, int64_t n3, const double *__restrict
 hipError_t launch_ax_batch(int N, int precision, const AxSlot *slots, int nslots, int64_t blocks,
                            hipStream_t s)
 {
+    if (nslots < 1 || nslots > BATCH_MAX_SLOTS || blocks < 1 || blocks > 0x7fffffff)
+        return hipErrorInvalidValue;
     switch (N + 1) {
 #define NEK_BCASE(NX)                                                                          \
     case NX:                                                                                   \

@@ -16,17 +16,19 @@
 namespace nek {
 namespace {
 
-__device__ __forceinline__ unsigned own_pair(const uint32_t *own, int64_t pt) {
+template <typename OwnPtr>
+__device__ __forceinline__ unsigned own_pair(OwnPtr own, int64_t pt) {
     // bits of points pt, pt+1 (pt even)
     return (own[pt >> 5] >> (pt & 31)) & 3u;
 }
 
 // ---------------------------------------------------------------- dssum + mask
 template <int C>
-__device__ __forceinline__ void gs_row(const GsGroup &G, int32_t row, double *__restrict__ w) {
+__device__ __forceinline__ void gs_row(gptr<const int32_t> idx, int32_t rows, int32_t row,
+                                       gptr<double> w) {
     int32_t id[C];
 #pragma unroll
-    for (int m = 0; m < C; ++m) id[m] = G.idx[(int64_t)m * G.rows + row];
+    for (int m = 0; m < C; ++m) id[m] = idx[(int64_t)m * rows + row];
     double v[C];
 #pragma unroll
     for (int m = 0; m < C; ++m) v[m] = w[id[m]];
@@ -37,26 +39,28 @@ __device__ __forceinline__ void gs_row(const GsGroup &G, int32_t row, double *__
     for (int m = 0; m < C; ++m) w[id[m]] = s;
 }
 
-__device__ __forceinline__ void gs_vblock(const GsArgs &a, int vb, double *__restrict__ w) {
+__device__ __forceinline__ void gs_vblock(const GsArgs &a, int vb, gptr<double> w) {
     int g = 0;
     while (g + 1 < a.ngroups && vb >= a.grp[g + 1].block0) ++g;
     const GsGroup &G = a.grp[g];
     const int32_t row = (vb - G.block0) * GS_THREADS + (int32_t)threadIdx.x;
     if (row >= G.rows) return;
+    const gptr<const int32_t> idx = (gptr<const int32_t>)G.idx;
     switch (G.kind) {
-    case 0: w[G.idx[row]] = 0.0; break;
-    case 2: gs_row<2>(G, row, w); break;
-    case 3: gs_row<3>(G, row, w); break;
-    case 4: gs_row<4>(G, row, w); break;
-    case 5: gs_row<5>(G, row, w); break;
-    case 6: gs_row<6>(G, row, w); break;
-    case 7: gs_row<7>(G, row, w); break;
-    case 8: gs_row<8>(G, row, w); break;
+    case 0: w[idx[row]] = 0.0; break;
+    case 2: gs_row<2>(idx, G.rows, row, w); break;
+    case 3: gs_row<3>(idx, G.rows, row, w); break;
+    case 4: gs_row<4>(idx, G.rows, row, w); break;
+    case 5: gs_row<5>(idx, G.rows, row, w); break;
+    case 6: gs_row<6>(idx, G.rows, row, w); break;
+    case 7: gs_row<7>(idx, G.rows, row, w); break;
+    case 8: gs_row<8>(idx, G.rows, row, w); break;
     default: {   // CSR rows with many copies
-        const int32_t o0 = G.off[row], o1 = G.off[row + 1];
+        const gptr<const int32_t> off = (gptr<const int32_t>)G.off;
+        const int32_t o0 = off[row], o1 = off[row + 1];
         double s = 0.0;
-        for (int32_t o = o0; o < o1; ++o) s += w[G.idx[o]];
-        for (int32_t o = o0; o < o1; ++o) w[G.idx[o]] = s;
+        for (int32_t o = o0; o < o1; ++o) s += w[idx[o]];
+        for (int32_t o = o0; o < o1; ++o) w[idx[o]] = s;
     }
     }
 }
@@ -68,9 +72,9 @@ constexpr int N_XCD = 8;   // gfx950: workgroups are dealt round-robin to 8 XCDs
 // and the rows next to it share that XCD's L2.  Local workgroup 0 also turns
 // the (p, A_L p) partials of the preceding ax launch into alpha.
 // lb / nb: local workgroup index and count (nb a multiple of 8).
-__device__ __forceinline__ void gs_body(int lb, int nb, const GsArgs &a, double *__restrict__ w,
-                                        const double *__restrict__ axparts, long nparts,
-                                        CgScalars *sc) {
+__device__ __forceinline__ void gs_body(int lb, int nb, const GsArgs &a, gptr<double> w,
+                                        gptr<const double> axparts, long nparts,
+                                        gptr<CgScalars> sc) {
     if (sc != nullptr && sc->done) return;
     const int xcd = lb % N_XCD;
     const int per = nb / N_XCD;
@@ -101,17 +105,17 @@ __device__ __forceinline__ void gs_body(int lb, int nb, const GsArgs &a, double 
 __global__ void __launch_bounds__(GS_THREADS)
 gs_kernel(GsArgs a, double *__restrict__ w, const double *__restrict__ axparts, long nparts,
           CgScalars *sc) {
-    gs_body(blockIdx.x, gridDim.x, a, w, axparts, nparts, sc);
+    gs_body(blockIdx.x, gridDim.x, a, (gptr<double>)w, (gptr<const double>)axparts, nparts,
+            (gptr<CgScalars>)sc);
 }
 
 __global__ void __launch_bounds__(GS_THREADS)
 gs_batch_kernel(const GsSlot *__restrict__ slots, int nslots) {
-    int sidx = 0;
-    while (sidx + 1 < nslots && (int64_t)blockIdx.x >= slots[sidx + 1].block0) ++sidx;
-    const GsSlot &S = slots[sidx];
+    const GsSlot &S = slots[batch_slot(slots, nslots, (int64_t)blockIdx.x)];
     const int lb = (int)((int64_t)blockIdx.x - S.block0);
     if (lb >= S.nblocks) return;
-    gs_body(lb, (int)S.nblocks, S.args, S.w, S.axparts, (long)S.nparts, S.sc);
+    gs_body(lb, (int)S.nblocks, S.args, (gptr<double>)S.w, (gptr<const double>)S.axparts,
+            (long)S.nparts, (gptr<CgScalars>)S.sc);
 }
 
 // ---------------------------------------------------------------- CG steps
@@ -147,7 +151,8 @@ __device__ __forceinline__ bool owns_tail(int64_t P) {
     return (P & 1) && blockIdx.x == gridDim.x - 1 && threadIdx.x == VEC_THREADS - 1;
 }
 
-__device__ __forceinline__ bool own_bit(const uint32_t *own, int64_t t) {
+template <typename OwnPtr>
+__device__ __forceinline__ bool own_bit(OwnPtr own, int64_t t) {
     return (own[t >> 5] >> (t & 31)) & 1u;
 }
 
@@ -206,10 +211,9 @@ cg_init_kernel(int64_t P, const double *__restrict__ b, double *__restrict__ x,
 }
 
 // r -= alpha w; rho' = (r, r); beta = rho' / rho; convergence and iteration cap
-__device__ __forceinline__ void update_body(int lb, int nb, int64_t P, double *__restrict__ r,
-                                            const double *__restrict__ w,
-                                            const uint32_t *__restrict__ own, const RedSite &red,
-                                            CgScalars *sc) {
+__device__ __forceinline__ void update_body(int lb, int nb, int64_t P, gptr<double> r,
+                                            gptr<const double> w, gptr<const uint32_t> own,
+                                            const RedSite &red, gptr<CgScalars> sc) {
     if (sc->done) return;
     __shared__ double lds[VEC_THREADS / 64];
     const double alpha = sc->alpha;
@@ -221,8 +225,8 @@ __device__ __forceinline__ void update_body(int lb, int nb, int64_t P, double *_
         for (int m = 0; m < VEC_PAIRS; ++m) {
             const int64_t q = base + threadIdx.x + (int64_t)m * VEC_THREADS;
             if (q < npairs) {
-                rv[m] = ((const double2 *)r)[q];
-                wv[m] = ((const double2 *)w)[q];
+                rv[m] = ((gptr<const double2>)r)[q];
+                wv[m] = ((gptr<const double2>)w)[q];
             }
         }
 #pragma unroll
@@ -232,7 +236,7 @@ __device__ __forceinline__ void update_body(int lb, int nb, int64_t P, double *_
                 double2 nr;
                 nr.x = rv[m].x - alpha * wv[m].x;
                 nr.y = rv[m].y - alpha * wv[m].y;
-                ((double2 *)r)[q] = nr;
+                ((gptr<double2>)r)[q] = nr;
                 const unsigned o = own_pair(own, 2 * q);
                 if (o & 1u) acc += nr.x * nr.x;
                 if (o & 2u) acc += nr.y * nr.y;
@@ -269,21 +273,27 @@ __device__ __forceinline__ void update_body(int lb, int nb, int64_t P, double *_
 __global__ void __launch_bounds__(VEC_THREADS)
 cg_update_kernel(int64_t P, double *__restrict__ r, const double *__restrict__ w,
                  const uint32_t *__restrict__ own, RedSite red, CgScalars *sc) {
-    update_body(blockIdx.x, gridDim.x, P, r, w, own, red, sc);
+    update_body(blockIdx.x, gridDim.x, P, (gptr<double>)r, (gptr<const double>)w,
+                (gptr<const uint32_t>)own, red, (gptr<CgScalars>)sc);
 }
 
 __global__ void __launch_bounds__(VEC_THREADS)
 update_batch_kernel(const UpdSlot *__restrict__ slots, int nslots) {
-    int sidx = 0;
-    while (sidx + 1 < nslots && (int64_t)blockIdx.x >= slots[sidx + 1].block0) ++sidx;
-    const UpdSlot &S = slots[sidx];
-    update_body((int)((int64_t)blockIdx.x - S.block0), (int)S.nblocks, S.P, S.r, S.w, S.own, S.red,
-                S.sc);
+    const UpdSlot S = slots[batch_slot(slots, nslots, (int64_t)blockIdx.x)];
+    update_body((int)((int64_t)blockIdx.x - S.block0), (int)S.nblocks, S.P, (gptr<double>)S.r,
+                (gptr<const double>)S.w, (gptr<const uint32_t>)S.own, S.red, (gptr<CgScalars>)S.sc);
 }
 
 __global__ void gather_scalars_kernel(CgScalars *const *src, int n, CgScalars *dst) {
+    typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+    static_assert(sizeof(CgScalars) % sizeof(u32x4) == 0, "CgScalars is copied in 16-byte pieces");
+    constexpr int PIECES = sizeof(CgScalars) / sizeof(u32x4);
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n) dst[i] = *src[i];
+    if (i >= n) return;
+    const gptr<const u32x4> from = (gptr<const u32x4>)src[i];
+    const gptr<u32x4> to = (gptr<u32x4>)(dst + i);
+#pragma unroll
+    for (int q = 0; q < PIECES; ++q) to[q] = from[q];
 }
 
 // x += alpha p when the last alpha has not reached x yet (end of a solve,
@@ -412,11 +422,15 @@ hipError_t launch_gs(const GsDevice &gs, double *w, const double *axparts, int64
 }
 
 hipError_t launch_gs_batch(const GsSlot *slots, int nslots, int64_t blocks, hipStream_t s) {
+    if (nslots < 1 || nslots > BATCH_MAX_SLOTS || blocks < 1 || blocks > 0x7fffffff)
+        return hipErrorInvalidValue;
     hipLaunchKernelGGL(gs_batch_kernel, dim3((unsigned)blocks), dim3(GS_THREADS), 0, s, slots, nslots);
     return hipGetLastError();
 }
 
 hipError_t launch_update_batch(const UpdSlot *slots, int nslots, int64_t blocks, hipStream_t s) {
+    if (nslots < 1 || nslots > BATCH_MAX_SLOTS || blocks < 1 || blocks > 0x7fffffff)
+        return hipErrorInvalidValue;
     hipLaunchKernelGGL(update_batch_kernel, dim3((unsigned)blocks), dim3(VEC_THREADS), 0, s, slots,
                        nslots);
     return hipGetLastError();

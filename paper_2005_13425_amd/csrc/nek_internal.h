@@ -71,6 +71,23 @@ hipError_t launch_ax_f32(int64_t E, int N, const float *D32, const void *g_lo, i
 // number of workgroups of an ax launch (one partial each)
 int64_t ax_blocks(int64_t E, int N);
 
+// ---------------------------------------------------------------- batched launches
+// A launch that serves several solves gives each one a contiguous range of
+// workgroups, described by a table of slots sorted by block0 (slots[0].block0
+// is 0).  At most BATCH_MAX_SLOTS slots share a launch.
+constexpr int BATCH_MAX_SLOTS = 64;
+
+// Slot owning workgroup blk.  Every lane of the (full, 64-lane) wave loads one
+// slot's block0 and a ballot counts the slots starting at or before blk: one
+// load per workgroup instead of a chain of dependent ones.  The result is
+// uniform across the wave.
+template <typename Slot>
+__device__ __forceinline__ int batch_slot(const Slot *__restrict__ slots, int nslots, int64_t blk) {
+    const int lane = (int)(threadIdx.x & 63u);
+    const bool before = lane < nslots && slots[lane].block0 <= blk;
+    return __popcll(__ballot(before)) - 1;
+}
+
 // One solve inside a launch that serves several (same degree and precision).
 struct AxSlot {
     int64_t block0;      // first workgroup of this solve in the launch

@@ -11,6 +11,8 @@
 
 #include <hip/hip_runtime.h>
 
+#include "addrspace.h"
+
 namespace nek {
 
 constexpr int RED_GROUP = 32;          // workgroups per first-level ticket
@@ -41,19 +43,19 @@ __device__ __forceinline__ double block_sum(double v, double *lds) {
     return s;
 }
 
-__device__ __forceinline__ double load_coherent(const double *p) {
+__device__ __forceinline__ double load_coherent(gptr<const double> p) {
     unsigned long long bits =
-        __hip_atomic_load((const unsigned long long *)p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_load((gptr<const unsigned long long>)p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     return __longlong_as_double((long long)bits);
 }
 
-__device__ __forceinline__ void store_coherent(double *p, double v) {
-    __hip_atomic_store((unsigned long long *)p, (unsigned long long)__double_as_longlong(v),
+__device__ __forceinline__ void store_coherent(gptr<double> p, double v) {
+    __hip_atomic_store((gptr<unsigned long long>)p, (unsigned long long)__double_as_longlong(v),
                        __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 // Agent-scope ticket: the caller's coherent stores have completed first.
-__device__ __forceinline__ unsigned int take_ticket(unsigned int *t) {
+__device__ __forceinline__ unsigned int take_ticket(gptr<unsigned int> t) {
     __builtin_amdgcn_s_waitcnt(0);
     return __hip_atomic_fetch_add(t, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
@@ -86,37 +88,41 @@ template <int NT>
 __device__ bool grid_finish(double s, const RedSite &r, double *out, double *lds, unsigned int lb,
                             unsigned int nb) {
     __shared__ int stage;   // 0: not last, 1: last of its group, 2: last overall
+    const gptr<double> part = (gptr<double>)r.part;
+    const gptr<double> gpart = (gptr<double>)r.gpart;
+    const gptr<unsigned int> tk = (gptr<unsigned int>)r.tk;
+    const gptr<const double> extra = (gptr<const double>)r.extra;
     const unsigned int grp = lb / RED_GROUP;
     const unsigned int ngroups = (nb + RED_GROUP - 1) / RED_GROUP;
     const unsigned int gsize = (grp + 1 == ngroups) ? nb - grp * RED_GROUP : RED_GROUP;
     if (threadIdx.x == 0) {
-        store_coherent(&r.part[lb], s);
-        const unsigned int t = take_ticket(&r.tk[1 + grp]);
+        store_coherent(part + lb, s);
+        const unsigned int t = take_ticket(tk + 1 + grp);
         stage = (t == gsize - 1u) ? 1 : 0;
     }
     __syncthreads();
     if (stage == 0) return false;
     // last workgroup of the group: ordered group sum
     double v = 0.0;
-    if (threadIdx.x < gsize) v = load_coherent(&r.part[grp * RED_GROUP + threadIdx.x]);
+    if (threadIdx.x < gsize) v = load_coherent(part + grp * RED_GROUP + threadIdx.x);
     v = block_sum<NT>(v, lds);
     if (threadIdx.x == 0) {
-        r.tk[1 + grp] = 0u;
-        store_coherent(&r.gpart[grp], v);
-        const unsigned int t = take_ticket(&r.tk[0]);
+        tk[1 + grp] = 0u;
+        store_coherent(gpart + grp, v);
+        const unsigned int t = take_ticket(tk);
         stage = (t == ngroups - 1u) ? 2 : 0;
     }
     __syncthreads();
     if (stage != 2) return false;
     // last group: ordered sum of the group sums, then the extra partials
     double u = 0.0;
-    for (long q = threadIdx.x; q < (long)ngroups; q += NT) u += load_coherent(&r.gpart[q]);
+    for (long q = threadIdx.x; q < (long)ngroups; q += NT) u += load_coherent(gpart + q);
     double e = 0.0;
-    for (long q = threadIdx.x; q < r.nextra; q += NT) e += load_coherent(&r.extra[q]);
+    for (long q = threadIdx.x; q < r.nextra; q += NT) e += load_coherent(extra + q);
     u = block_sum<NT>(u, lds);
     e = block_sum<NT>(e, lds);
     if (threadIdx.x == 0) {
-        r.tk[0] = 0u;
+        tk[0] = 0u;
         *out = e + u;
     }
     return true;

@@ -27,6 +27,8 @@ namespace nek {
 namespace {
 
 constexpr int MAX_SLOTS = 64;
+static_assert(MAX_SLOTS <= BATCH_MAX_SLOTS, "a batched launch holds at most BATCH_MAX_SLOTS solves");
+constexpr int PREP_THREADS = 4;   // host threads preparing submitted requests
 
 bool is_mixed(int prec) { return prec == NEK_PREC_F32G32 || prec == NEK_PREC_F32GBF16; }
 
@@ -60,7 +62,6 @@ struct Request {
     nek_request spec{};
     int64_t E = 0, P = 0;
     Footprint fp{};
-    std::vector<double> b;        // copied at submit, dropped once staged
     double t_submit = 0.0;
     // filled by the preparation thread
     std::atomic<bool> prepared{false};
@@ -164,8 +165,9 @@ struct nek_server {
     std::chrono::steady_clock::time_point t0;
     uint64_t next_id = 1;
 
-    // preparation thread
-    std::thread worker;
+    // preparation threads: requests are prepared independently, admitted in
+    // arrival order
+    std::vector<std::thread> workers;
     std::mutex mu;
     std::condition_variable cv;
     std::deque<Request *> prep_queue;
@@ -218,7 +220,7 @@ struct nek_server {
                 R->prep_msg = "pinned staging allocation failed";
             } else {
                 char *st = (char *)R->staging;
-                memcpy(st, R->b.data(), (size_t)P * sizeof(double));
+                memcpy(st, q.b, (size_t)P * sizeof(double));   // the caller's b, read once
                 if (!R->gs.idx.empty()) memcpy(st + R->off_idx, R->gs.idx.data(), R->gs.idx.size() * sizeof(int32_t));
                 memcpy(st + R->off_own, R->gs.own.data(), R->gs.own.size() * sizeof(uint32_t));
                 double D[(NEK_MAX_DEGREE + 1) * (NEK_MAX_DEGREE + 1)];
@@ -228,8 +230,6 @@ struct nek_server {
                 for (int t = 0; t < n * n; ++t) D32[t] = (float)D[t];
             }
         }
-        // b is in the staging buffer now (the gather-scatter image is dropped at admission)
-        std::vector<double>().swap(R->b);
         R->prepared.store(true, std::memory_order_release);
     }
 
@@ -312,10 +312,17 @@ struct nek_server {
         return NEK_OK;
     }
 
+    // Admission in arrival order among prepared requests: a request still in
+    // preparation does not hold back prepared ones behind it, but a prepared
+    // request that does not fit stops admission, so a large request is never
+    // overtaken indefinitely by smaller ones.
     int admit() {
-        while (!waiting.empty()) {
-            Request *R = waiting.front().get();
-            if (!R->prepared.load(std::memory_order_acquire)) break;
+        for (auto it = waiting.begin(); it != waiting.end();) {
+            Request *R = it->get();
+            if (!R->prepared.load(std::memory_order_acquire)) {
+                ++it;
+                continue;
+            }
             if (R->prep_status != NEK_OK) {
                 // report the failure as a finished request
                 nek_result r{};
@@ -327,12 +334,12 @@ struct nek_server {
                 r.N = R->spec.N;
                 if (R->staging) pinned.put(R->staging);
                 results.push_back(r);
-                waiting.pop_front();
+                it = waiting.erase(it);
                 continue;
             }
             if (used + R->fp.total > budget || free_index.empty()) break;
-            std::unique_ptr<Request> own = std::move(waiting.front());
-            waiting.pop_front();
+            std::unique_ptr<Request> own = std::move(*it);
+            it = waiting.erase(it);
             int rc = admit_one(std::move(own));
             if (rc != NEK_OK) return rc;
         }
@@ -579,7 +586,7 @@ int nek_server_create(size_t hbm_budget, nek_server **out) {
     NEK_HIP(hipHostMalloc((void **)&S->fin, MAX_SLOTS * sizeof(FinArea), hipHostMallocDefault));
     for (int i = MAX_SLOTS - 1; i >= 0; --i) S->free_index.push_back(i);
     nek_server *raw = S.get();
-    S->worker = std::thread([raw] { raw->worker_loop(); });
+    for (int k = 0; k < PREP_THREADS; ++k) S->workers.emplace_back([raw] { raw->worker_loop(); });
     *out = S.release();
     return NEK_OK;
 }
@@ -597,14 +604,12 @@ int nek_server_submit(nek_server *srv, const nek_request *req, uint64_t *id) {
     if (P >= ((int64_t)1 << 31)) return fail(NEK_ERR_ARG, "nek_server_submit: E*(N+1)^3 must be < 2^31");
     auto R = std::make_unique<Request>();
     R->id = srv->next_id++;
-    R->spec = *req;
-    R->spec.b = nullptr;
+    R->spec = *req;   // b is read by a preparation thread, not copied here
     R->E = E;
     R->P = P;
     R->fp = footprint_of(E, req->N, req->precision);
     if (R->fp.total > srv->budget)
         return fail(NEK_ERR_NOMEM, "nek_server_submit: the request alone exceeds the budget");
-    R->b.assign(req->b, req->b + P);
     R->t_submit = srv->clock();
     if (id) *id = R->id;
     {
@@ -659,7 +664,8 @@ int nek_server_destroy(nek_server *srv) {
         srv->stop = true;
     }
     srv->cv.notify_all();
-    if (srv->worker.joinable()) srv->worker.join();
+    for (auto &t : srv->workers)
+        if (t.joinable()) t.join();
     hipError_t e = hipStreamSynchronize(srv->stream);
     for (auto &s : srv->slots) {
         if (s->arena) (void)hipFree(s->arena);

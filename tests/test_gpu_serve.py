@@ -130,6 +130,41 @@ def test_admission_by_footprint(nek):
     np.testing.assert_array_equal(xs[1], xs2[1])
 
 
+def test_waiting_request_that_does_not_fit_is_not_overtaken(nek):
+    """X runs; Y (prepared, too large to join X) arrives before the small Z,
+    which would fit beside X: Z waits behind Y."""
+    import time
+    X, Y, Z = ((4, 4, 4), 7), ((4, 4, 4), 9), ((2, 2, 2), 3)
+    fX, fY, fZ = (nek.server_footprint(*box, N) for box, N in (X, Y, Z))
+    budget = fY + 2 * fZ
+    assert fX + fZ <= budget < fX + fY
+    srv = nek.Server(budget)
+    a = synth.geom_coeffs()
+    sub = lambda box, N, seed: srv.submit(*box, N, _rhs(nek, box, N, seed), amp=synth.AMP, a=a,
+                                          rel_tol=1e-10, max_iter=20000)
+    ids = {sub(*X, 1): "X"}
+    for _ in range(100000):
+        act, _ = srv.step(1)
+        if act == 1:
+            break
+    assert act == 1
+    ids[sub(*Y, 2)] = "Y"
+    ids[sub(*Z, 3)] = "Z"
+    time.sleep(0.5)                 # both are prepared by now (tiny meshes)
+    res = {}
+    for _ in range(200000):
+        srv.step(1)
+        for r in srv.poll():
+            res[ids[r["id"]]] = r
+            srv.fetch(r["id"])
+        if len(res) == 3:
+            break
+    srv.close()
+    assert all(r["status"] == 0 for r in res.values())
+    assert res["Y"]["t_admit"] >= res["X"]["t_done"] - 1e-9
+    assert res["Z"]["t_admit"] >= res["Y"]["t_admit"]
+
+
 def test_server_errors(nek):
     srv = nek.Server(1 << 20)
     b = np.zeros(8 ** 3 * 64)
