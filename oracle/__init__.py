@@ -17,6 +17,10 @@ that the C routine follows:
 * :func:`dssum`, :func:`mask` -- the communication step of Ax (Sec. III) and
   the boundary masking (Sec. VI-B).
 * :func:`gdot`, :func:`cg` -- the CG solve of Sec. III / Sec. V.
+* :func:`ax_diag`, :func:`jacobi_inverse`, :func:`pcg` -- the diagonal of the
+  element operator of Listing 1 and CG preconditioned by the inverse of the
+  assembled diagonal (Jacobi), the simplest form of the preconditioning that
+  Sec. VII names as future work.
 """
 from __future__ import annotations
 
@@ -77,6 +81,11 @@ def _load():
     lib.or_cg.argtypes = [i64, ci, dp, dp, i64p, i64, u8p, dp, dp, ci,
                           ctypes.c_double, ctypes.POINTER(ci), dp, ci]
     lib.or_cg.restype = ci
+    lib.or_ax_diag.argtypes = [i64, ci, dp, dp, dp]
+    lib.or_ax_diag.restype = None
+    lib.or_pcg.argtypes = [i64, ci, dp, dp, i64p, i64, u8p, dp, dp, dp, ci,
+                           ctypes.c_double, ctypes.POINTER(ci), dp, ci]
+    lib.or_pcg.restype = ci
     lib.or_max_threads.argtypes = []
     lib.or_max_threads.restype = ci
     _lib = lib
@@ -246,6 +255,41 @@ def cg(mesh: BoxMesh, b, max_iter: int = 100, rel_tol: float = 0.0, nthreads: in
     rc = _load().or_cg(mesh.E, mesh.N, _d(mesh.D), _d(mesh.g), _i64(mesh.glo), mesh.U,
                        _u8(mesh.dirichlet), _d(b), _d(x), int(max_iter), float(rel_tol),
                        ctypes.byref(it), _d(hist), int(nthreads))
+    return CGResult(x, int(it.value), int(rc), hist[: it.value + 1].copy())
+
+
+def ax_diag(E: int, N: int, D, g):
+    """Diagonal of the element operator of Listing 1 at every local point."""
+    D = np.ascontiguousarray(D, dtype=np.float64).reshape(-1)
+    g = np.ascontiguousarray(g, dtype=np.float64).reshape(-1)
+    d = np.empty(E * (N + 1) ** 3)
+    _load().or_ax_diag(E, N, _d(D), _d(g), _d(d))
+    return d
+
+
+def jacobi_inverse(mesh: BoxMesh):
+    """Jacobi preconditioner M^-1 as a continuous local vector: one over the
+    diagonal of the assembled operator (dssum of the element diagonals) at
+    free nodes, zero at Dirichlet nodes."""
+    dg = dssum(mesh.glo, ax_diag(mesh.E, mesh.N, mesh.D, mesh.g), mesh.U)
+    inv = np.zeros_like(dg)
+    free = mesh.dirichlet == 0
+    inv[free] = 1.0 / dg[free]
+    return inv
+
+
+def pcg(mesh: BoxMesh, b, dinv, max_iter: int = 100, rel_tol: float = 0.0,
+        nthreads: int = 0) -> CGResult:
+    """CG preconditioned with M^-1 = dinv on mask(dssum(A_L .)) x = b, x_0 = 0;
+    the residual history and the stopping test use ||r|| / ||b||."""
+    b = np.ascontiguousarray(b, dtype=np.float64).reshape(-1)
+    dinv = np.ascontiguousarray(dinv, dtype=np.float64).reshape(-1)
+    x = np.zeros_like(b)
+    hist = np.zeros(max_iter + 1)
+    it = ctypes.c_int(0)
+    rc = _load().or_pcg(mesh.E, mesh.N, _d(mesh.D), _d(mesh.g), _i64(mesh.glo), mesh.U,
+                        _u8(mesh.dirichlet), _d(dinv), _d(b), _d(x), int(max_iter),
+                        float(rel_tol), ctypes.byref(it), _d(hist), int(nthreads))
     return CGResult(x, int(it.value), int(rc), hist[: it.value + 1].copy())
 
 

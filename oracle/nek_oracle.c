@@ -32,6 +32,11 @@
  *                 nodes.
  *   or_cg         unpreconditioned conjugate gradients on the assembled,
  *                 masked system (Sec. III; 100 iterations in Sec. V).
+ *   or_ax_diag    the diagonal of the element operator of Listing 1, from
+ *                 the quadrature form of A_e applied to unit vectors.
+ *   or_pcg        conjugate gradients preconditioned by the inverse of the
+ *                 assembled diagonal (Jacobi): the preconditioning that
+ *                 Sec. VII names as future work, in its simplest form.
  *
  * Layouts follow the Fortran arrays of Listing 1, 0-based:
  *   u(i,j,k,e)        at u[i + n*(j + n*(k + n*e))]
@@ -414,6 +419,109 @@ int or_cg(int64_t E, int N, const double *D, const double *g,
     if (status == 0 && rel_tol > 0.0 && !(sqrt(rho / bb) <= rel_tol)) status = 1;
     *iters = it;
     free(r); free(p); free(w);
+    return status;
+}
+
+/* Diagonal of the element operator of Listing 1, per local point.
+ * A_e u = sum over quadrature points m of grad(phi)(m)^T G(m) grad(u)(m), with
+ * the reference-space gradient of the basis function phi_p, p = (i,j,k), at
+ * m = (i',j',k') equal to
+ *   ( dxm1(i',i) [j'=j][k'=k],  [i'=i] dxm1(j',j) [k'=k],  [i'=i][j'=j] dxm1(k',k) ).
+ * So (A_e)_pp = sum_m grad(phi_p)(m)^T G(m) grad(phi_p)(m).  Only the points m
+ * on the three grid lines through p make a term non-zero: the rr term runs
+ * over i', the ss term over j', the tt term over k', and each off-diagonal
+ * term (rs, rt, st, each twice by symmetry) survives only at m = p.
+ * Every element on its own; d has the layout of u. */
+void or_ax_diag(int64_t E, int N, const double *D, const double *g, double *d)
+{
+    int n = N + 1;
+    int64_t n3 = (int64_t)n * n * n;
+    for (int64_t e = 0; e < E; ++e) {
+        const double *ge = g + 6 * n3 * e;
+        for (int k = 0; k < n; ++k)
+        for (int j = 0; j < n; ++j)
+        for (int i = 0; i < n; ++i) {
+            int64_t p = i + n * (j + n * k);
+            double s = 0.0;
+            for (int m = 0; m < n; ++m) {     /* rr: points (m, j, k) */
+                double dr = D[m + n * i];
+                s = s + dr * ge[0 * n3 + (m + n * (j + n * k))] * dr;
+            }
+            for (int m = 0; m < n; ++m) {     /* ss: points (i, m, k) */
+                double ds = D[m + n * j];
+                s = s + ds * ge[3 * n3 + (i + n * (m + n * k))] * ds;
+            }
+            for (int m = 0; m < n; ++m) {     /* tt: points (i, j, m) */
+                double dt = D[m + n * k];
+                s = s + dt * ge[5 * n3 + (i + n * (j + n * m))] * dt;
+            }
+            double dii = D[i + n * i], djj = D[j + n * j], dkk = D[k + n * k];
+            s = s + 2.0 * dii * ge[1 * n3 + p] * djj     /* rs at m = p */
+                  + 2.0 * dii * ge[2 * n3 + p] * dkk     /* rt */
+                  + 2.0 * djj * ge[4 * n3 + p] * dkk;    /* st */
+            d[n3 * e + p] = s;
+        }
+    }
+}
+
+/* Conjugate gradients preconditioned with M^-1 = dinv, a continuous local
+ * vector (for Jacobi: the mask divided by the assembled diagonal, zero at
+ * Dirichlet nodes).  The textbook preconditioned recurrence:
+ *   x_0 = 0, r_0 = b, z_0 = dinv r_0, p_0 = z_0, rz = (r_0, z_0)
+ *   per iteration:  w = mask(dssum(A_L p));  alpha = rz / (p, w)
+ *                   x += alpha p;  r -= alpha w;  z = dinv r
+ *                   rz' = (r, z);  beta = rz' / rz;  p = z + beta p
+ * The stopping test and res_hist use the unpreconditioned residual,
+ * sqrt((r, r) / (b, b)), as or_cg does.  Return codes as or_cg. */
+int or_pcg(int64_t E, int N, const double *D, const double *g,
+           const int64_t *glo, int64_t U, const uint8_t *dirichlet, const double *dinv,
+           const double *b, double *x, int max_iter, double rel_tol,
+           int *iters, double *res_hist, int nthreads)
+{
+    int n = N + 1;
+    int64_t P = E * n * n * n;
+    double *r = (double *)malloc(sizeof(double) * P);
+    double *z = (double *)malloc(sizeof(double) * P);
+    double *p = (double *)malloc(sizeof(double) * P);
+    double *w = (double *)malloc(sizeof(double) * P);
+    int status = 0, it = 0;
+    if (!r || !z || !p || !w) { free(r); free(z); free(p); free(w); return -2; }
+    for (int64_t L = 0; L < P; ++L) {
+        x[L] = 0.0;
+        r[L] = b[L];
+        z[L] = dinv[L] * r[L];
+        p[L] = z[L];
+    }
+    double bb = or_gdot(P, glo, U, b, b);
+    double rr = bb;
+    double rz = or_gdot(P, glo, U, r, z);
+    if (res_hist) res_hist[0] = bb > 0.0 ? 1.0 : 0.0;
+    for (it = 0; it < max_iter; ) {
+        if (rr == 0.0) break;
+        or_ax(E, N, D, g, p, w, nthreads);
+        if (or_dssum(P, glo, U, w) != 0) { status = -2; break; }
+        or_mask(P, dirichlet, w);
+        double pw = or_gdot(P, glo, U, p, w);
+        if (!(pw > 0.0) || !isfinite(pw)) { status = -5; break; }
+        double alpha = rz / pw;
+        for (int64_t L = 0; L < P; ++L) {
+            x[L] = x[L] + alpha * p[L];
+            r[L] = r[L] - alpha * w[L];
+            z[L] = dinv[L] * r[L];
+        }
+        rr = or_gdot(P, glo, U, r, r);
+        double rz_new = or_gdot(P, glo, U, r, z);
+        ++it;
+        if (!isfinite(rr) || !isfinite(rz_new)) { status = -5; break; }
+        if (res_hist) res_hist[it] = sqrt(rr / bb);
+        if (rel_tol > 0.0 && sqrt(rr / bb) <= rel_tol) break;
+        double beta = rz_new / rz;
+        rz = rz_new;
+        for (int64_t L = 0; L < P; ++L) p[L] = z[L] + beta * p[L];
+    }
+    if (status == 0 && rel_tol > 0.0 && !(sqrt(rr / bb) <= rel_tol)) status = 1;
+    *iters = it;
+    free(r); free(z); free(p); free(w);
     return status;
 }
 

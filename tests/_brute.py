@@ -113,3 +113,25 @@ def cg_dense(A, b, iters):
         p = r + (rho_new / rho) * p
         rho = rho_new
     return x, np.array(hist)
+
+
+def pcg_dense(A, b, Minv, iters):
+    """Textbook preconditioned CG on a dense SPD matrix with a diagonal
+    preconditioner Minv (a vector); returns x and ||r|| / ||b|| per step."""
+    x = np.zeros_like(b)
+    r = b.copy()
+    z = Minv * r
+    p = z.copy()
+    rz = r @ z
+    hist = [np.sqrt((r @ r) / (b @ b))]
+    for _ in range(iters):
+        w = A @ p
+        alpha = rz / (p @ w)
+        x = x + alpha * p
+        r = r - alpha * w
+        z = Minv * r
+        rz_new = r @ z
+        hist.append(np.sqrt((r @ r) / (b @ b)))
+        p = z + (rz_new / rz) * p
+        rz = rz_new
+    return x, np.array(hist)

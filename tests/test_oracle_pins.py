@@ -309,6 +309,92 @@ def test_cg_fixed_iterations_and_breakdown():
     assert oracle.cg(m, bad, max_iter=5).status == -5
 
 
+# ---------------------------------------------------------------- Jacobi PCG
+@pytest.mark.parametrize("N", [1, 2, 3])
+def test_ax_diag_matches_bruteforce_element_stiffness(N):
+    # the diagonal of the dense quadrature stiffness (Lagrange derivatives by
+    # the product rule, not dxm1) of each perturbed element
+    m = _rand_mesh(2, 1, 1, N)
+    n3 = (N + 1) ** 3
+    zb, wb = _brute.gll_numpy(N)
+    d = oracle.ax_diag(m.E, N, m.D, m.g)
+    for e in range(m.E):
+        Xe = m.X[:, e * n3:(e + 1) * n3].reshape(3, N + 1, N + 1, N + 1)
+        K = _brute.element_stiffness_brute(Xe, zb, wb)
+        np.testing.assert_allclose(d[e * n3:(e + 1) * n3], np.diag(K), rtol=1e-13, atol=0)
+
+
+@pytest.mark.parametrize("N,box", [(4, (2, 1, 1)), (6, (1, 1, 2))])
+def test_ax_diag_is_listing1_on_unit_vectors(N, box):
+    m = _rand_mesh(*box, N)
+    d = oracle.ax_diag(m.E, N, m.D, m.g)
+    rng = np.random.default_rng(5)
+    for L in rng.choice(m.P, size=40, replace=False):
+        e = np.zeros(m.P)
+        e[L] = 1.0
+        assert abs(oracle.ax(m.E, N, m.D, m.g, e)[L] - d[L]) <= 1e-14 * abs(d[L])
+
+
+def test_ax_diag_affine_closed_form():
+    N, box = 3, (2, 1, 1)
+    m = oracle.box_mesh(*box, N)
+    zb, wb = _brute.gll_numpy(N)
+    A = _brute.affine_element_matrix(zb, wb, 1 / box[0], 1 / box[1], 1 / box[2])
+    d = oracle.ax_diag(m.E, N, m.D, m.g)
+    n3 = (N + 1) ** 3
+    for e in range(m.E):
+        np.testing.assert_allclose(d[e * n3:(e + 1) * n3], np.diag(A), rtol=1e-13)
+
+
+@pytest.mark.parametrize("N", [1, 2, 3])
+def test_jacobi_inverse_is_inverse_of_assembled_diagonal(N):
+    m = _rand_mesh(2, 2, 2, N)
+    A, interior, first = _assembled(m)
+    inv = oracle.jacobi_inverse(m)
+    np.testing.assert_allclose(inv[first[interior]], 1.0 / np.diag(A), rtol=1e-13)
+    assert np.all(inv[m.dirichlet == 1] == 0.0)
+    # continuous: every copy of a node holds the same value
+    for G in interior:
+        assert np.ptp(inv[m.glo == G]) == 0.0
+
+
+@pytest.mark.parametrize("N", [1, 2, 3])
+def test_pcg_matches_dense_solve_and_textbook_recurrence(N):
+    m = _rand_mesh(2, 2, 2, N)
+    A, interior, first = _assembled(m)
+    inv = oracle.jacobi_inverse(m)
+    b = oracle.lattice_to_local(m, synth.lattice_uniform(2, 2, 2, N))
+    res = oracle.pcg(m, b, inv, max_iter=400, rel_tol=1e-13)
+    assert res.status == 0
+    assert res.iters <= len(interior) + 5
+    xd = np.linalg.solve(A, b[first[interior]])
+    np.testing.assert_allclose(res.x[first[interior]], xd, rtol=1e-11, atol=1e-12)
+    _, hist = _brute.pcg_dense(A, b[first[interior]], 1.0 / np.diag(A), min(10, res.iters))
+    np.testing.assert_allclose(res.res_hist[: len(hist)], hist, rtol=1e-9, atol=1e-14)
+    assert np.all(res.x[m.dirichlet == 1] == 0)
+
+
+def test_pcg_with_identity_preconditioner_is_cg_bitwise():
+    m = _rand_mesh(2, 2, 2, 4)
+    b = oracle.lattice_to_local(m, synth.lattice_uniform(2, 2, 2, 4))
+    ident = (m.dirichlet == 0).astype(np.float64)
+    a = oracle.pcg(m, b, ident, max_iter=25)
+    c = oracle.cg(m, b, max_iter=25)
+    np.testing.assert_array_equal(a.x, c.x)
+    np.testing.assert_array_equal(a.res_hist, c.res_hist)
+
+
+def test_pcg_fewer_iterations_on_stretched_elements():
+    # elements of aspect 2:1:1 make the diagonal vary; Jacobi pays off there
+    m = oracle.box_mesh(4, 2, 2, 5, synth.AMP, synth.geom_coeffs())
+    b = oracle.lattice_to_local(m, synth.lattice_uniform(4, 2, 2, 5))
+    plain = oracle.cg(m, b, max_iter=3000, rel_tol=1e-10)
+    jac = oracle.pcg(m, b, oracle.jacobi_inverse(m), max_iter=3000, rel_tol=1e-10)
+    assert plain.status == 0 and jac.status == 0
+    assert jac.iters < plain.iters
+    assert np.linalg.norm(jac.x - plain.x) / np.linalg.norm(plain.x) < 1e-8
+
+
 def test_paper_accounting_numbers():
     acc = _load("paper_accounting.json")
     n = acc["n"]
