@@ -16,6 +16,9 @@ uniform in [-1, 1] per global node, zero Dirichlet boundary.
 * mixed: time to a true relative residual of 1e-10 on a manufactured
   solution, FP64 CG against the FP32 operator (g in FP32 / BF16) inside FP64
   reliable-update CG.
+* jacobi: time to ||r||/||b|| <= 1e-10 with and without the Jacobi
+  preconditioner on the 16x8x8 and 16x16x16 boxes at N = 9.
+* sweep: ax_e alone for N = 5..15 at about 32.8 M points each.
 * serve: a seeded stream of box-mesh solves of mixed sizes and degrees
   (to 1e-10) through the served form, against the same solves one after
   another with nek_cg_solve: capacity (solves/s) and p50/p99 latency under
@@ -53,7 +56,9 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--serve-requests", type=int, default=24)
-    ap.add_argument("--serve-budget-gb", type=float, default=64.0)
+    ap.add_argument("--serve-budget-gb", type=float, default=2.0)
+    ap.add_argument("--no-sweep", action="store_true")
+    ap.add_argument("--no-jacobi", action="store_true")
     ap.add_argument("--serve-iters-per-step", type=int, default=4)
     return ap.parse_args()
 
@@ -143,6 +148,15 @@ def main():
     a1.record(stream)
     torch.cuda.synchronize()
     ax_us_warm = 1e3 * a0.elapsed_time(a1) / reps
+    # per-launch distribution of the cold phase (an event after every launch)
+    evs = [torch.cuda.Event(enable_timing=True) for _ in range(reps + 1)]
+    evs[0].record(stream)
+    for r in range(reps):
+        up, gp, wp = args_q[r % nsets]
+        call(E, N, up, Dp, gp, wp, sp)
+        evs[r + 1].record(stream)
+    torch.cuda.synchronize()
+    ax_per = np.array([1e3 * evs[r].elapsed_time(evs[r + 1]) for r in range(reps)])
     ax_bytes = 64 * P
     ax_flops = (12 * n + 15) * P
     ax_gbs = ax_bytes / (ax_us_cold * 1e-6) / 1e9
@@ -167,6 +181,7 @@ def main():
         return (nread + 1) * 8 * P / (us_ * 1e-6) / 1e9, us_
     stream7_gbs, stream7_us = probe(7)
     copy_gbs, _ = probe(1)
+    memcpy_gbs = memcpy_rate(torch, dev, stream)
 
     out = {
         "metric": "ax_e GFLOP/s + % HBM roofline at E=4096 N=9; CG solves/s, p50/p99 latency",
@@ -194,6 +209,9 @@ def main():
         "ax_e": {"us_per_call_cold": round(ax_us_cold, 2), "us_per_call_warm": round(ax_us_warm, 2),
                  "gflops_cold": round(ax_flops / (ax_us_cold * 1e-6) / 1e9, 1),
                  "gflops_warm": round(ax_flops / (ax_us_warm * 1e-6) / 1e9, 1),
+                 "us_per_call_cold_median": round(float(np.median(ax_per)), 2),
+                 "us_per_call_cold_p10": round(float(np.percentile(ax_per, 10)), 2),
+                 "us_per_call_cold_p90": round(float(np.percentile(ax_per, 90)), 2),
                  "gbs_cold": round(ax_gbs, 1),
                  "gbs_warm": round(ax_bytes / (ax_us_warm * 1e-6) / 1e9, 1),
                  "measured_roofline_gbs": round(stream7_gbs, 1),
@@ -205,10 +223,17 @@ def main():
                "final_rel_res": last.rel_res if last else None},
         "measured_stream7_gbs": round(stream7_gbs, 1),
         "measured_copy_gbs": round(copy_gbs, 1),
+        "measured_memcpy_dtod_gbs": round(memcpy_gbs, 1),
     }
+    del us, gsets, wsets
+    torch.cuda.empty_cache()
 
     if not args.no_mixed:
         out["mixed"] = mixed_leg(nek, torch, dev, Ex, Ey, Ez, N, D, g, gs, ws)
+    if not args.no_jacobi:
+        out["jacobi"] = jacobi_leg(nek, torch, dev)
+    if not args.no_sweep:
+        out["sweep"] = sweep_leg(nek, torch, dev, stream)
     if not args.no_serve:
         out["serve"] = serve_leg(nek, torch, args.serve_requests, args.serve_budget_gb,
                                  args.serve_iters_per_step)
@@ -262,6 +287,127 @@ def mixed_leg(nek, torch, dev, Ex, Ey, Ez, N, D, g, gs, ws, tol=1e-10):
     return res
 
 
+def jacobi_leg(nek, torch, dev, tol=1e-10, N=9):
+    """Time to a relative residual of 1e-10 (rhs U[-1, 1] per node) of plain CG
+    and Jacobi-preconditioned CG on the paper's box shapes at N = 9; the
+    preconditioner's setup (element diagonals, dssum, reciprocal) is timed
+    on its own."""
+    import synth
+    out = {}
+    stream = torch.cuda.current_stream()
+    for box in ((16, 8, 8), (16, 16, 16)):
+        E = box[0] * box[1] * box[2]
+        D = torch.from_numpy(nek.gll(N)[2]).to(dev)
+        g, _, _ = nek.box_geometry(*box, N, synth.AMP, synth.geom_coeffs())
+        glo, dr = nek.box_numbering(*box, N)
+        gs = nek.GatherScatter(E, N, glo, dr)
+        bh = synth.lattice_uniform(*box, N)[glo]
+        bh[dr == 1] = 0.0
+        b = torch.from_numpy(bh).to(dev)
+        x = torch.empty_like(b)
+        ws = nek.cg_workspace(E, N)
+        dinv = nek.jacobi_inverse(D, g, gs)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        nek.jacobi_inverse(D, g, gs, out=dinv)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        setup_ms = e0.elapsed_time(e1)
+        leg = {"E": E, "N": N, "box": list(box), "jacobi_setup_ms": round(setup_ms, 3)}
+        for name, pre in (("cg", None), ("jacobi_pcg", dinv)):
+            nek.cg_solve(D, g, gs, b, x, max_iter=10000, rel_tol=tol, workspace=ws, dinv=pre)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            _, r = nek.cg_solve(D, g, gs, b, x, max_iter=10000, rel_tol=tol, workspace=ws, dinv=pre,
+                                true_residual=True)
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t0
+            leg[name] = {"ms": round(1e3 * dt, 3), "iters": r.iters, "us_per_iter": round(1e6 * dt / max(r.iters, 1), 2),
+                         "rel_res": r.rel_res, "true_rel_res": r.rel_res_true}
+        leg["speedup"] = round(leg["cg"]["ms"] / leg["jacobi_pcg"]["ms"], 3)
+        out[f"E{E}"] = leg
+        gs.close()
+        del g, b, x, ws, dinv
+    torch.cuda.empty_cache()
+    return out
+
+
+def memcpy_rate(torch, dev, stream, nbytes=1 << 30, reps=20):
+    """Device-to-device copy through the runtime (torch's copy_ of one
+    contiguous buffer, a D2D memcpy) of 1 GiB, well above the 256 MB
+    last-level cache: bytes read + written per second."""
+    a = torch.empty(nbytes // 8, dtype=torch.float64, device=dev).uniform_()
+    b = torch.empty_like(a)
+    b.copy_(a)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record(stream)
+    for _ in range(reps):
+        b.copy_(a)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    t = 1e-3 * e0.elapsed_time(e1)
+    del a, b
+    return 2 * nbytes * reps / t / 1e9
+
+
+def sweep_leg(nek, torch, dev, stream, reps=20):
+    """ax_e alone over the degree sweep N = 5..15: per N a box of about 32.8 M
+    local points (u + g + w about 2.1 GB, far above the 256 MB last-level
+    cache, so back-to-back launches stream from HBM), timed per launch with
+    HIP events on the launch stream, next to the 7:1 streaming probe at the
+    same footprint."""
+    import ctypes
+    import numpy as np
+    import synth
+    sp = ctypes.c_void_p(stream.cuda_stream)
+    vp = lambda t: ctypes.c_void_p(t.data_ptr())
+    gen = torch.Generator(device=dev)
+    gen.manual_seed(synth.SEED_U)
+    out = {}
+    for N, box in sorted(synth.SWEEP_BOXES.items()):
+        n = N + 1
+        E = box[0] * box[1] * box[2]
+        P = E * n ** 3
+        g, _, _ = nek.box_geometry(*box, N, synth.AMP, synth.geom_coeffs())
+        D = torch.from_numpy(nek.gll(N)[2]).to(dev)
+        u = torch.rand(P, dtype=torch.float64, device=dev, generator=gen) * 2 - 1
+        w = torch.empty_like(u)
+        cargs = (E, N, vp(u), vp(D), vp(g), vp(w), sp)
+        for _ in range(3):
+            nek._lib.nek_ax(*cargs)
+        evs = [torch.cuda.Event(enable_timing=True) for _ in range(reps + 1)]
+        evs[0].record(stream)
+        for r in range(reps):
+            nek._lib.nek_ax(*cargs)
+            evs[r + 1].record(stream)
+        torch.cuda.synchronize()
+        per = np.array([1e3 * evs[r].elapsed_time(evs[r + 1]) for r in range(reps)])
+        del g, u, w
+        src = torch.empty(7 * P, dtype=torch.float64, device=dev).uniform_()
+        dst = torch.empty(P, dtype=torch.float64, device=dev)
+        nek._lib.nek_bw_probe(P, 7, vp(src), vp(dst), 0, sp)
+        evs[0].record(stream)
+        for r in range(reps):
+            nek._lib.nek_bw_probe(P, 7, vp(src), vp(dst), 0, sp)
+        evs[1].record(stream)
+        torch.cuda.synchronize()
+        probe_gbs = 64 * P * reps / (1e-3 * evs[0].elapsed_time(evs[1])) / 1e9
+        del src, dst
+        torch.cuda.empty_cache()
+        t = float(per.mean()) * 1e-6
+        gbs = 64 * P / t / 1e9
+        out[str(N)] = {"box": list(box), "E": E, "P": P,
+                       "us_mean": round(float(per.mean()), 2), "us_median": round(float(np.median(per)), 2),
+                       "us_p10": round(float(np.percentile(per, 10)), 2),
+                       "us_p90": round(float(np.percentile(per, 90)), 2),
+                       "gbs": round(gbs, 1), "gflops": round((12 * n + 15) * P / t / 1e9, 1),
+                       "frac_of_hbm_peak": round(gbs / HBM_PEAK_GBS, 4),
+                       "measured_stream7_gbs": round(probe_gbs, 1),
+                       "frac_of_measured_roofline": round(gbs / probe_gbs, 4)}
+    return out
+
+
 def serve_leg(nek, torch, n_req, budget_gb, iters_per_step, tol=1e-10, max_iter=10000):
     """Served solves.  Requests: box meshes with E uniform over {64, 512, 1024,
     4096, 8192} and N over {5, 7, 9, 11}, perturbed geometry and rhs U[-1, 1]
@@ -269,11 +415,15 @@ def serve_leg(nek, torch, n_req, budget_gb, iters_per_step, tol=1e-10, max_iter=
 
     1. plain FP64 CG: the requests solved one after another with nek_cg_solve
        (their setup untimed) -- the reference throughput;
-    2. served, all requests arriving at once: the server's capacity (solves/s);
-    3. served under seeded Poisson arrivals at 0.5 and 0.9 of that capacity:
-       latency from submission to the step that saw the solve finish
-       (p50 / p99; with a few dozen requests p99 is close to the maximum).
-    2 and 3 run in FP64 and in the mixed form (FP32 operator, FP32 g)."""
+    2. served, all requests arriving at once, with a budget that holds them
+       all: the server's capacity (solves/s);
+    3. the same with a device-memory budget of budget_gb (below the mix's
+       total footprint, so admission has to queue);
+    4. served under seeded Poisson arrivals at 0.25, 0.5, 1 and 1.5 times the
+       capacity with that budget: latency from submission to the step that saw
+       the solve finish (p50 / p99; with a few dozen requests p99 is close to
+       the maximum).
+    2-4 run in FP64 and in the mixed form (FP32 operator, FP32 g)."""
     import numpy as np
     import synth
 
@@ -317,24 +467,30 @@ def serve_leg(nek, torch, n_req, budget_gb, iters_per_step, tol=1e-10, max_iter=
         "sequential_fp64": {"solves_per_s": round(n_req / seq_s, 3), "total_s": round(seq_s, 3),
                             "iters": seq_iters},
     }
+    big = 64 << 30
     budget = int(budget_gb * (1 << 30))
     for name, prec in (("fp64", nek.NEK_PREC_F64), ("f32_g32", nek.NEK_PREC_F32G32)):
-        sat = _serve_run(nek, reqs, [0.0] * n_req, prec, budget, iters_per_step, tol, max_iter)
+        out[f"footprint_gb_{name}"] = round(sum(nek.server_footprint(*r["box"], r["N"], prec)
+                                                for r in reqs) / (1 << 30), 3)
+        sat = _serve_run(nek, reqs, [0.0] * n_req, prec, big, iters_per_step, tol, max_iter)
         cap = sat["solves_per_s"]
         leg = {"saturated": sat, "speedup_vs_sequential_fp64": round(cap * seq_s / n_req, 3)}
+        iters = sat.pop("iters")
         if prec == nek.NEK_PREC_F64:
-            leg["iters_equal_to_sequential"] = sat.pop("iters") == seq_iters
-        else:
-            sat.pop("iters")
+            leg["iters_equal_to_sequential"] = iters == seq_iters
+        q = _serve_run(nek, reqs, [0.0] * n_req, prec, budget, iters_per_step, tol, max_iter)
+        q.pop("iters")
+        leg["saturated_in_budget"] = q
         pois = []
-        for frac in (0.5, 0.9):
+        for frac in (0.25, 0.5, 1.0, 1.5):
             rate = frac * cap
             run = _serve_run(nek, reqs, [r["t"] / rate for r in reqs], prec, budget, iters_per_step,
                              tol, max_iter)
             run.pop("iters")
             run["offered_rate"] = round(rate, 3)
+            run["offered_frac_of_capacity"] = frac
             pois.append(run)
-        leg["poisson"] = pois
+        leg["poisson_in_budget"] = pois
         out[name] = leg
     return out
 
@@ -348,7 +504,7 @@ def _serve_run(nek, reqs, times, precision, budget, iters_per_step, tol, max_ite
     n = len(reqs)
     srv = nek.Server(budget)
     ids, got = {}, {}
-    k = 0
+    k = max_active = 0
     t0 = srv.clock()
     while len(got) < n:
         now = srv.clock() - t0
@@ -358,6 +514,7 @@ def _serve_run(nek, reqs, times, precision, budget, iters_per_step, tol, max_ite
                            rel_tol=tol, max_iter=max_iter)] = k
             k += 1
         act, que = srv.step(iters_per_step)
+        max_active = max(max_active, act)
         for q in srv.poll():
             got[ids[q["id"]]] = q
             srv.fetch(q["id"])
@@ -369,6 +526,7 @@ def _serve_run(nek, reqs, times, precision, budget, iters_per_step, tol, max_ite
     wait = np.array([q["t_admit"] - q["t_submit"] for q in res])
     span = max(q["t_done"] for q in res) - min(q["t_submit"] for q in res)
     return {"solves_per_s": round(n / span, 3), "makespan_s": round(span, 3),
+            "max_active": max_active,
             "p50_ms": round(1e3 * float(np.percentile(lat, 50)), 2),
             "p99_ms": round(1e3 * float(np.percentile(lat, 99)), 2),
             "mean_admission_wait_ms": round(1e3 * float(wait.mean()), 2),
@@ -429,7 +587,14 @@ def cpu_baseline(Ex, Ey, Ez, N, budget_s):
     dt = time.perf_counter() - t0
     n = N + 1
     gflops = k * mesh.P * (12 * n + 34) / dt / 1e9
+    # the same on one core, over fewer iterations
+    k1 = 10
+    t1 = time.perf_counter()
+    oracle.cg(mesh, b, max_iter=k1, nthreads=1)
+    dt1 = time.perf_counter() - t1
     return {"value": round(gflops, 3), "unit": "GFLOP/s", "cores": oracle.max_threads(),
+            "single_core_value": round(k1 * mesh.P * (12 * n + 34) / dt1 / 1e9, 3),
+            "single_core_sample": f"{k1} FP64 CG iterations of the oracle on one thread ({dt1:.1f} s)",
             "kind": "oracle",
             "sample": f"{solves} x 100 FP64 CG iterations of the oracle on the same E={mesh.E} N={N} "
                       f"mesh ({dt:.1f} s; OpenMP threads over elements in the local operator, the rest "

@@ -179,6 +179,9 @@ typedef struct {
     void *workspace;       /* device scratch of nek_cg_workspace_bytes() bytes, or NULL
                               to let the call allocate and free its own */
     size_t workspace_bytes;
+    const double *dinv;    /* NULL: plain CG.  Else the Jacobi preconditioner from
+                              nek_jacobi_inverse (device, P doubles, 16-byte aligned):
+                              preconditioned CG, FP64 precision only */
 } nek_cg_opts;
 
 typedef struct {
@@ -189,7 +192,8 @@ typedef struct {
     int n_replacements;    /* reliable updates of r (mixed precision), else 0 */
 } nek_cg_stats;
 
-/* Fill opts with defaults: 100 iterations, rel_tol 0, FP64, no workspace. */
+/* Fill opts with defaults: 100 iterations, rel_tol 0, FP64, no workspace, no
+ * preconditioner. */
 void nek_cg_default_opts(nek_cg_opts *opts);
 
 /* Device bytes of scratch nek_cg_solve needs for E elements of degree N. */
@@ -203,10 +207,28 @@ size_t nek_cg_workspace_bytes(int64_t E, int N);
  * opts->check_every iterations.  Blocking: returns after the work on stream
  * has finished.  stats may be NULL.  Returns NEK_OK, or the failure code
  * (also stored in stats->status) -- NEK_ERR_NOCONV when rel_tol > 0 was not
- * reached. */
+ * reached.
+ *
+ * With opts->dinv set: preconditioned CG with M^-1 = dinv (the preconditioning
+ * Sec. VII leaves as future work, in its simplest, Jacobi form):
+ * z = dinv r, alpha = (r, z) / (p, A p), p <- z + beta p with
+ * beta = (r', z') / (r, z).  The stopping test and stats->rel_res still use
+ * sqrt((r, r) / (b, b)). */
 int nek_cg_solve(int64_t E, int N, const double *D, const double *g, const nek_gs *gs,
                  const double *b, double *x, const nek_cg_opts *opts, nek_cg_stats *stats,
                  void *stream);
+
+/* Jacobi preconditioner of the assembled, masked operator: on device
+ * dinv[P], 1 / (dssum of the diagonals of the element operators of Listing 1)
+ * at free nodes and 0 at masked nodes, a continuous local vector.  The
+ * diagonal of A_e at p = (i,j,k) is the quadrature form of A_e on the unit
+ * vector e_p: sum over m of dxm1(m,i)^2 g_rr(m,j,k), dxm1(m,j)^2 g_ss(i,m,k),
+ * dxm1(m,k)^2 g_tt(i,j,m), plus 2 dxm1(i,i) dxm1(j,j) g_rs + 2 dxm1(i,i)
+ * dxm1(k,k) g_rt + 2 dxm1(j,j) dxm1(k,k) g_st at p.  D, g as in nek_ax; gs
+ * built for the same mesh.  dinv: device, P doubles, 16-byte aligned, output
+ * (also the working buffer).  Allocates nothing.  Asynchronous. */
+int nek_jacobi_inverse(int64_t E, int N, const double *D, const double *g, const nek_gs *gs,
+                       double *dinv, void *stream);
 
 /* ------------------------------------------------------------ served solves */
 

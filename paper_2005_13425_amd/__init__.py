@@ -54,7 +54,7 @@ class CgOpts(ctypes.Structure):
                 ("precision", ctypes.c_int), ("D32", _vp), ("g_lo", _vp),
                 ("check_every", ctypes.c_int), ("true_residual", ctypes.c_int),
                 ("reliable_drop", ctypes.c_double), ("workspace", _vp),
-                ("workspace_bytes", ctypes.c_size_t)]
+                ("workspace_bytes", ctypes.c_size_t), ("dinv", _vp)]
 
 
 class CgStats(ctypes.Structure):
@@ -98,6 +98,7 @@ _sig("nek_gs_info", _ci, [_vp] + [ctypes.POINTER(_i64)] * 4)
 _sig("nek_dssum", _ci, [_vp, _vp, _vp])
 _sig("nek_gs_dot", _ci, [_vp, _vp, _vp, _vp, _vp])
 _sig("nek_bw_probe", _ci, [_i64, _ci, _vp, _vp, _ci, _vp])
+_sig("nek_jacobi_inverse", _ci, [_i64, _ci, _vp, _vp, _vp, _vp, _vp])
 _sig("nek_server_create", _ci, [ctypes.c_size_t, ctypes.POINTER(_vp)])
 _sig("nek_server_submit", _ci, [_vp, ctypes.POINTER(Request), ctypes.POINTER(ctypes.c_uint64)])
 _sig("nek_server_footprint", ctypes.c_size_t, [_ci, _ci, _ci, _ci, _ci])
@@ -322,8 +323,9 @@ def cg_workspace_bytes(E: int, N: int) -> int:
 def cg_solve(D, g, gs: GatherScatter, b, x=None, max_iter: int = 100, rel_tol: float = 0.0,
              precision: int = NEK_PREC_F64, D32=None, g_lo=None, check_every: int = 0,
              true_residual: bool = False, reliable_drop: float = 0.0, workspace=None,
-             raise_on_error: bool = True, stream=None):
-    """Unpreconditioned CG on mask(dssum(A_L x)) = b with x_0 = 0, on the device.
+             raise_on_error: bool = True, stream=None, dinv=None):
+    """CG on mask(dssum(A_L x)) = b with x_0 = 0, on the device; with dinv (from
+    jacobi_inverse) Jacobi-preconditioned CG.
 
     Returns (x, CgResult).  With raise_on_error=False a breakdown or
     non-convergence is reported in CgResult.status instead of raising."""
@@ -344,6 +346,8 @@ def cg_solve(D, g, gs: GatherScatter, b, x=None, max_iter: int = 100, rel_tol: f
     o.check_every = int(check_every)
     o.true_residual = 1 if true_residual else 0
     o.reliable_drop = float(reliable_drop)
+    if dinv is not None:
+        o.dinv = _dev(dinv, torch.float64, "dinv", P)
     if workspace is not None:
         if workspace.numel() * workspace.element_size() < cg_workspace_bytes(E, N):
             raise ValueError("workspace too small")
@@ -357,6 +361,20 @@ def cg_solve(D, g, gs: GatherScatter, b, x=None, max_iter: int = 100, rel_tol: f
     if rc != NEK_OK and (raise_on_error or rc not in (NEK_ERR_BREAKDOWN, NEK_ERR_NOCONV)):
         raise NekError(rc, "nek_cg_solve")
     return x, res
+
+
+def jacobi_inverse(D, g, gs: GatherScatter, out=None, stream=None):
+    """The Jacobi preconditioner of the assembled, masked operator as a device
+    vector: 1 / assembled diagonal at free nodes, 0 at masked nodes."""
+    torch = _torch()
+    E, N, P = gs.E, gs.N, gs.P
+    if out is None:
+        out = torch.empty(P, dtype=torch.float64, device=g.device)
+    _check(_lib.nek_jacobi_inverse(E, N, _dev(D, torch.float64, "D", (N + 1) ** 2),
+                                   _dev(g, torch.float64, "g", 6 * P), gs.handle,
+                                   _dev(out, torch.float64, "dinv", P), _stream_ptr(stream)),
+           "nek_jacobi_inverse")
+    return out
 
 
 def cg_workspace(E: int, N: int, device="cuda"):

@@ -475,12 +475,29 @@ int nek_dssum(const nek_gs *gs, double *w, void *stream) {
 
 static bool aligned16(const void *p) { return ((uintptr_t)p & 15u) == 0; }
 
+int nek_jacobi_inverse(int64_t E, int N, const double *D, const double *g, const nek_gs *gs,
+                       double *dinv, void *stream) {
+    clear_error();
+    if (E < 1) return fail(NEK_ERR_ARG, "nek_jacobi_inverse: E must be >= 1");
+    if (N < 1 || N > NEK_MAX_DEGREE) return fail(NEK_ERR_UNSUPPORTED, "nek_jacobi_inverse: degree must be in 1..15");
+    if (!D || !g || !gs || !dinv) return fail(NEK_ERR_ARG, "nek_jacobi_inverse: null argument");
+    if (!aligned8(D) || !aligned8(g) || !aligned16(dinv))
+        return fail(NEK_ERR_ARG, "nek_jacobi_inverse: misaligned pointer (dinv needs 16 bytes)");
+    if (gs->d.E != E || gs->d.N != N)
+        return fail(NEK_ERR_ARG, "nek_jacobi_inverse: gather-scatter built for another mesh");
+    const hipStream_t s = (hipStream_t)stream;
+    NEK_HIP(launch_ax_diag(E, N, D, g, dinv, s));
+    NEK_HIP(launch_gs(gs->d, dinv, nullptr, 0, nullptr, s));   // assembled diagonal, 0 at masked nodes
+    NEK_HIP(launch_reciprocal(E * n3_of(N), dinv, s));
+    return NEK_OK;
+}
+
 int nek_gs_dot(const nek_gs *gs, const double *a, const double *b, double *result, void *stream) {
     clear_error();
     if (!gs || !a || !b || !result) return fail(NEK_ERR_ARG, "nek_gs_dot: null argument");
     if (!aligned16(a) || !aligned16(b) || !aligned8(result))
         return fail(NEK_ERR_ARG, "nek_gs_dot: a and b must be 16-byte aligned");
-    const RedSite red{gs->partials, gs->partials + RED_MAX_BLOCKS, gs->ticket, nullptr, 0};
+    const RedSite red = red_site(gs->partials, gs->ticket);
     NEK_HIP(launch_gdot(gs->d.P, a, b, gs->d.own_bits, red, result, (hipStream_t)stream));
     return NEK_OK;
 }
@@ -542,6 +559,9 @@ int nek_cg_solve(int64_t E, int N, const double *D, const double *g, const nek_g
     if (mixed && (((uintptr_t)opts.g_lo & (opts.precision == NEK_PREC_F32G32 ? 7u : 3u)) ||
                   ((uintptr_t)opts.D32 & 3u)))
         return fail(NEK_ERR_ARG, "nek_cg_solve: misaligned g_lo or D32");
+    if (opts.dinv && mixed)
+        return fail(NEK_ERR_UNSUPPORTED, "nek_cg_solve: the Jacobi preconditioner is FP64 only");
+    if (opts.dinv && !aligned16(opts.dinv)) return fail(NEK_ERR_ARG, "nek_cg_solve: misaligned dinv");
     const int g_dtype = opts.precision == NEK_PREC_F32G32 ? NEK_G_F32 : NEK_G_BF16;
     const double drop = mixed ? (opts.reliable_drop > 0.0 ? opts.reliable_drop : 0.1) : 0.0;
     if (mixed && !(drop < 1.0)) return fail(NEK_ERR_ARG, "nek_cg_solve: reliable_drop must be < 1");
@@ -590,13 +610,14 @@ int nek_cg_solve(int64_t E, int N, const double *D, const double *g, const nek_g
         if (!first) {
             fz.r = r;
             fz.x = x;
+            fz.dinv = opts.dinv;
         }
         hipError_t e = mixed ? launch_ax_f32(E, N, opts.D32, opts.g_lo, g_dtype, p, w, fz, s)
                              : launch_ax_f64(E, N, D, g, p, w, fz, s);
         if (e != hipSuccess) return e;
         e = launch_gs(gs->d, w, axp, ax_parts, sc, s);
         if (e != hipSuccess) return e;
-        return launch_cg_update(P, r, w, own, red_upd, sc, s);
+        return launch_cg_update(P, r, w, own, opts.dinv, red_upd, sc, s);
     };
     // w <- mask(dssum(A64 x)) with x brought up to date first
     auto true_ax = [&]() -> hipError_t {
@@ -620,7 +641,7 @@ int nek_cg_solve(int64_t E, int N, const double *D, const double *g, const nek_g
     hipEvent_t ev[2] = {nullptr, nullptr};
     {
         CG_TRY(launch_cg_reset(sc, tickets, N_SITES * RED_TICKETS, opts.max_iter, opts.rel_tol, drop, s));
-        CG_TRY(launch_cg_init(P, b, x, r, p, own, site(SITE_INIT, nullptr, 0), sc, s));
+        CG_TRY(launch_cg_init(P, b, x, r, p, own, opts.dinv, site(SITE_INIT, nullptr, 0), sc, s));
         if (poll) {
             CG_TRY(hipEventCreateWithFlags(&ev[0], hipEventDisableTiming));
             CG_TRY(hipEventCreateWithFlags(&ev[1], hipEventDisableTiming));
@@ -687,7 +708,7 @@ out:
     }
     {
         int status = S.status;
-        const double rel = S.bb > 0.0 ? sqrt(S.rho / S.bb) : 0.0;
+        const double rel = S.bb > 0.0 ? sqrt(S.rr / S.bb) : 0.0;
         if (status == NEK_OK && opts.rel_tol > 0.0) {
             const double judged = mixed ? true_rel : rel;
             if (!(judged <= opts.rel_tol)) status = NEK_ERR_NOCONV;

@@ -125,6 +125,7 @@ __global__ void cg_reset_kernel(CgScalars *sc, unsigned int *tickets, int nticke
     if (threadIdx.x != 0) return;
     sc->bb = 0.0;
     sc->rho = 0.0;
+    sc->rr = 0.0;
     sc->pw = 0.0;
     sc->alpha = 0.0;
     sc->beta = 0.0;
@@ -138,7 +139,7 @@ __global__ void cg_reset_kernel(CgScalars *sc, unsigned int *tickets, int nticke
     sc->need_replace = 0;
     sc->n_replace = 0;
     sc->lag_applied = 1;
-    sc->pad_ = 0;
+    sc->pad_[0] = sc->pad_[1] = sc->pad_[2] = 0;
 }
 
 // Pairs of a chunk: chunk c covers pairs [c * VEC_THREADS * VEC_PAIRS, ...);
@@ -159,20 +160,33 @@ __device__ __forceinline__ bool own_bit(OwnPtr own, int64_t t) {
 #define NEK_CHUNKS                                                                       \
     for (int64_t base = blockIdx.x * VEC_CHUNK; base < npairs; base += (int64_t)gridDim.x * VEC_CHUNK)
 
-// x = 0, r = b, p = b, rho = (b, b)
+// x = 0, r = b, p = z = M^-1 b (z = b without a preconditioner),
+// bb = rr = (b, b), rho = (b, z)
+template <bool PRE>
 __global__ void __launch_bounds__(VEC_THREADS)
 cg_init_kernel(int64_t P, const double *__restrict__ b, double *__restrict__ x,
                double *__restrict__ r, double *__restrict__ p, const uint32_t *__restrict__ own,
-               RedSite red, CgScalars *sc) {
+               const double *__restrict__ dinv, RedSite red, CgScalars *sc) {
+    constexpr int K = PRE ? 2 : 1;
     __shared__ double lds[VEC_THREADS / 64];
     const int64_t npairs = P >> 1;
-    double acc = 0.0;
+    double acc[K];
+#pragma unroll
+    for (int c = 0; c < K; ++c) acc[c] = 0.0;
     NEK_CHUNKS {
-        double2 bv[VEC_PAIRS];
+        double2 bv[VEC_PAIRS], zv[VEC_PAIRS];
 #pragma unroll
         for (int m = 0; m < VEC_PAIRS; ++m) {
             const int64_t q = base + threadIdx.x + (int64_t)m * VEC_THREADS;
-            if (q < npairs) bv[m] = ((const double2 *)b)[q];
+            if (q < npairs) {
+                bv[m] = ((const double2 *)b)[q];
+                if constexpr (PRE) {
+                    const double2 dv = ((const double2 *)dinv)[q];
+                    zv[m] = make_double2(dv.x * bv[m].x, dv.y * bv[m].y);
+                } else {
+                    zv[m] = bv[m];
+                }
+            }
         }
 #pragma unroll
         for (int m = 0; m < VEC_PAIRS; ++m) {
@@ -180,53 +194,76 @@ cg_init_kernel(int64_t P, const double *__restrict__ b, double *__restrict__ x,
             if (q < npairs) {
                 ((double2 *)x)[q] = make_double2(0.0, 0.0);
                 ((double2 *)r)[q] = bv[m];
-                ((double2 *)p)[q] = bv[m];
+                ((double2 *)p)[q] = zv[m];
                 const unsigned o = own_pair(own, 2 * q);
-                if (o & 1u) acc += bv[m].x * bv[m].x;
-                if (o & 2u) acc += bv[m].y * bv[m].y;
+                if (o & 1u) {
+                    acc[0] += bv[m].x * bv[m].x;
+                    if constexpr (PRE) acc[K - 1] += bv[m].x * zv[m].x;
+                }
+                if (o & 2u) {
+                    acc[0] += bv[m].y * bv[m].y;
+                    if constexpr (PRE) acc[K - 1] += bv[m].y * zv[m].y;
+                }
             }
         }
     }
     if (owns_tail(P)) {
         const int64_t t = P - 1;
         const double bv = b[t];
+        const double zv = PRE ? dinv[t] * bv : bv;
         x[t] = 0.0;
         r[t] = bv;
-        p[t] = bv;
-        if (own_bit(own, t)) acc += bv * bv;
+        p[t] = zv;
+        if (own_bit(own, t)) {
+            acc[0] += bv * bv;
+            if constexpr (PRE) acc[K - 1] += bv * zv;
+        }
     }
-    const double s = block_sum<VEC_THREADS>(acc, lds);
-    double tot;
-    if (grid_finish<VEC_THREADS>(s, red, &tot, lds) && threadIdx.x == 0) {
-        sc->bb = tot;
-        sc->rho = tot;
-        sc->rho_last_true = tot;
-        sc->rel_tol2 = sc->rel_tol2 * tot;
-        if (!(tot > 0.0)) {           // b = 0 (x = 0 is the solution) or non-finite
+    double s[K], tot[K];
+#pragma unroll
+    for (int c = 0; c < K; ++c) s[c] = block_sum<VEC_THREADS>(acc[c], lds);
+    if (grid_finish_k<VEC_THREADS, K>(s, red, tot, lds, blockIdx.x, gridDim.x) && threadIdx.x == 0) {
+        const double bb = tot[0];
+        sc->bb = bb;
+        sc->rr = bb;
+        sc->rho = tot[K - 1];
+        sc->rho_last_true = bb;
+        sc->rel_tol2 = sc->rel_tol2 * bb;
+        if (!(bb > 0.0)) {            // b = 0 (x = 0 is the solution) or non-finite
             sc->done = 1;
-            if (!__builtin_isfinite(tot)) sc->status = NEK_ERR_BREAKDOWN;
+            if (!__builtin_isfinite(bb)) sc->status = NEK_ERR_BREAKDOWN;
+        } else if (!__builtin_isfinite(tot[K - 1])) {
+            sc->done = 1;
+            sc->status = NEK_ERR_BREAKDOWN;
         }
         if (sc->max_iter <= 0) sc->done = 1;
     }
 }
 
-// r -= alpha w; rho' = (r, r); beta = rho' / rho; convergence and iteration cap
+// r -= alpha w; rr = (r, r); rho' = (r, z) with z = M^-1 r (= rr without a
+// preconditioner); beta = rho' / rho; convergence on rr and the iteration cap
+template <bool PRE>
 __device__ __forceinline__ void update_body(int lb, int nb, int64_t P, gptr<double> r,
                                             gptr<const double> w, gptr<const uint32_t> own,
-                                            const RedSite &red, gptr<CgScalars> sc) {
+                                            gptr<const double> dinv, const RedSite &red,
+                                            gptr<CgScalars> sc) {
+    constexpr int K = PRE ? 2 : 1;
     if (sc->done) return;
     __shared__ double lds[VEC_THREADS / 64];
     const double alpha = sc->alpha;
     const int64_t npairs = P >> 1;
-    double acc = 0.0;
+    double acc[K];
+#pragma unroll
+    for (int c = 0; c < K; ++c) acc[c] = 0.0;
     for (int64_t base = (int64_t)lb * VEC_CHUNK; base < npairs; base += (int64_t)nb * VEC_CHUNK) {
-        double2 rv[VEC_PAIRS], wv[VEC_PAIRS];
+        double2 rv[VEC_PAIRS], wv[VEC_PAIRS], dv[VEC_PAIRS];
 #pragma unroll
         for (int m = 0; m < VEC_PAIRS; ++m) {
             const int64_t q = base + threadIdx.x + (int64_t)m * VEC_THREADS;
             if (q < npairs) {
                 rv[m] = ((gptr<const double2>)r)[q];
                 wv[m] = ((gptr<const double2>)w)[q];
+                if constexpr (PRE) dv[m] = ((gptr<const double2>)dinv)[q];
             }
         }
 #pragma unroll
@@ -238,8 +275,14 @@ __device__ __forceinline__ void update_body(int lb, int nb, int64_t P, gptr<doub
                 nr.y = rv[m].y - alpha * wv[m].y;
                 ((gptr<double2>)r)[q] = nr;
                 const unsigned o = own_pair(own, 2 * q);
-                if (o & 1u) acc += nr.x * nr.x;
-                if (o & 2u) acc += nr.y * nr.y;
+                if (o & 1u) {
+                    acc[0] += nr.x * nr.x;
+                    if constexpr (PRE) acc[K - 1] += nr.x * (dv[m].x * nr.x);
+                }
+                if (o & 2u) {
+                    acc[0] += nr.y * nr.y;
+                    if constexpr (PRE) acc[K - 1] += nr.y * (dv[m].y * nr.y);
+                }
             }
         }
     }
@@ -247,41 +290,50 @@ __device__ __forceinline__ void update_body(int lb, int nb, int64_t P, gptr<doub
         const int64_t t = P - 1;
         const double nr = r[t] - alpha * w[t];
         r[t] = nr;
-        if (own_bit(own, t)) acc += nr * nr;
+        if (own_bit(own, t)) {
+            acc[0] += nr * nr;
+            if constexpr (PRE) acc[K - 1] += nr * (dinv[t] * nr);
+        }
     }
-    const double s = block_sum<VEC_THREADS>(acc, lds);
-    double tot;
-    if (grid_finish<VEC_THREADS>(s, red, &tot, lds, lb, nb) && threadIdx.x == 0) {
+    double s[K], tot[K];
+#pragma unroll
+    for (int c = 0; c < K; ++c) s[c] = block_sum<VEC_THREADS>(acc[c], lds);
+    if (grid_finish_k<VEC_THREADS, K>(s, red, tot, lds, lb, nb) && threadIdx.x == 0) {
+        const double rr = tot[0], rz = tot[K - 1];
         sc->it += 1;
-        if (!__builtin_isfinite(tot)) {
+        if (!__builtin_isfinite(rr) || !__builtin_isfinite(rz)) {
             sc->status = NEK_ERR_BREAKDOWN;
             sc->done = 1;
         } else {
-            sc->beta = tot / sc->rho;
-            sc->rho = tot;
-            if (sc->rel_tol2 > 0.0 && tot <= sc->rel_tol2) {
+            sc->beta = rz / sc->rho;
+            sc->rho = rz;
+            sc->rr = rr;
+            if (sc->rel_tol2 > 0.0 && rr <= sc->rel_tol2) {
                 if (sc->drop2 > 0.0) sc->need_replace = 1;   // mixed: confirm with the true residual
                 else sc->done = 1;
             }
-            if (sc->drop2 > 0.0 && tot <= sc->drop2 * sc->rho_last_true) sc->need_replace = 1;
-            if (tot == 0.0) sc->done = 1;
+            if (sc->drop2 > 0.0 && rr <= sc->drop2 * sc->rho_last_true) sc->need_replace = 1;
+            if (rr == 0.0) sc->done = 1;
             if (sc->it >= sc->max_iter) sc->done = 1;
         }
     }
 }
 
+template <bool PRE>
 __global__ void __launch_bounds__(VEC_THREADS)
 cg_update_kernel(int64_t P, double *__restrict__ r, const double *__restrict__ w,
-                 const uint32_t *__restrict__ own, RedSite red, CgScalars *sc) {
-    update_body(blockIdx.x, gridDim.x, P, (gptr<double>)r, (gptr<const double>)w,
-                (gptr<const uint32_t>)own, red, (gptr<CgScalars>)sc);
+                 const uint32_t *__restrict__ own, const double *__restrict__ dinv, RedSite red,
+                 CgScalars *sc) {
+    update_body<PRE>(blockIdx.x, gridDim.x, P, (gptr<double>)r, (gptr<const double>)w,
+                     (gptr<const uint32_t>)own, (gptr<const double>)dinv, red, (gptr<CgScalars>)sc);
 }
 
 __global__ void __launch_bounds__(VEC_THREADS)
 update_batch_kernel(const UpdSlot *__restrict__ slots, int nslots) {
     const UpdSlot S = slots[batch_slot(slots, nslots, (int64_t)blockIdx.x)];
-    update_body((int)((int64_t)blockIdx.x - S.block0), (int)S.nblocks, S.P, (gptr<double>)S.r,
-                (gptr<const double>)S.w, (gptr<const uint32_t>)S.own, S.red, (gptr<CgScalars>)S.sc);
+    update_body<false>((int)((int64_t)blockIdx.x - S.block0), (int)S.nblocks, S.P, (gptr<double>)S.r,
+                       (gptr<const double>)S.w, (gptr<const uint32_t>)S.own, nullptr, S.red,
+                       (gptr<CgScalars>)S.sc);
 }
 
 __global__ void gather_scalars_kernel(CgScalars *const *src, int n, CgScalars *dst) {
@@ -353,6 +405,7 @@ cg_replace_kernel(int64_t P, const double *__restrict__ b, const double *__restr
     double tot;
     if (grid_finish<VEC_THREADS>(s, red, &tot, lds) && threadIdx.x == 0) {
         sc->rho = tot;
+        sc->rr = tot;
         sc->rho_last_true = tot;
         sc->need_replace = 0;
         sc->n_replace += 1;
@@ -450,16 +503,25 @@ hipError_t launch_cg_reset(CgScalars *sc, unsigned int *tickets, int nticket, in
 }
 
 hipError_t launch_cg_init(int64_t P, const double *b, double *x, double *r, double *p,
-                          const uint32_t *own, const RedSite &red, CgScalars *sc, hipStream_t s) {
-    hipLaunchKernelGGL(cg_init_kernel, dim3((unsigned)vec_blocks(P)), dim3(VEC_THREADS), 0, s, P, b, x,
-                       r, p, own, red, sc);
+                          const uint32_t *own, const double *dinv, const RedSite &red, CgScalars *sc,
+                          hipStream_t s) {
+    if (dinv != nullptr)
+        hipLaunchKernelGGL(cg_init_kernel<true>, dim3((unsigned)vec_blocks(P)), dim3(VEC_THREADS), 0, s,
+                           P, b, x, r, p, own, dinv, red, sc);
+    else
+        hipLaunchKernelGGL(cg_init_kernel<false>, dim3((unsigned)vec_blocks(P)), dim3(VEC_THREADS), 0, s,
+                           P, b, x, r, p, own, dinv, red, sc);
     return hipGetLastError();
 }
 
 hipError_t launch_cg_update(int64_t P, double *r, const double *w, const uint32_t *own,
-                            const RedSite &red, CgScalars *sc, hipStream_t s) {
-    hipLaunchKernelGGL(cg_update_kernel, dim3((unsigned)vec_blocks(P)), dim3(VEC_THREADS), 0, s, P, r,
-                       w, own, red, sc);
+                            const double *dinv, const RedSite &red, CgScalars *sc, hipStream_t s) {
+    if (dinv != nullptr)
+        hipLaunchKernelGGL(cg_update_kernel<true>, dim3((unsigned)vec_blocks(P)), dim3(VEC_THREADS), 0,
+                           s, P, r, w, own, dinv, red, sc);
+    else
+        hipLaunchKernelGGL(cg_update_kernel<false>, dim3((unsigned)vec_blocks(P)), dim3(VEC_THREADS), 0,
+                           s, P, r, w, own, dinv, red, sc);
     return hipGetLastError();
 }
 

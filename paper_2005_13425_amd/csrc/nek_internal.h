@@ -33,7 +33,8 @@ inline int64_t n3_of(int N) { return (int64_t)(N + 1) * (N + 1) * (N + 1); }
 // last workgroup of a reduction kernel or by single-thread kernels).
 struct CgScalars {
     double bb;            // (b, b)
-    double rho;           // (r, r) of the current residual
+    double rho;           // (r, r) of the current residual; (r, M^-1 r) with a preconditioner
+    double rr;            // (r, r) of the current residual (the stopping test)
     double pw;            // (p, w)
     double alpha;
     double beta;
@@ -47,12 +48,13 @@ struct CgScalars {
     int need_replace;     // mixed precision: r should be replaced by b - A64 x
     int n_replace;
     int lag_applied;      // 0: x still lacks alpha * p of the last (p, w)
-    int pad_;
+    int pad_[3];          // size a multiple of 16 bytes
 };
 
 // ---------------------------------------------------------------- ax_e
 // Optional CG fusion of the local-operator launch (all device pointers):
 //   r != null : p <- r + beta p on the way in (beta from sc);
+//   dinv != null (with r) : p <- dinv r + beta p (Jacobi-preconditioned CG);
 //   x != null : x += alpha p_old first, if sc->lag_applied == 0;
 //   partials != null : per-workgroup sum of p * (A_L p) over all local
 //                      points, at partials[blockIdx];
@@ -62,6 +64,7 @@ struct AxFuse {
     double *x = nullptr;
     double *partials = nullptr;
     const CgScalars *sc = nullptr;
+    const double *dinv = nullptr;
 };
 
 hipError_t launch_ax_f64(int64_t E, int N, const double *D, const double *g, double *p, double *w,
@@ -197,10 +200,12 @@ int64_t vec_blocks(int64_t P);          // workgroups of the vector kernels (<= 
 
 hipError_t launch_cg_reset(CgScalars *sc, unsigned int *tickets, int nticket, int max_iter,
                            double rel_tol, double drop, hipStream_t s);
+// dinv (may be null): the Jacobi preconditioner M^-1 as a continuous local vector
 hipError_t launch_cg_init(int64_t P, const double *b, double *x, double *r, double *p,
-                          const uint32_t *own, const RedSite &red, CgScalars *sc, hipStream_t s);
+                          const uint32_t *own, const double *dinv, const RedSite &red, CgScalars *sc,
+                          hipStream_t s);
 hipError_t launch_cg_update(int64_t P, double *r, const double *w, const uint32_t *own,
-                            const RedSite &red, CgScalars *sc, hipStream_t s);
+                            const double *dinv, const RedSite &red, CgScalars *sc, hipStream_t s);
 
 struct UpdSlot {
     int64_t block0;
@@ -226,7 +231,13 @@ hipError_t launch_gdiff2(int64_t P, const double *a, const double *b, const uint
                          const RedSite &red, double *result, hipStream_t s);
 
 // storage of one reduction site inside a workspace
-constexpr size_t RED_SITE_DOUBLES = RED_MAX_BLOCKS + RED_MAX_GROUPS;
+// one reduction site: RED_MAX_SUMS partials per workgroup, then per group
+constexpr size_t RED_SITE_DOUBLES = (size_t)RED_MAX_SUMS * (RED_MAX_BLOCKS + RED_MAX_GROUPS);
+
+inline RedSite red_site(double *mem, unsigned int *tickets, const double *extra = nullptr,
+                        long nextra = 0) {
+    return RedSite{mem, mem + (size_t)RED_MAX_SUMS * RED_MAX_BLOCKS, tickets, extra, nextra};
+}
 
 inline size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
@@ -257,8 +268,8 @@ struct CgWs {
     unsigned int *tickets;
     CgScalars *sc;
     RedSite site(int k, const double *extra = nullptr, long nextra = 0) const {
-        double *base = site_mem + (size_t)k * RED_SITE_DOUBLES;
-        return RedSite{base, base + RED_MAX_BLOCKS, tickets + (size_t)k * RED_TICKETS, extra, nextra};
+        return red_site(site_mem + (size_t)k * RED_SITE_DOUBLES, tickets + (size_t)k * RED_TICKETS,
+                        extra, nextra);
     }
 };
 
@@ -291,6 +302,10 @@ hipError_t launch_box_geometry(int Ex, int Ey, int Ez, int N, double amp, double
                                hipStream_t s);
 
 hipError_t launch_probe(int64_t n, int nread, const double *src, double *dst, int grid, hipStream_t s);
+// diagonal of the element operator at every local point, and the reciprocal
+// of a continuous vector in place (0 stays 0)
+hipError_t launch_ax_diag(int64_t E, int N, const double *D, const double *g, double *d, hipStream_t s);
+hipError_t launch_reciprocal(int64_t P, double *v, hipStream_t s);
 
 // host GLL routine shared by the setup entry points
 int gll_host(int N, double *z, double *w, double *D);

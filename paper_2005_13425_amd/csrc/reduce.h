@@ -60,11 +60,15 @@ __device__ __forceinline__ unsigned int take_ticket(gptr<unsigned int> t) {
     return __hip_atomic_fetch_add(t, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-// Storage of one reduction site (all device memory):
-//   part[gridDim.x]   per-workgroup partials
-//   gpart[groups]     per-group sums
-//   tk[RED_TICKETS]   zero-initialised counters (reset after use)
-//   extra[nextra]     partials written by an earlier launch, added last
+// Storage of one reduction site (all device memory), for up to RED_MAX_SUMS
+// sums reduced together (component c of workgroup lb at part[lb*K + c]):
+//   part[K * gridDim.x]   per-workgroup partials
+//   gpart[K * groups]     per-group sums
+//   tk[RED_TICKETS]       zero-initialised counters (reset after use)
+//   extra[nextra]         partials written by an earlier launch, added last
+//                         to the first sum
+constexpr int RED_MAX_SUMS = 2;
+
 struct RedSite {
     double *part;
     double *gpart;
@@ -73,8 +77,9 @@ struct RedSite {
     long nextra;
 };
 
-// Publish s (valid in thread 0).  Returns true in every thread of the one
-// workgroup that completes the reduction; thread 0 of it has the total in *out.
+// Publish K sums s[0..K) (valid in thread 0).  Returns true in every thread of
+// the one workgroup that completes the reduction; thread 0 of it has the
+// totals in out[0..K).
 //
 // Partials go out with agent-scope atomic stores (through the per-XCD L2 to
 // the device-coherent level) and each thread waits for its stores before it
@@ -83,10 +88,12 @@ struct RedSite {
 //
 // lb / nb: this workgroup's index and the number of workgroups taking part
 // (blockIdx.x / gridDim.x for a plain launch, the slot-local values in a
-// launch that serves several solves).
-template <int NT>
-__device__ bool grid_finish(double s, const RedSite &r, double *out, double *lds, unsigned int lb,
-                            unsigned int nb) {
+// launch that serves several solves).  Every component is summed in the same
+// fixed order, so K = 1 and the first component of K = 2 agree bitwise.
+template <int NT, int K>
+__device__ bool grid_finish_k(const double *s, const RedSite &r, double *out, double *lds,
+                              unsigned int lb, unsigned int nb) {
+    static_assert(K >= 1 && K <= RED_MAX_SUMS, "at most RED_MAX_SUMS sums per site");
     __shared__ int stage;   // 0: not last, 1: last of its group, 2: last overall
     const gptr<double> part = (gptr<double>)r.part;
     const gptr<double> gpart = (gptr<double>)r.gpart;
@@ -96,36 +103,55 @@ __device__ bool grid_finish(double s, const RedSite &r, double *out, double *lds
     const unsigned int ngroups = (nb + RED_GROUP - 1) / RED_GROUP;
     const unsigned int gsize = (grp + 1 == ngroups) ? nb - grp * RED_GROUP : RED_GROUP;
     if (threadIdx.x == 0) {
-        store_coherent(part + lb, s);
+#pragma unroll
+        for (int c = 0; c < K; ++c) store_coherent(part + (size_t)lb * K + c, s[c]);
         const unsigned int t = take_ticket(tk + 1 + grp);
         stage = (t == gsize - 1u) ? 1 : 0;
     }
     __syncthreads();
     if (stage == 0) return false;
-    // last workgroup of the group: ordered group sum
-    double v = 0.0;
-    if (threadIdx.x < gsize) v = load_coherent(part + grp * RED_GROUP + threadIdx.x);
-    v = block_sum<NT>(v, lds);
+    // last workgroup of the group: ordered group sums
+    double v[K];
+#pragma unroll
+    for (int c = 0; c < K; ++c) {
+        v[c] = 0.0;
+        if (threadIdx.x < gsize)
+            v[c] = load_coherent(part + ((size_t)grp * RED_GROUP + threadIdx.x) * K + c);
+        v[c] = block_sum<NT>(v[c], lds);
+    }
     if (threadIdx.x == 0) {
         tk[1 + grp] = 0u;
-        store_coherent(gpart + grp, v);
+#pragma unroll
+        for (int c = 0; c < K; ++c) store_coherent(gpart + (size_t)grp * K + c, v[c]);
         const unsigned int t = take_ticket(tk);
         stage = (t == ngroups - 1u) ? 2 : 0;
     }
     __syncthreads();
     if (stage != 2) return false;
-    // last group: ordered sum of the group sums, then the extra partials
-    double u = 0.0;
-    for (long q = threadIdx.x; q < (long)ngroups; q += NT) u += load_coherent(gpart + q);
+    // last group: ordered sums of the group sums, then the extra partials
     double e = 0.0;
     for (long q = threadIdx.x; q < r.nextra; q += NT) e += load_coherent(extra + q);
-    u = block_sum<NT>(u, lds);
     e = block_sum<NT>(e, lds);
+    double u[K];
+#pragma unroll
+    for (int c = 0; c < K; ++c) {
+        u[c] = 0.0;
+        for (long q = threadIdx.x; q < (long)ngroups; q += NT) u[c] += load_coherent(gpart + q * K + c);
+        u[c] = block_sum<NT>(u[c], lds);
+    }
     if (threadIdx.x == 0) {
         tk[0] = 0u;
-        *out = e + u;
+        out[0] = e + u[0];
+#pragma unroll
+        for (int c = 1; c < K; ++c) out[c] = u[c];
     }
     return true;
+}
+
+template <int NT>
+__device__ __forceinline__ bool grid_finish(double s, const RedSite &r, double *out, double *lds,
+                                            unsigned int lb, unsigned int nb) {
+    return grid_finish_k<NT, 1>(&s, r, out, lds, lb, nb);
 }
 
 template <int NT>

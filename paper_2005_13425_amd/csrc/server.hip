@@ -296,7 +296,7 @@ struct nek_server {
         const double drop = is_mixed(q.precision) ? 0.1 : 0.0;
         NEK_HIP(launch_cg_reset(S->W.sc, S->W.tickets, N_SITES * RED_TICKETS, q.max_iter, q.rel_tol, drop,
                                 stream));
-        NEK_HIP(launch_cg_init(R->P, S->b, S->x, S->W.r, S->W.p, S->gsd.own_bits, S->W.site(SITE_INIT),
+        NEK_HIP(launch_cg_init(R->P, S->b, S->x, S->W.r, S->W.p, S->gsd.own_bits, nullptr, S->W.site(SITE_INIT),
                                S->W.sc, stream));
         used += f.total;
         S->t_admit = clock();
@@ -469,7 +469,7 @@ struct nek_server {
                 nek_result &r = S->res;
                 r.iters = sc.it;
                 r.n_replacements = sc.n_replace;
-                r.rel_res = bb > 0.0 ? sqrt(sc.rho / bb) : 0.0;
+                r.rel_res = bb > 0.0 ? sqrt(sc.rr / bb) : 0.0;
                 r.rel_res_true = bb > 0.0 ? sqrt(fin[S->index].t2 / bb) : 0.0;
                 int status = sc.status;
                 if (status == NEK_OK && q.rel_tol > 0.0) {
