@@ -139,8 +139,9 @@ def test_jacobi_argument_errors(nek):
     Dt, gt = _dev(m.D), _dev(m.g)
     dinv = nek.jacobi_inverse(Dt, gt, gs)
     b = _dev(oracle.lattice_to_local(m, synth.lattice_uniform(2, 2, 2, 4)))
-    with pytest.raises(nek.NekError) as ei:        # built for another mesh
-        nek.jacobi_inverse(Dt, gt, other)
+    with pytest.raises(nek.NekError) as ei:        # gather-scatter built for another mesh
+        nek._check(nek._lib.nek_jacobi_inverse(m.E, 4, Dt.data_ptr(), gt.data_ptr(), other.handle,
+                                               dinv.data_ptr(), None), "nek_jacobi_inverse")
     assert ei.value.code == nek.NEK_ERR_ARG
     buf = torch.empty(m.P + 1, dtype=torch.float64, device="cuda")
     with pytest.raises(nek.NekError) as ei:        # misaligned output
