@@ -333,30 +333,6 @@ int gs_build_host(int64_t E, int N, const int64_t *glo, const uint8_t *dirichlet
     }
     std::sort(zero.begin(), zero.end());
 
-    // pair rows: the two-copy nodes whose copies lie the smallest common offset
-    // apart, when at least an eighth of the two-copy nodes share it
-    std::vector<int32_t> pair_nodes;
-    int64_t delta = 0;
-    {
-        std::vector<int32_t> &R2 = rows[2];
-        int64_t dmin = INT64_MAX;
-        for (int32_t G : R2) dmin = std::min<int64_t>(dmin, copies[(size_t)start[(size_t)G] + 1] - copies[(size_t)start[(size_t)G]]);
-        if (!R2.empty()) {
-            size_t cnt = 0;
-            for (int32_t G : R2)
-                cnt += (copies[(size_t)start[(size_t)G] + 1] - copies[(size_t)start[(size_t)G]] == dmin);
-            if (cnt >= 64 && 8 * cnt >= R2.size()) delta = dmin;
-        }
-        if (delta > 0) {
-            std::vector<int32_t> rest;
-            for (int32_t G : R2) {
-                if (copies[(size_t)start[(size_t)G] + 1] - copies[(size_t)start[(size_t)G]] == delta) pair_nodes.push_back(G);
-                else rest.push_back(G);
-            }
-            R2.swap(rest);
-        }
-    }
-
     H = GsHost();
     H.E = E;
     H.N = N;
@@ -397,30 +373,11 @@ int gs_build_host(int64_t E, int N, const int64_t *glo, const uint8_t *dirichlet
         host[off_at + csr_nodes.size()] = o;
         H.groups.push_back({-1, (int32_t)csr_nodes.size(), idx_at, off_at});
     }
-    if (!pair_nodes.empty()) {   // last, so that CG iterations can leave it out
-        const size_t at = host.size();
-        const size_t nr = pair_nodes.size();
-        host.resize(at + 2 * nr);
-        for (size_t rr = 0; rr < nr; ++rr)
-            for (int m = 0; m < 2; ++m)
-                host[at + (size_t)m * nr + rr] = copies[(size_t)start[(size_t)pair_nodes[rr]] + m];
-        H.groups.push_back({2, (int32_t)nr, at, 0});
-    }
     const size_t words = (size_t)((P + 31) / 32);
-    const size_t pwords = pair_nodes.empty() ? 0 : (size_t)((P + 15) / 16);
-    H.own.assign(words + pwords, 0u);
+    H.own.assign(words, 0u);
     for (int64_t G = 0; G < U; ++G) {
         const int32_t L = copies[(size_t)start[(size_t)G]];
         H.own[(size_t)L >> 5] |= 1u << (L & 31);
-    }
-    if (pwords) {
-        H.delta = delta;
-        uint32_t *pb = H.own.data() + words;
-        for (int32_t G : pair_nodes) {
-            const int32_t lo = copies[(size_t)start[(size_t)G]], hi = lo + (int32_t)delta;
-            pb[(size_t)lo >> 4] |= 1u << (2 * (lo & 15));   // partner at +delta
-            pb[(size_t)hi >> 4] |= 2u << (2 * (hi & 15));   // partner at -delta
-        }
     }
     return NEK_OK;
 }
@@ -436,14 +393,10 @@ void gs_attach(const GsHost &H, void *arena, size_t own_offset, GsDevice &d) {
     d.n_zero = H.n_zero;
     d.arena = arena;
     d.own_bits = (uint32_t *)((char *)arena + own_offset);
-    d.delta = H.delta;
-    d.pair_bits = H.delta ? d.own_bits + (H.P + 31) / 32 : nullptr;
     const int32_t *base = (const int32_t *)arena;
     d.args.ngroups = 0;
     int32_t blocks = 0;
-    d.args.nblocks_cg = 0;
     for (const GsHostGroup &q : H.groups) {
-        if (H.delta && d.args.ngroups + 1 == (int)H.groups.size()) d.args.nblocks_cg = blocks;   // pair group
         GsGroup &G = d.args.grp[d.args.ngroups++];
         G.kind = q.kind;
         G.rows = q.rows;
@@ -453,7 +406,6 @@ void gs_attach(const GsHost &H, void *arena, size_t own_offset, GsDevice &d) {
         blocks += (q.rows + GS_THREADS - 1) / GS_THREADS;
     }
     d.args.nblocks = blocks;
-    if (!H.delta) d.args.nblocks_cg = blocks;
 }
 
 }  // namespace nek
@@ -665,7 +617,7 @@ int nek_cg_solve(int64_t E, int N, const double *D, const double *g, const nek_g
         if (e != hipSuccess) return e;
         e = launch_gs(gs->d, w, axp, ax_parts, sc, s);
         if (e != hipSuccess) return e;
-        return launch_cg_update(P, r, w, gs->d, opts.dinv, red_upd, sc, s);
+        return launch_cg_update(P, r, w, own, opts.dinv, red_upd, sc, s);
     };
     // w <- mask(dssum(A64 x)) with x brought up to date first
     auto true_ax = [&]() -> hipError_t {

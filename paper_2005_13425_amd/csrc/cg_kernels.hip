@@ -71,15 +71,15 @@ constexpr int N_XCD = 8;   // gfx950: workgroups are dealt round-robin to 8 XCDs
 // one contiguous eighth of the virtual blocks, so the copies a row touches
 // and the rows next to it share that XCD's L2.  Local workgroup 0 also turns
 // the (p, A_L p) partials of the preceding ax launch into alpha.
-// lb / nb: local workgroup index and count (nb a multiple of 8); nvb: virtual
-// blocks to cover (all groups, or all but the pair group inside CG iterations).
-__device__ __forceinline__ void gs_body(int lb, int nb, const GsArgs &a, int nvb, gptr<double> w,
+// lb / nb: local workgroup index and count (nb a multiple of 8).
+__device__ __forceinline__ void gs_body(int lb, int nb, const GsArgs &a, gptr<double> w,
                                         gptr<const double> axparts, long nparts,
                                         gptr<CgScalars> sc) {
     if (sc != nullptr && sc->done) return;
     const int xcd = lb % N_XCD;
     const int per = nb / N_XCD;
     const int lq = lb / N_XCD;
+    const int nvb = a.nblocks;
     const int v0 = (int)(((long)nvb * xcd) / N_XCD);
     const int v1 = (int)(((long)nvb * (xcd + 1)) / N_XCD);
     for (int vb = v0 + lq; vb < v1; vb += per) gs_vblock(a, vb, w);
@@ -105,8 +105,8 @@ __device__ __forceinline__ void gs_body(int lb, int nb, const GsArgs &a, int nvb
 __global__ void __launch_bounds__(GS_THREADS)
 gs_kernel(GsArgs a, double *__restrict__ w, const double *__restrict__ axparts, long nparts,
           CgScalars *sc) {
-    gs_body(blockIdx.x, gridDim.x, a, sc != nullptr ? a.nblocks_cg : a.nblocks, (gptr<double>)w,
-            (gptr<const double>)axparts, nparts, (gptr<CgScalars>)sc);
+    gs_body(blockIdx.x, gridDim.x, a, (gptr<double>)w, (gptr<const double>)axparts, nparts,
+            (gptr<CgScalars>)sc);
 }
 
 __global__ void __launch_bounds__(GS_THREADS)
@@ -114,8 +114,8 @@ gs_batch_kernel(const GsSlot *__restrict__ slots, int nslots) {
     const GsSlot &S = slots[batch_slot(slots, nslots, (int64_t)blockIdx.x)];
     const int lb = (int)((int64_t)blockIdx.x - S.block0);
     if (lb >= S.nblocks) return;
-    gs_body(lb, (int)S.nblocks, S.args, S.args.nblocks_cg, (gptr<double>)S.w,
-            (gptr<const double>)S.axparts, (long)S.nparts, (gptr<CgScalars>)S.sc);
+    gs_body(lb, (int)S.nblocks, S.args, (gptr<double>)S.w, (gptr<const double>)S.axparts,
+            (long)S.nparts, (gptr<CgScalars>)S.sc);
 }
 
 // ---------------------------------------------------------------- CG steps
@@ -242,21 +242,9 @@ cg_init_kernel(int64_t P, const double *__restrict__ b, double *__restrict__ x,
 
 // r -= alpha w; rr = (r, r); rho' = (r, z) with z = M^-1 r (= rr without a
 // preconditioner); beta = rho' / rho; convergence on rr and the iteration cap
-// The sum over the two copies of a pair row (see GsHost): lower local index
-// first, as the gather-scatter sums.
-__device__ __forceinline__ double pair_sum(gptr<const double> w, int64_t L, double wl, unsigned bits,
-                                           int64_t delta) {
-    if (bits == 1u) return (0.0 + wl) + w[L + delta];
-    if (bits == 2u) return (0.0 + w[L - delta]) + wl;
-    return wl;
-}
-
-// PAIR: w comes from a gather-scatter that left out the pair rows; their
-// copies are summed here as they are read.
-template <bool PRE, bool PAIR>
+template <bool PRE>
 __device__ __forceinline__ void update_body(int lb, int nb, int64_t P, gptr<double> r,
                                             gptr<const double> w, gptr<const uint32_t> own,
-                                            gptr<const uint32_t> pair, int64_t delta,
                                             gptr<const double> dinv, const RedSite &red,
                                             gptr<CgScalars> sc) {
     constexpr int K = PRE ? 2 : 1;
@@ -276,19 +264,6 @@ __device__ __forceinline__ void update_body(int lb, int nb, int64_t P, gptr<doub
                 rv[m] = ((gptr<const double2>)r)[q];
                 wv[m] = ((gptr<const double2>)w)[q];
                 if constexpr (PRE) dv[m] = ((gptr<const double2>)dinv)[q];
-            }
-        }
-        if constexpr (PAIR) {
-#pragma unroll
-            for (int m = 0; m < VEC_PAIRS; ++m) {
-                const int64_t q = base + threadIdx.x + (int64_t)m * VEC_THREADS;
-                if (q < npairs) {
-                    const unsigned pb = (pair[q >> 3] >> (4 * (q & 7))) & 15u;   // points 2q, 2q+1
-                    if (pb != 0u) {
-                        wv[m].x = pair_sum(w, 2 * q, wv[m].x, pb & 3u, delta);
-                        wv[m].y = pair_sum(w, 2 * q + 1, wv[m].y, pb >> 2, delta);
-                    }
-                }
             }
         }
 #pragma unroll
@@ -313,9 +288,7 @@ __device__ __forceinline__ void update_body(int lb, int nb, int64_t P, gptr<doub
     }
     if ((P & 1) && lb == nb - 1 && threadIdx.x == VEC_THREADS - 1) {
         const int64_t t = P - 1;
-        double wt = w[t];
-        if constexpr (PAIR) wt = pair_sum(w, t, wt, (pair[t >> 4] >> (2 * (t & 15))) & 3u, delta);
-        const double nr = r[t] - alpha * wt;
+        const double nr = r[t] - alpha * w[t];
         r[t] = nr;
         if (own_bit(own, t)) {
             acc[0] += nr * nr;
@@ -346,28 +319,21 @@ __device__ __forceinline__ void update_body(int lb, int nb, int64_t P, gptr<doub
     }
 }
 
-template <bool PRE, bool PAIR>
+template <bool PRE>
 __global__ void __launch_bounds__(VEC_THREADS)
 cg_update_kernel(int64_t P, double *__restrict__ r, const double *__restrict__ w,
-                 const uint32_t *__restrict__ own, const uint32_t *__restrict__ pair, int64_t delta,
-                 const double *__restrict__ dinv, RedSite red, CgScalars *sc) {
-    update_body<PRE, PAIR>(blockIdx.x, gridDim.x, P, (gptr<double>)r, (gptr<const double>)w,
-                           (gptr<const uint32_t>)own, (gptr<const uint32_t>)pair, delta,
-                           (gptr<const double>)dinv, red, (gptr<CgScalars>)sc);
+                 const uint32_t *__restrict__ own, const double *__restrict__ dinv, RedSite red,
+                 CgScalars *sc) {
+    update_body<PRE>(blockIdx.x, gridDim.x, P, (gptr<double>)r, (gptr<const double>)w,
+                     (gptr<const uint32_t>)own, (gptr<const double>)dinv, red, (gptr<CgScalars>)sc);
 }
 
 __global__ void __launch_bounds__(VEC_THREADS)
 update_batch_kernel(const UpdSlot *__restrict__ slots, int nslots) {
     const UpdSlot S = slots[batch_slot(slots, nslots, (int64_t)blockIdx.x)];
-    const int lb = (int)((int64_t)blockIdx.x - S.block0);
-    if (S.pair != nullptr)
-        update_body<false, true>(lb, (int)S.nblocks, S.P, (gptr<double>)S.r, (gptr<const double>)S.w,
-                                 (gptr<const uint32_t>)S.own, (gptr<const uint32_t>)S.pair, S.delta,
-                                 nullptr, S.red, (gptr<CgScalars>)S.sc);
-    else
-        update_body<false, false>(lb, (int)S.nblocks, S.P, (gptr<double>)S.r, (gptr<const double>)S.w,
-                                  (gptr<const uint32_t>)S.own, nullptr, 0, nullptr, S.red,
-                                  (gptr<CgScalars>)S.sc);
+    update_body<false>((int)((int64_t)blockIdx.x - S.block0), (int)S.nblocks, S.P, (gptr<double>)S.r,
+                       (gptr<const double>)S.w, (gptr<const uint32_t>)S.own, nullptr, S.red,
+                       (gptr<CgScalars>)S.sc);
 }
 
 __global__ void gather_scalars_kernel(CgScalars *const *src, int n, CgScalars *dst) {
@@ -494,9 +460,8 @@ int64_t vec_blocks(int64_t P) {
     return nb < 1 ? 1 : nb;
 }
 
-int64_t gs_grid(const GsDevice &gs, bool cg) {
-    const int64_t nvb = cg ? gs.args.nblocks_cg : gs.args.nblocks;
-    int64_t g = nvb < RED_MAX_BLOCKS ? nvb : RED_MAX_BLOCKS;
+int64_t gs_grid(const GsDevice &gs) {
+    int64_t g = gs.args.nblocks < RED_MAX_BLOCKS ? gs.args.nblocks : RED_MAX_BLOCKS;
     g = (g + N_XCD - 1) / N_XCD * N_XCD;
     return g < N_XCD ? N_XCD : g;
 }
@@ -504,8 +469,8 @@ int64_t gs_grid(const GsDevice &gs, bool cg) {
 hipError_t launch_gs(const GsDevice &gs, double *w, const double *axparts, int64_t nparts,
                      CgScalars *sc, hipStream_t s) {
     if (gs.args.nblocks == 0 && sc == nullptr) return hipSuccess;
-    hipLaunchKernelGGL(gs_kernel, dim3((unsigned)gs_grid(gs, sc != nullptr)), dim3(GS_THREADS), 0, s,
-                       gs.args, w, axparts, (long)nparts, sc);
+    hipLaunchKernelGGL(gs_kernel, dim3((unsigned)gs_grid(gs)), dim3(GS_THREADS), 0, s, gs.args, w,
+                       axparts, (long)nparts, sc);
     return hipGetLastError();
 }
 
@@ -549,19 +514,14 @@ hipError_t launch_cg_init(int64_t P, const double *b, double *x, double *r, doub
     return hipGetLastError();
 }
 
-hipError_t launch_cg_update(int64_t P, double *r, const double *w, const GsDevice &gs,
+hipError_t launch_cg_update(int64_t P, double *r, const double *w, const uint32_t *own,
                             const double *dinv, const RedSite &red, CgScalars *sc, hipStream_t s) {
-    const dim3 grid((unsigned)vec_blocks(P)), block(VEC_THREADS);
-    const uint32_t *own = gs.own_bits, *pair = gs.pair_bits;
-    const int64_t delta = gs.delta;
-    if (dinv != nullptr && pair != nullptr)
-        hipLaunchKernelGGL((cg_update_kernel<true, true>), grid, block, 0, s, P, r, w, own, pair, delta, dinv, red, sc);
-    else if (dinv != nullptr)
-        hipLaunchKernelGGL((cg_update_kernel<true, false>), grid, block, 0, s, P, r, w, own, pair, delta, dinv, red, sc);
-    else if (pair != nullptr)
-        hipLaunchKernelGGL((cg_update_kernel<false, true>), grid, block, 0, s, P, r, w, own, pair, delta, dinv, red, sc);
+    if (dinv != nullptr)
+        hipLaunchKernelGGL(cg_update_kernel<true>, dim3((unsigned)vec_blocks(P)), dim3(VEC_THREADS), 0,
+                           s, P, r, w, own, dinv, red, sc);
     else
-        hipLaunchKernelGGL((cg_update_kernel<false, false>), grid, block, 0, s, P, r, w, own, pair, delta, dinv, red, sc);
+        hipLaunchKernelGGL(cg_update_kernel<false>, dim3((unsigned)vec_blocks(P)), dim3(VEC_THREADS), 0,
+                           s, P, r, w, own, dinv, red, sc);
     return hipGetLastError();
 }
 

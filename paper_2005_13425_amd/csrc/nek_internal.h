@@ -128,23 +128,12 @@ constexpr int GS_MAXG = GS_MAXC + 2;
 
 struct GsArgs {
     int ngroups;
-    int nblocks;        // virtual blocks of all groups (dssum + mask)
-    int nblocks_cg;     // the same without the pair group (inside CG iterations)
+    int nblocks;
     GsGroup grp[GS_MAXG];
 };
 
 // Host image of a gather-scatter map (built on the host, uploaded into one
-// device arena: the int32 index arrays, then the bit words).
-//
-// Pair rows: unmasked nodes with exactly two copies whose local indices
-// differ by the most common such offset `delta` (on a box mesh the faces
-// between x-neighbours: point (n-1, j, k) of element e and (0, j, k) of
-// element e+1, n^3 - N apart).  Their copies are strided in memory, so the
-// gather-scatter touches a whole cache line for each 8-byte access.  They
-// form the last group: plain dssum runs it, but inside CG iterations the
-// update kernel, which streams all of w anyway, adds the partner copy itself
-// (in the same order, lower local index first) and the gather-scatter skips
-// the group.
+// device arena: the int32 index arrays, then the first-copy bits).
 struct GsHostGroup {
     int kind;
     int32_t rows;
@@ -157,10 +146,7 @@ struct GsHost {
     int64_t P = 0, U = 0, n_rows = 0, n_entries = 0, n_masked = 0, n_zero = 0;
     std::vector<int32_t> idx;
     std::vector<GsHostGroup> groups;
-    std::vector<uint32_t> own;  // first-copy bits ((P+31)/32 words), then 2 pair bits per
-                                // point ((P+15)/16 words) when delta != 0: 1 = partner
-                                // at L + delta, 2 = partner at L - delta
-    int64_t delta = 0;
+    std::vector<uint32_t> own;
     size_t idx_bytes() const { return ((idx.size() * sizeof(int32_t) + 4) + 255) & ~(size_t)255; }
     size_t arena_bytes() const { return idx_bytes() + own.size() * sizeof(uint32_t); }
 };
@@ -187,18 +173,14 @@ struct GsDevice {
     GsArgs args{};
     void *arena = nullptr;   // one allocation holding every index array
     uint32_t *own_bits = nullptr;  // P bits: first copy of every node
-    const uint32_t *pair_bits = nullptr;  // 2 bits per point (pair rows), or null
-    int64_t delta = 0;             // local-index offset of the pair rows' copies
 };
 
-// dssum + mask in place.  With sc != null (inside CG iterations), workgroup 0
-// also sums the nparts partials of (p, A_L p) left by the ax launch, in index
-// order, into sc->pw and sc->alpha (or flags a breakdown), and the pair rows
-// are left for launch_cg_update to sum.
+// dssum + mask in place.  With sc != null, workgroup 0 also sums the nparts
+// partials of (p, A_L p) left by the ax launch, in index order, into
+// sc->pw and sc->alpha (or flags a breakdown).
 hipError_t launch_gs(const GsDevice &gs, double *w, const double *axparts, int64_t nparts,
                      CgScalars *sc, hipStream_t s);
-// workgroups of a gather-scatter launch, a multiple of 8 (cg: without the pair group)
-int64_t gs_grid(const GsDevice &gs, bool cg);
+int64_t gs_grid(const GsDevice &gs);   // a multiple of 8
 
 struct GsSlot {
     int64_t block0;      // a multiple of 8, so a slot's workgroups keep their XCD order
@@ -222,9 +204,7 @@ hipError_t launch_cg_reset(CgScalars *sc, unsigned int *tickets, int nticket, in
 hipError_t launch_cg_init(int64_t P, const double *b, double *x, double *r, double *p,
                           const uint32_t *own, const double *dinv, const RedSite &red, CgScalars *sc,
                           hipStream_t s);
-// r -= alpha w with w = mask(dssum(A_L p)) from a CG-mode gather-scatter of gs
-// (the pair rows are summed here)
-hipError_t launch_cg_update(int64_t P, double *r, const double *w, const GsDevice &gs,
+hipError_t launch_cg_update(int64_t P, double *r, const double *w, const uint32_t *own,
                             const double *dinv, const RedSite &red, CgScalars *sc, hipStream_t s);
 
 struct UpdSlot {
@@ -234,8 +214,6 @@ struct UpdSlot {
     double *r;
     const double *w;
     const uint32_t *own;
-    const uint32_t *pair;   // pair bits of the gather-scatter, or null
-    int64_t delta;
     RedSite red;
     CgScalars *sc;
 };

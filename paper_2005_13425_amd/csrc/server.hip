@@ -33,8 +33,8 @@ constexpr int PREP_THREADS = 4;   // host threads preparing submitted requests
 bool is_mixed(int prec) { return prec == NEK_PREC_F32G32 || prec == NEK_PREC_F32GBF16; }
 
 // Device bytes of one admitted request (arena + solution vector).  The
-// gather-scatter part is bounded by one int32 per local point (every local
-// point appears in at most one group) plus the first-copy and pair bits.
+// gather-scatter part is bounded by one int32 per local point plus the
+// first-copy bits (every local point appears in at most one group).
 struct Footprint {
     size_t g, b, gs, D, D32, glo, ws, arena, x, total;
 };
@@ -45,7 +45,7 @@ Footprint footprint_of(int64_t E, int N, int prec) {
     Footprint f;
     f.g = align256(6 * P * sizeof(double));
     f.b = align256(P * sizeof(double));
-    f.gs = align256(P * sizeof(int32_t) + 4) + align256(((P + 31) / 32 + (P + 15) / 16) * sizeof(uint32_t));
+    f.gs = align256(P * sizeof(int32_t) + 4) + align256((P + 31) / 32 * sizeof(uint32_t));
     f.D = align256(n2 * sizeof(double));
     f.D32 = align256(n2 * sizeof(float));
     f.glo = prec == NEK_PREC_F32G32 ? align256(6 * P * sizeof(float))
@@ -384,7 +384,7 @@ struct nek_server {
             G.ax_blocks += ax_blocks(S->req->E, q.N);
             GsSlot &Gs = gsl[i];
             Gs.block0 = G.gs_blocks;
-            Gs.nblocks = gs_grid(S->gsd, true);
+            Gs.nblocks = gs_grid(S->gsd);
             Gs.args = S->gsd.args;
             Gs.w = S->W.w;
             Gs.axparts = S->W.axp;
@@ -398,8 +398,6 @@ struct nek_server {
             U.r = S->W.r;
             U.w = S->W.w;
             U.own = S->gsd.own_bits;
-            U.pair = S->gsd.pair_bits;
-            U.delta = S->gsd.delta;
             U.red = S->W.site(SITE_UPDATE);
             U.sc = S->W.sc;
             G.upd_blocks += U.nblocks;
