@@ -262,7 +262,10 @@ typedef struct {
 
 typedef struct {
     uint64_t id;
-    int status;          /* NEK_OK, NEK_ERR_BREAKDOWN, NEK_ERR_NOCONV, NEK_ERR_DEVICE */
+    int status;          /* NEK_OK, NEK_ERR_BREAKDOWN, NEK_ERR_NOCONV; or, for a request
+                            that never ran, the error of its preparation (NEK_ERR_ARG,
+                            NEK_ERR_NOMEM for pinned staging) or NEK_ERR_NOMEM when the
+                            device could not allocate it at admission */
     int iters;
     int n_replacements;
     double rel_res;      /* recurrence residual */

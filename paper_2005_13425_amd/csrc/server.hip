@@ -248,6 +248,21 @@ struct nek_server {
     }
 
     // ------------------------------------------------------------ admission
+    // A request that could not be prepared or admitted is reported as finished
+    // with that status; its staging buffer goes back to the pool.
+    void report_failed(Request &R, int status) {
+        nek_result r{};
+        r.id = R.id;
+        r.status = status;
+        r.t_submit = R.t_submit;
+        r.t_admit = r.t_done = clock();
+        r.E = R.E;
+        r.N = R.spec.N;
+        if (R.staging) pinned.put(R.staging);
+        R.staging = nullptr;
+        results.push_back(r);
+    }
+
     int admit_one(std::unique_ptr<Request> R) {
         const nek_request &q = R->spec;
         const Footprint &f = R->fp;
@@ -256,6 +271,14 @@ struct nek_server {
         free_index.pop_back();
         hipError_t e = hipMallocAsync((void **)&S->arena, f.arena, stream);
         if (e == hipSuccess) e = hipMallocAsync((void **)&S->x, f.x, stream);
+        if (e == hipErrorOutOfMemory) {
+            // the device is short of memory although the budget is not: report
+            // the request as failed and keep serving the others
+            if (S->arena) (void)hipFreeAsync(S->arena, stream);
+            free_index.push_back(S->index);
+            report_failed(*R, NEK_ERR_NOMEM);
+            return NEK_OK;
+        }
         if (e != hipSuccess) return check_hip(e, "server admission: hipMallocAsync");
         char *a = S->arena;
         S->g = (double *)a;
@@ -324,16 +347,7 @@ struct nek_server {
                 continue;
             }
             if (R->prep_status != NEK_OK) {
-                // report the failure as a finished request
-                nek_result r{};
-                r.id = R->id;
-                r.status = R->prep_status;
-                r.t_submit = R->t_submit;
-                r.t_admit = r.t_done = clock();
-                r.E = R->E;
-                r.N = R->spec.N;
-                if (R->staging) pinned.put(R->staging);
-                results.push_back(r);
+                report_failed(*R, R->prep_status);
                 it = waiting.erase(it);
                 continue;
             }

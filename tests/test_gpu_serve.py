@@ -170,6 +170,35 @@ def test_waiting_request_that_does_not_fit_is_not_overtaken(nek):
     assert res["Z"]["t_admit"] >= res["Y"]["t_admit"]
 
 
+def test_failing_requests_in_a_mix(nek):
+    """A request whose rhs holds a NaN reports a breakdown, one that cannot
+    reach its tolerance within max_iter reports non-convergence, and a healthy
+    request served beside them is bitwise the same as served alone."""
+    box, N = (3, 3, 3), 5
+    a = synth.geom_coeffs()
+    good = _rhs(nek, box, N, 11)
+    bad = good.copy()
+    glo, dr = nek.box_numbering(*box, N)
+    bad[np.argmax(dr == 0)] = np.nan
+    alone = nek.Server(4 * GB)
+    rid = alone.submit(*box, N, good, amp=synth.AMP, a=a, rel_tol=1e-10)
+    r_alone = alone.run_until_done([rid])[rid]
+    x_alone = alone.fetch(rid)
+    alone.close()
+    srv = nek.Server(4 * GB)
+    ids = {srv.submit(*box, N, bad, amp=synth.AMP, a=a, rel_tol=1e-10): "nan",
+           srv.submit(*box, N, good, amp=synth.AMP, a=a, rel_tol=1e-14, max_iter=10): "cap",
+           srv.submit(*box, N, good, amp=synth.AMP, a=a, rel_tol=1e-10): "good"}
+    got = srv.run_until_done(list(ids))
+    x_good = srv.fetch([k for k, v in ids.items() if v == "good"][0])
+    srv.close()
+    res = {ids[k]: v for k, v in got.items()}
+    assert res["nan"]["status"] == nek.NEK_ERR_BREAKDOWN
+    assert res["cap"]["status"] == nek.NEK_ERR_NOCONV and res["cap"]["iters"] == 10
+    assert res["good"]["status"] == 0 and res["good"]["iters"] == r_alone["iters"]
+    np.testing.assert_array_equal(x_good, x_alone)
+
+
 def test_server_errors(nek):
     srv = nek.Server(1 << 20)
     b = np.zeros(8 ** 3 * 64)
