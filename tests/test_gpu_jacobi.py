@@ -91,6 +91,13 @@ def test_pcg_100_iterations_paper_shape(nek):
     assert _rel(x, ref.x) <= TOL
 
 
+def test_pcg_100_iterations_full_shape(nek):
+    m, x, res, ref = _pcg_case(nek, (16, 16, 16), 9, 100)
+    print(f"PCG E=4096 N=9: rel-L2 {_rel(x, ref.x):.2e}", flush=True)
+    assert res.iters == 100
+    assert _rel(x, ref.x) <= TOL
+
+
 def test_pcg_to_tolerance(nek):
     m, x, res, ref = _pcg_case(nek, (4, 4, 4), 7, 2000, rel_tol=1e-13)
     print(f"PCG to 1e-13: iters {res.iters} oracle {ref.iters}", flush=True)

@@ -119,6 +119,35 @@ def test_mixed_cg_reaches_1e10_true_residual(nek, prec):
     gs.close()
 
 
+@pytest.mark.parametrize("prec", ["f32", "bf16"])
+def test_mixed_full_size_true_residual_by_the_oracle(nek, prec):
+    # the mixed-precision workload at its full size (E = 4096, N = 9, manufactured
+    # rhs, 1e-10): the oracle evaluates b - A x of the GPU's solution itself
+    box, N = (16, 16, 16), 9
+    m = oracle.box_mesh(*box, N, synth.AMP, synth.geom_coeffs())
+    b = oracle.manufactured_rhs(m)
+    gs = nek.GatherScatter(m.E, N, m.glo, m.dirichlet)
+    Dt, gt = _dev(m.D), _dev(m.g)
+    code = nek.NEK_G_F32 if prec == "f32" else nek.NEK_G_BF16
+    precision = nek.NEK_PREC_F32G32 if prec == "f32" else nek.NEK_PREC_F32GBF16
+    x, res = nek.cg_solve(Dt, gt, gs, _dev(b), max_iter=5000, rel_tol=1e-10, precision=precision,
+                          D32=_dev(m.D.astype(np.float32)), g_lo=nek.convert_g(gt, N, code))
+    torch.cuda.synchronize()
+    gs.close()
+    xh = x.cpu().numpy()
+    r = b - oracle.masked_ax(m, xh)
+    # the residual over unique nodes, as the solver measures it
+    true_rel = np.sqrt(oracle.gdot(m.glo, r, r, m.U) / oracle.gdot(m.glo, b, b, m.U))
+    xs, ys, zs = m.X
+    ustar = np.sin(np.pi * xs) * np.sin(np.pi * ys) * np.sin(np.pi * zs)
+    print(f"mixed {prec} E=4096: iters {res.iters}, oracle true residual {true_rel:.3e}, "
+          f"library {res.rel_res_true:.3e}, error vs sin {np.max(np.abs(xh - ustar)):.2e}", flush=True)
+    assert res.status == 0
+    assert true_rel <= 1.01e-10
+    assert abs(true_rel - res.rel_res_true) <= 1e-3 * true_rel
+    assert np.max(np.abs(xh - ustar)) <= 1e-6
+
+
 def test_mixed_cg_fixed_iterations_and_errors(nek):
     m = oracle.box_mesh(2, 2, 2, 4, synth.AMP, synth.geom_coeffs())
     b = oracle.lattice_to_local(m, synth.lattice_uniform(2, 2, 2, 4))

@@ -170,6 +170,24 @@ def test_cg_100_iterations_paper_shape(nek):
     assert _rel(x, ref.x) <= TOL
 
 
+@pytest.mark.parametrize("box", [(16, 16, 8), (16, 16, 16)])
+def test_cg_100_iterations_full_shapes(nek, box):
+    # the benchmark's shapes (E = 2048, 4096 at N = 9), with a caller workspace
+    # as the timed step uses
+    N = 9
+    m = _mesh(box, N)
+    b = oracle.lattice_to_local(m, synth.lattice_uniform(*box, N))
+    gs = nek.GatherScatter(m.E, N, m.glo, m.dirichlet)
+    ws = nek.cg_workspace(m.E, N)
+    x, res = nek.cg_solve(_dev(m.D), _dev(m.g), gs, _dev(b), max_iter=100, workspace=ws)
+    torch.cuda.synchronize()
+    gs.close()
+    ref = oracle.cg(m, b, max_iter=100)
+    err = _rel(x, ref.x)
+    print(f"CG E={m.E} N=9, 100 iterations: rel-L2 {err:.2e}", flush=True)
+    assert res.iters == 100 and err <= TOL
+
+
 def test_cg_to_tolerance(nek):
     m, x, res, ref = _cg_case(nek, (4, 4, 4), 7, 2000, rel_tol=1e-13)
     assert res.status == 0 and ref.status == 0
