@@ -77,6 +77,21 @@ def test_argument_errors_before_device_work(nek):
     assert lib.nek_cg_solve(4, 9, fake, fake, None, fake, fake, None, None, None) == nek.NEK_ERR_ARG
     assert lib.nek_cg_workspace_bytes(0, 9) == 0
     assert lib.nek_cg_workspace_bytes(4096, 9) >= 3 * 4096 * 1000 * 8
+    # the gather-scatter indexes local points with int32: E (N+1)^3 < 2^31
+    big_E = (1 << 31) // 1000 + 1
+    assert lib.nek_gs_create(big_E, 9, fake, None, ctypes.byref(h)) == nek.NEK_ERR_ARG
+    assert "2^31" in lib.nek_last_error().decode()
+    # Jacobi setup
+    assert lib.nek_jacobi_inverse(0, 9, fake, fake, fake, fake, None) == nek.NEK_ERR_ARG
+    assert lib.nek_jacobi_inverse(4, 16, fake, fake, fake, fake, None) == nek.NEK_ERR_UNSUPPORTED
+    assert lib.nek_jacobi_inverse(4, 9, fake, fake, None, fake, None) == nek.NEK_ERR_ARG
+    assert lib.nek_jacobi_inverse(4, 9, fake, fake, fake, ctypes.c_void_p(0x1008), None) == nek.NEK_ERR_ARG
+    # served footprint: positive, growing with E and N, larger for the mixed forms
+    f = [lib.nek_server_footprint(4, 4, 4, N, nek.NEK_PREC_F64) for N in (3, 5, 7)]
+    assert 0 < f[0] < f[1] < f[2]
+    assert lib.nek_server_footprint(8, 4, 4, 7, nek.NEK_PREC_F64) > f[2]
+    assert (lib.nek_server_footprint(4, 4, 4, 7, nek.NEK_PREC_F32G32)
+            > lib.nek_server_footprint(4, 4, 4, 7, nek.NEK_PREC_F32GBF16) > f[2])
 
 
 @pytest.mark.parametrize("N", list(range(1, 16)))

@@ -196,6 +196,24 @@ def test_cg_to_tolerance(nek):
     assert _rel(x, ref.x) <= 1e-10
 
 
+@pytest.mark.parametrize("N", [2, 4])
+def test_cg_single_element(nek, N):
+    # one element: every boundary node masked, no shared node, (N-1)^3 unknowns;
+    # N = 2 leaves one unknown, so CG ends after one iteration
+    m = _mesh((1, 1, 1), N)
+    b = oracle.lattice_to_local(m, synth.lattice_uniform(1, 1, 1, N))
+    gs = nek.GatherScatter(1, N, m.glo, m.dirichlet)
+    x, res = nek.cg_solve(_dev(m.D), _dev(m.g), gs, _dev(b), max_iter=200, rel_tol=1e-13,
+                          true_residual=True)
+    torch.cuda.synchronize()
+    gs.close()
+    ref = oracle.cg(m, b, max_iter=200, rel_tol=1e-13)
+    assert res.status == 0 and ref.status == 0
+    assert res.iters <= (N - 1) ** 3 + 2 and abs(res.iters - ref.iters) <= 1
+    assert _rel(x, ref.x) <= 1e-12
+    assert np.all(x.cpu().numpy()[m.dirichlet == 1] == 0.0)
+
+
 def test_cg_deterministic(nek):
     m = _mesh((4, 4, 4), 7)
     b = _dev(oracle.lattice_to_local(m, synth.lattice_uniform(4, 4, 4, 7)))

@@ -208,6 +208,13 @@ def test_server_errors(nek):
     with pytest.raises(nek.NekError) as ei:
         srv.submit(1, 1, 1, 16, np.zeros(17 ** 3))
     assert ei.value.code == nek.NEK_ERR_UNSUPPORTED
+    # more than 2^31 local points: rejected before the rhs is touched
+    req = nek.Request(1290, 1290, 1290, 1, 0.0, (nek.ctypes.c_double * 3)(0, 0, 0), b.ctypes.data,
+                      nek.NEK_PREC_F64, 1e-10, 100)
+    rid = nek.ctypes.c_uint64()
+    big = nek.Server(1 << 62)
+    assert nek._lib.nek_server_submit(big._h, nek.ctypes.byref(req), nek.ctypes.byref(rid)) == nek.NEK_ERR_ARG
+    big.close()
     with pytest.raises(nek.NekError):
         srv.fetch(12345) if 12345 in srv._sizes else nek._check(
             nek._lib.nek_server_fetch(srv._h, nek.ctypes.c_uint64(12345), b.ctypes.data), "fetch")
