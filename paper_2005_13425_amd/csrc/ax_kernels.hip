@@ -42,13 +42,15 @@ struct AxShape {
     static constexpr int RS = NX | 1;                                  // row stride (elements)
     static constexpr int LS = NX * RS;                                 // layer stride
     static constexpr int BUF = NX * LS;                                // one n^3 buffer
-    // waves per SIMD the register budget is held to: the LDS of one workgroup
-    // (3 BUF values per element) allows about this many on a 160 KB CU
-#ifdef NEK_AX_MINW
-    static constexpr int MINW = NEK_AX_MINW;
-#else
-    static constexpr int MINW = (sizeof(T) == 8 && NX <= 10) ? 3 : 1;
-#endif
+    static constexpr int LDS_BYTES = EPB * 2 * BUF * (int)sizeof(T);   // two buffers per element
+    // waves per SIMD the register budget is held to: as many as the LDS of
+    // the workgroups that fit a 160 KB CU provides, capped so that the FP64
+    // form of every degree compiles without register spills
+    static constexpr int WPS = (163840 / LDS_BYTES) * (THREADS / 64) / 4;
+    static constexpr int REG_CAP = sizeof(T) == 8 ? ((NX <= 8 || NX == 10) ? 4 : (NX <= 14 ? 3 : 2)) : 4;
+    static constexpr int MINW = WPS < 1 ? 1 : (WPS > REG_CAP ? REG_CAP : WPS);
+    // the CG-fused form also carries the FP64 p column through the element
+    static constexpr int MINW_FUSED = MINW < (NX <= 10 ? 3 : 2) ? MINW : (NX <= 10 ? 3 : 2);
     // layers of geometric factors held in registers ahead of their use
 #ifdef NEK_AX_PF
     static constexpr int PF = NEK_AX_PF < NX ? NEK_AX_PF : NX;
@@ -102,24 +104,26 @@ struct GLoad<float, uint16_t, N3> {
 
 // T: compute type (double or float); GT: storage type of g; FUSE: CG fusion.
 //
-// Per element, three LDS buffers B0, B1, B2 of n^3 (padded) values.  Thread
-// (a, b) of an element plays three roles: the column (i,j) = (a,b), the
-// r-pencil (j,k) = (a,b) and the s-pencil (i,k) = (a,b).
+// Per element, two LDS buffers B0, B1 of n^3 (padded) values.  Thread (a, b)
+// of an element plays three roles: the column (i,j) = (a,b), the r-pencil
+// (j,k) = (a,b) and the s-pencil (i,k) = (a,b).
 //   1. the column u(a,b,:) goes from HBM to B0;
 //   2. forward contractions, one dxm1 column l at a time (outer products):
-//      wr(:,a,b) += dxm1(:,l) u(l,a,b), ws(a,:,b) += dxm1(:,l) u(a,l,b) and
-//      wt(a,b,:) += dxm1(:,l) u(a,b,l); wr -> B1, ws -> B2, wt stays in
-//      registers;
-//   3. column: the symmetric g multiply gives ur -> B1, us -> B2 (in place)
+//      wr(:,a,b) += dxm1(:,l) u(l,a,b) -> B1 and wt(a,b,:) += dxm1(:,l)
+//      u(a,b,l), kept in registers; then, once every thread has read u, each
+//      s-pencil owner forms ws(a,:,b) += dxm1(:,l) u(a,l,b) and writes it over
+//      its own pencil of B0;
+//   3. column: the symmetric g multiply gives ur -> B1, us -> B0 (in place)
 //      and ut in registers;
 //   4. the ur pencil (:,a,b) and the us pencil (a,:,b) are read into registers;
 //   5. transposed contractions, one dxtm1 row i at a time (inner products):
-//      the r part at (i,a,b) -> B0, the s part at (a,i,b) -> B1 and the t part
-//      at (a,b,i) -> B2;
-//   6. w(a,b,:) = B0 + B1 + B2 at the column, stored to HBM.
+//      the r part at (i,a,b) -> B0 and the s part at (a,i,b) -> B1;
+//   6. per layer i of the column, the t part (inner product of dxtm1 row i
+//      with ut) is added to B0 + B1 and the sum stored to HBM as w(a,b,i).
 // Only one column or row of the derivative matrix (n values, uniform across
-// the workgroup) is live at a time, so it stays in scalar registers.  Five
-// workgroup barriers per element.
+// the workgroup) is live at a time, so it stays in scalar registers.  Two
+// buffers instead of three keep more elements resident per CU (the high
+// degrees were occupancy-bound).  Six workgroup barriers per element.
 template <int NX, typename T, typename GT, bool FUSE>
 __device__ __forceinline__ void ax_body(int64_t blk, int64_t E, kptr<T> D, gptr<const GT> g,
                                         gptr<double> p, gptr<double> w, const AxFuse &fz)
@@ -140,7 +144,7 @@ __device__ __forceinline__ void ax_body(int64_t blk, int64_t E, kptr<T> D, gptr<
     const gptr<const double> fdinv = (gptr<const double>)fz.dinv;
     if (FUSE && sc->done) return;   // uniform: CG already finished
 
-    __shared__ T lds[EPB * 3 * BUF];
+    __shared__ T lds[EPB * 2 * BUF];
 
     const int tid = threadIdx.x;
     const int eb = tid / NN;
@@ -151,9 +155,8 @@ __device__ __forceinline__ void ax_body(int64_t blk, int64_t E, kptr<T> D, gptr<
     const int64_t e = blk * EPB + eb;
     const bool active = in_slab && e < E;
 
-    T *B0 = lds + (in_slab ? eb : 0) * 3 * BUF;
+    T *B0 = lds + (in_slab ? eb : 0) * 2 * BUF;
     T *B1 = B0 + BUF;
-    T *B2 = B1 + BUF;
     const int col = b * RS + a;       // column (a,b) within a layer
     const int rpen = b * LS + a * RS; // start of r-pencil (:,a,b)
     const int spen = b * LS + a;      // start of s-pencil (a,:,b), stride RS
@@ -222,34 +225,44 @@ __device__ __forceinline__ void ax_body(int64_t blk, int64_t E, kptr<T> D, gptr<
     // ---- 2. forward contractions: outer products with dxm1(:, l) = D[n l .. n l + n)
     T wt[NX];
     {
-        T wr[NX], ws[NX];
+        T wr[NX];
 #pragma unroll
         for (int q = 0; q < NX; ++q) {
             wr[q] = T(0);
-            ws[q] = T(0);
             wt[q] = T(0);
         }
         if (in_slab) {
 #pragma unroll 2
             for (int l = 0; l < NX; ++l) {
                 const T vr = B0[rpen + l];          // u(l, a, b)
-                const T vs = B0[spen + l * RS];     // u(a, l, b)
                 const T vt = B0[l * LS + col];      // u(a, b, l)
                 const kptr<T> Dl = D + NX * l;
 #pragma unroll
                 for (int q = 0; q < NX; ++q) {
                     const T d = Dl[q];
                     wr[q] += d * vr;
-                    ws[q] += d * vs;
                     wt[q] += d * vt;
                 }
             }
 #pragma unroll
-            for (int q = 0; q < NX; ++q) {
-                B1[rpen + q] = wr[q];               // wr(q, a, b)
-                B2[spen + q * RS] = ws[q];          // ws(a, q, b)
-            }
+            for (int q = 0; q < NX; ++q) B1[rpen + q] = wr[q];   // wr(q, a, b)
         }
+    }
+    __syncthreads();
+    // the s-pencil (a, :, b) of B0 is now read and rewritten by its owner only
+    if (in_slab) {
+        T ws[NX];
+#pragma unroll
+        for (int q = 0; q < NX; ++q) ws[q] = T(0);
+#pragma unroll 2
+        for (int l = 0; l < NX; ++l) {
+            const T vs = B0[spen + l * RS];         // u(a, l, b)
+            const kptr<T> Dl = D + NX * l;
+#pragma unroll
+            for (int q = 0; q < NX; ++q) ws[q] += Dl[q] * vs;
+        }
+#pragma unroll
+        for (int q = 0; q < NX; ++q) B0[spen + q * RS] = ws[q];  // ws(a, q, b)
     }
     __syncthreads();
 
@@ -261,12 +274,12 @@ __device__ __forceinline__ void ax_body(int64_t blk, int64_t E, kptr<T> D, gptr<
         T urv = T(0), usv = T(0), utv = T(0);
         if (in_slab) {
             const T wrv = B1[k * LS + col];
-            const T wsv = B2[k * LS + col];
+            const T wsv = B0[k * LS + col];
             urv = gc[0] * wrv + gc[1] * wsv + gc[2] * wt[k];
             usv = gc[1] * wrv + gc[3] * wsv + gc[4] * wt[k];
             utv = gc[2] * wrv + gc[4] * wsv + gc[5] * wt[k];
             B1[k * LS + col] = urv;
-            B2[k * LS + col] = usv;
+            B0[k * LS + col] = usv;
         }
         ut[k] = utv;
         if (k + PF < NX && active) GLoad<T, GT, N3>::load(ge, (k + PF) * NN + c, gq[k % PF]);
@@ -278,7 +291,7 @@ __device__ __forceinline__ void ax_body(int64_t blk, int64_t E, kptr<T> D, gptr<
 #pragma unroll
     for (int l = 0; l < NX; ++l) {
         vr[l] = in_slab ? B1[rpen + l] : T(0);          // ur(l, a, b)
-        vs[l] = in_slab ? B2[spen + l * RS] : T(0);     // us(a, l, b)
+        vs[l] = in_slab ? B0[spen + l * RS] : T(0);     // us(a, l, b)
     }
     __syncthreads();
 
@@ -287,29 +300,37 @@ __device__ __forceinline__ void ax_body(int64_t blk, int64_t E, kptr<T> D, gptr<
 #pragma unroll 2
         for (int i = 0; i < NX; ++i) {
             const kptr<T> Di = D + NX * i;
-            T pr = T(0), ps = T(0), pt = T(0);
+            T pr = T(0), ps = T(0);
 #pragma unroll
             for (int l = 0; l < NX; ++l) {
                 const T d = Di[l];
                 pr += d * vr[l];
                 ps += d * vs[l];
-                pt += d * ut[l];
             }
             B0[rpen + i] = pr;              // r part at (i, a, b)
             B1[spen + i * RS] = ps;         // s part at (a, i, b)
-            B2[i * LS + col] = pt;          // t part at (a, b, i)
         }
     }
     __syncthreads();
 
-    // ---- 6. w = r part + s part + t part
-    double pw = 0.0;
+    // ---- 6. w(a, b, i) = r part + s part + t part, the t part formed here
     if (active) {
+#pragma unroll 2
+        for (int i = 0; i < NX; ++i) {
+            const kptr<T> Di = D + NX * i;
+            T pt = T(0);
 #pragma unroll
-        for (int k = 0; k < NX; ++k) {
-            const double wv = (double)(B0[k * LS + col] + B1[k * LS + col] + B2[k * LS + col]);
-            w[base + k * NN] = wv;
-            if constexpr (FUSE) pw += pcol[k] * wv;
+            for (int l = 0; l < NX; ++l) pt += Di[l] * ut[l];
+            const T wv = (B0[i * LS + col] + B1[i * LS + col]) + pt;
+            w[base + i * NN] = (double)wv;
+            if constexpr (FUSE) B0[i * LS + col] = wv;   // the column's own slots
+        }
+    }
+    double pw = 0.0;
+    if constexpr (FUSE) {
+        if (active) {
+#pragma unroll
+            for (int k = 0; k < NX; ++k) pw += pcol[k] * (double)B0[k * LS + col];
         }
     }
     // ---- 7. CG: per-workgroup sum of p (A_L p) over all local points.  For a
@@ -325,7 +346,8 @@ __device__ __forceinline__ void ax_body(int64_t blk, int64_t E, kptr<T> D, gptr<
 }
 
 template <int NX, typename T, typename GT, bool FUSE>
-__global__ void __launch_bounds__((AxShape<NX, T>::THREADS), (AxShape<NX, T>::MINW))
+__global__ void __launch_bounds__((AxShape<NX, T>::THREADS),
+                                  (FUSE ? AxShape<NX, T>::MINW_FUSED : AxShape<NX, T>::MINW))
 ax_kernel(int64_t E, const T *__restrict__ D, const GT *__restrict__ g, double *__restrict__ p,
           double *__restrict__ w, AxFuse fz)
 {
@@ -338,7 +360,7 @@ ax_kernel(int64_t E, const T *__restrict__ D, const GT *__restrict__ g, double *
 // workgroups its own launch would, so its arithmetic does not depend on
 // which other solves share the launch.
 template <int NX, typename T, typename GT>
-__global__ void __launch_bounds__((AxShape<NX, T>::THREADS), (AxShape<NX, T>::MINW))
+__global__ void __launch_bounds__((AxShape<NX, T>::THREADS), (AxShape<NX, T>::MINW_FUSED))
 ax_batch_kernel(const AxSlot *__restrict__ slots, int nslots)
 {
     const AxSlot S = slots[batch_slot(slots, nslots, (int64_t)blockIdx.x)];
