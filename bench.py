@@ -66,8 +66,8 @@ def parse():
 def main():
     args = parse()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1 "
-                                   "(the multi-GPU sharding is described, not built)"}))
+        print(json.dumps({"error": "one GPU only: --gpus must be 1 "
+                                   "(the path is not sharded across GPUs)"}))
         sys.exit(2)
 
     import numpy as np
