@@ -175,7 +175,7 @@ typedef struct {
     int check_every;       /* host polls convergence every this many iterations (0: 25) */
     int true_residual;     /* 1: report ||b - A x|| / ||b|| computed in FP64 at the end */
     double reliable_drop;  /* NEK_PREC_F32G*: replace r by b - A64 x whenever ||r|| fell
-                              by this factor since the last replacement (0: 0.1) */
+                              by this factor since the last replacement (0: 0.3) */
     void *workspace;       /* device scratch of nek_cg_workspace_bytes() bytes, or NULL
                               to let the call allocate and free its own */
     size_t workspace_bytes;

@@ -563,7 +563,7 @@ int nek_cg_solve(int64_t E, int N, const double *D, const double *g, const nek_g
         return fail(NEK_ERR_UNSUPPORTED, "nek_cg_solve: the Jacobi preconditioner is FP64 only");
     if (opts.dinv && !aligned16(opts.dinv)) return fail(NEK_ERR_ARG, "nek_cg_solve: misaligned dinv");
     const int g_dtype = opts.precision == NEK_PREC_F32G32 ? NEK_G_F32 : NEK_G_BF16;
-    const double drop = mixed ? (opts.reliable_drop > 0.0 ? opts.reliable_drop : 0.1) : 0.0;
+    const double drop = mixed ? (opts.reliable_drop > 0.0 ? opts.reliable_drop : RELIABLE_DROP_DEFAULT) : 0.0;
     if (mixed && !(drop < 1.0)) return fail(NEK_ERR_ARG, "nek_cg_solve: reliable_drop must be < 1");
     int check_every = opts.check_every > 0 ? opts.check_every : (mixed ? 4 : 25);
     const bool poll = mixed || opts.rel_tol > 0.0;

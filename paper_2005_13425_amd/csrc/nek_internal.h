@@ -51,6 +51,12 @@ struct CgScalars {
     int pad_[3];          // size a multiple of 16 bytes
 };
 
+// Mixed precision: r is replaced by the FP64 true residual once ||r|| has
+// fallen by this factor since the last replacement (measured at E = 4096,
+// N = 9: 0.3 takes 6% fewer iterations than 0.1 with BF16 g, the same with
+// FP32 g).
+constexpr double RELIABLE_DROP_DEFAULT = 0.3;
+
 // ---------------------------------------------------------------- ax_e
 // Optional CG fusion of the local-operator launch (all device pointers):
 //   r != null : p <- r + beta p on the way in (beta from sc);

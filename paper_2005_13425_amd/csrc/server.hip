@@ -316,7 +316,7 @@ struct nek_server {
         if (is_mixed(q.precision))
             NEK_HIP(launch_convert_g(R->E, q.N, S->g,
                                      q.precision == NEK_PREC_F32G32 ? NEK_G_F32 : NEK_G_BF16, S->glo, stream));
-        const double drop = is_mixed(q.precision) ? 0.1 : 0.0;
+        const double drop = is_mixed(q.precision) ? RELIABLE_DROP_DEFAULT : 0.0;
         NEK_HIP(launch_cg_reset(S->W.sc, S->W.tickets, N_SITES * RED_TICKETS, q.max_iter, q.rel_tol, drop,
                                 stream));
         NEK_HIP(launch_cg_init(R->P, S->b, S->x, S->W.r, S->W.p, S->gsd.own_bits, nullptr, S->W.site(SITE_INIT),
