@@ -294,8 +294,10 @@ size_t nek_server_footprint(int Ex, int Ey, int Ez, int N, int precision);
 
 /* One step: admit prepared requests in arrival order while they fit (a
  * request still being prepared does not hold back prepared ones behind it; a
- * prepared one that does not fit holds back all later ones), run
- * `iters` CG iterations of every admitted solve, and retire solves whose
+ * prepared one that does not fit holds back all later ones), run at least
+ * `iters` CG iterations of every admitted solve (solves are grouped by degree,
+ * precision and size; groups much cheaper than the heaviest get up to 8 times
+ * as many, within half the heaviest group's time), and retire solves whose
  * completion the step observed.  active / queued (may be NULL) receive the
  * number of admitted and waiting requests after the step.  Returns after
  * queueing the device work (it waits only for the device work of the step

@@ -144,10 +144,58 @@ struct TableSet {       // slot tables of one step, host (pinned) and device
 };
 
 struct Group {
-    int N, precision;
+    int N, precision, size_class;
     int first, count;            // range in the slot tables
     int64_t ax_blocks, gs_blocks, upd_blocks;
+    int64_t points;              // local points of its solves
+    int extra = 0;               // iterations per step beyond the common count
 };
+
+// Solves of similar size share a group: a class spans a factor of 4 in local
+// points.
+int size_class(int64_t P) {
+    int c = 0;
+    while (P >= 4) {
+        P >>= 2;
+        ++c;
+    }
+    return c;
+}
+
+// Extra iterations per step for cheap groups.  A group costs about its local
+// points plus the launch overhead of its three kernels (worth about 0.5 M
+// points); every group runs `iters` iterations, then a budget of half the
+// heaviest group's step goes, cheapest group first, to up to 7 * iters more.
+// Small solves no longer move at the pace of the largest ones, and the step
+// grows by at most half.
+constexpr int64_t LAUNCH_POINTS = 500000;
+constexpr int MAX_ITER_WEIGHT = 8;
+
+void assign_extra(std::vector<Group> &groups, int iters) {
+    if (groups.size() < 2) {
+        for (Group &G : groups) G.extra = 0;
+        return;
+    }
+    std::vector<int> order(groups.size());
+    int64_t cmax = 0;
+    for (size_t g = 0; g < groups.size(); ++g) {
+        order[g] = (int)g;
+        groups[g].extra = 0;
+        cmax = std::max(cmax, groups[g].points + LAUNCH_POINTS);
+    }
+    std::stable_sort(order.begin(), order.end(),
+                     [&](int a, int b) { return groups[a].points < groups[b].points; });
+    int64_t budget = (int64_t)iters * cmax / 2;
+    for (int g : order) {
+        const int64_t c = groups[g].points + LAUNCH_POINTS;
+        if (c >= cmax) continue;
+        const int64_t want = (int64_t)(MAX_ITER_WEIGHT - 1) * iters;
+        const int64_t can = budget / c;
+        const int64_t e = want < can ? want : can;
+        groups[g].extra = (int)e;
+        budget -= e * c;
+    }
+}
 
 constexpr size_t TABLE_BYTES =
     MAX_SLOTS * (sizeof(AxSlot) + sizeof(GsSlot) + sizeof(UpdSlot) + sizeof(CgScalars *));
@@ -370,7 +418,9 @@ struct nek_server {
             if (s->state == ACTIVE) act.push_back(s.get());
         std::stable_sort(act.begin(), act.end(), [](const Slot *a, const Slot *b) {
             if (a->req->spec.N != b->req->spec.N) return a->req->spec.N < b->req->spec.N;
-            return a->req->spec.precision < b->req->spec.precision;
+            if (a->req->spec.precision != b->req->spec.precision)
+                return a->req->spec.precision < b->req->spec.precision;
+            return size_class(a->req->P) < size_class(b->req->P);
         });
         AxSlot *ax = (AxSlot *)T.host;
         GsSlot *gsl = (GsSlot *)(T.host + MAX_SLOTS * sizeof(AxSlot));
@@ -380,9 +430,12 @@ struct nek_server {
         for (size_t i = 0; i < act.size(); ++i) {
             Slot *S = act[i];
             const nek_request &q = S->req->spec;
-            if (groups.empty() || groups.back().N != q.N || groups.back().precision != q.precision)
-                groups.push_back({q.N, q.precision, (int)i, 0, 0, 0, 0});
+            const int cls = size_class(S->req->P);
+            if (groups.empty() || groups.back().N != q.N || groups.back().precision != q.precision ||
+                groups.back().size_class != cls)
+                groups.push_back({q.N, q.precision, cls, (int)i, 0, 0, 0, 0, 0});
             Group &G = groups.back();
+            G.points += S->req->P;
             const bool mixed = is_mixed(q.precision);
             AxSlot &A = ax[i];
             A.block0 = G.ax_blocks;
@@ -524,8 +577,10 @@ struct nek_server {
             const GsSlot *gsl = (const GsSlot *)(T.dev + MAX_SLOTS * sizeof(AxSlot));
             const UpdSlot *up = (const UpdSlot *)(T.dev + MAX_SLOTS * (sizeof(AxSlot) + sizeof(GsSlot)));
             CgScalars *const *scp = (CgScalars *const *)(T.dev + MAX_SLOTS * (sizeof(AxSlot) + sizeof(GsSlot) + sizeof(UpdSlot)));
-            for (int it = 0; it < std::max(1, iters); ++it) {
-                for (const Group &G : groups) {
+            const int base_iters = std::max(1, iters);
+            assign_extra(groups, base_iters);
+            for (const Group &G : groups) {
+                for (int it = 0; it < base_iters + G.extra; ++it) {
                     NEK_HIP(launch_ax_batch(G.N, G.precision, ax + G.first, G.count, G.ax_blocks, stream));
                     NEK_HIP(launch_gs_batch(gsl + G.first, G.count, G.gs_blocks, stream));
                     NEK_HIP(launch_update_batch(up + G.first, G.count, G.upd_blocks, stream));
