@@ -328,8 +328,11 @@ int nek_server_destroy(nek_server *srv);
  * 7 = the 7:1 read:write mix of the FP64 local operator).  src: device,
  * nread*n doubles, 16-byte aligned; dst: device, n doubles, 16-byte aligned,
  * not overlapping src.  grid_cap > 0 caps the number of workgroups (0: one
- * pass).  Allocates nothing.  Asynchronous. */
-int nek_bw_probe(int64_t n, int nread, const double *src, double *dst, int grid_cap, void *stream);
+ * pass).  streaming != 0: the loads and stores carry the non-temporal hint (as
+ * the plain FP64 operator's do from N = 7 up); the measured roofline is the
+ * better of the two.  Allocates nothing.  Asynchronous. */
+int nek_bw_probe(int64_t n, int nread, const double *src, double *dst, int grid_cap, int streaming,
+                 void *stream);
 
 #ifdef __cplusplus
 }

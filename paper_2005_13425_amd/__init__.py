@@ -97,7 +97,7 @@ _sig("nek_gs_destroy", _ci, [_vp])
 _sig("nek_gs_info", _ci, [_vp] + [ctypes.POINTER(_i64)] * 4)
 _sig("nek_dssum", _ci, [_vp, _vp, _vp])
 _sig("nek_gs_dot", _ci, [_vp, _vp, _vp, _vp, _vp])
-_sig("nek_bw_probe", _ci, [_i64, _ci, _vp, _vp, _ci, _vp])
+_sig("nek_bw_probe", _ci, [_i64, _ci, _vp, _vp, _ci, _ci, _vp])
 _sig("nek_jacobi_inverse", _ci, [_i64, _ci, _vp, _vp, _vp, _vp, _vp])
 _sig("nek_server_create", _ci, [ctypes.c_size_t, ctypes.POINTER(_vp)])
 _sig("nek_server_submit", _ci, [_vp, ctypes.POINTER(Request), ctypes.POINTER(ctypes.c_uint64)])
@@ -246,12 +246,14 @@ def ax_f32(u, D32, g_lo, g_dtype: int, N: int, out=None, stream=None):
     return out
 
 
-def bw_probe(src, dst, nread: int, grid_cap: int = 0, stream=None):
-    """dst[i] = sum_k src[k*n + i] (nread read streams, one write stream)."""
+def bw_probe(src, dst, nread: int, grid_cap: int = 0, streaming: bool = False, stream=None):
+    """dst[i] = sum_k src[k*n + i] (nread read streams, one write stream);
+    streaming: non-temporal loads and stores."""
     torch = _torch()
     n = dst.numel()
     _check(_lib.nek_bw_probe(n, int(nread), _dev(src, torch.float64, "src", nread * n),
-                             _dev(dst, torch.float64, "dst", n), int(grid_cap), _stream_ptr(stream)),
+                             _dev(dst, torch.float64, "dst", n), int(grid_cap), 1 if streaming else 0,
+                             _stream_ptr(stream)),
            "nek_bw_probe")
     return dst
 

@@ -232,7 +232,8 @@ int nek_convert_g(int64_t E, int N, const double *g, int g_dtype, void *g_lo, vo
 }
 
 // ---------------------------------------------------------------- measurement
-int nek_bw_probe(int64_t n, int nread, const double *src, double *dst, int grid_cap, void *stream) {
+int nek_bw_probe(int64_t n, int nread, const double *src, double *dst, int grid_cap, int streaming,
+                 void *stream) {
     clear_error();
     if (n < 1) return fail(NEK_ERR_ARG, "nek_bw_probe: n must be >= 1");
     if (nread < 1 || nread > 8) return fail(NEK_ERR_ARG, "nek_bw_probe: nread must be in 1..8");
@@ -241,7 +242,7 @@ int nek_bw_probe(int64_t n, int nread, const double *src, double *dst, int grid_
     const uintptr_t sb = (uintptr_t)src, db = (uintptr_t)dst;
     if (db < sb + (uintptr_t)(nread * n) * 8 && sb < db + (uintptr_t)n * 8)
         return fail(NEK_ERR_ARG, "nek_bw_probe: src and dst overlap");
-    NEK_HIP(launch_probe(n, nread, src, dst, grid_cap, (hipStream_t)stream));
+    NEK_HIP(launch_probe(n, nread, src, dst, grid_cap, streaming != 0, (hipStream_t)stream));
     return NEK_OK;
 }
 

@@ -81,6 +81,13 @@ def test_argument_errors_before_device_work(nek):
     big_E = (1 << 31) // 1000 + 1
     assert lib.nek_gs_create(big_E, 9, fake, None, ctypes.byref(h)) == nek.NEK_ERR_ARG
     assert "2^31" in lib.nek_last_error().decode()
+    # bandwidth probe
+    big = ctypes.c_void_p(0x100000)
+    assert lib.nek_bw_probe(0, 7, fake, big, 0, 0, None) == nek.NEK_ERR_ARG
+    assert lib.nek_bw_probe(16, 9, fake, big, 0, 0, None) == nek.NEK_ERR_ARG
+    assert lib.nek_bw_probe(16, 0, fake, big, 0, 1, None) == nek.NEK_ERR_ARG
+    assert lib.nek_bw_probe(16, 1, ctypes.c_void_p(0x1008), big, 0, 0, None) == nek.NEK_ERR_ARG
+    assert lib.nek_bw_probe(16, 2, fake, ctypes.c_void_p(0x1010), 0, 0, None) == nek.NEK_ERR_ARG   # overlap
     # Jacobi setup
     assert lib.nek_jacobi_inverse(0, 9, fake, fake, fake, fake, None) == nek.NEK_ERR_ARG
     assert lib.nek_jacobi_inverse(4, 16, fake, fake, fake, fake, None) == nek.NEK_ERR_UNSUPPORTED

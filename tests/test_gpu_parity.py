@@ -278,6 +278,26 @@ def test_cg_odd_point_count_and_interior_mask(nek):
         gs.close()
 
 
+@pytest.mark.parametrize("streaming", [False, True])
+def test_bw_probe_sums_its_streams(nek, streaming):
+    # dst[i] = sum over k of src[k*n + i], summed in k order; odd n for the tail
+    rng = np.random.default_rng(9)
+    for nread, n in ((1, 1001), (7, 40001), (8, 12345)):
+        src = rng.uniform(-1, 1, nread * n)
+        dst = torch.empty(n, dtype=torch.float64, device="cuda")
+        nek.bw_probe(_dev(src), dst, nread, streaming=streaming)
+        ref = np.zeros(n)
+        for k in range(nread):
+            ref = ref + src[k * n:(k + 1) * n]
+        np.testing.assert_array_equal(dst.cpu().numpy(), ref)
+    # a capped grid walks the rest with a stride
+    src = rng.uniform(-1, 1, 3 * 300001)
+    dst = torch.empty(300001, dtype=torch.float64, device="cuda")
+    nek.bw_probe(_dev(src), dst, 3, grid_cap=7, streaming=streaming)
+    ref = src[:300001] + src[300001:600002] + src[600002:]
+    np.testing.assert_array_equal(dst.cpu().numpy(), ref)
+
+
 def test_gs_dot_odd_and_unaligned_rejected(nek):
     m = _mesh((3, 1, 1), 2)
     gs = nek.GatherScatter(m.E, 2, m.glo, m.dirichlet)
