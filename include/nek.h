@@ -196,7 +196,9 @@ typedef struct {
  * preconditioner. */
 void nek_cg_default_opts(nek_cg_opts *opts);
 
-/* Device bytes of scratch nek_cg_solve needs for E elements of degree N. */
+/* Device bytes of scratch nek_cg_solve needs for E elements of degree N, with
+ * or without a preconditioner (without one, one vector of P doubles less is
+ * enough). */
 size_t nek_cg_workspace_bytes(int64_t E, int N);
 
 /* Solve mask(dssum(A_L x)) = b by unpreconditioned CG with x_0 = 0 (Sec. III,
@@ -207,7 +209,12 @@ size_t nek_cg_workspace_bytes(int64_t E, int N);
  * opts->check_every iterations.  Blocking: returns after the work on stream
  * has finished.  stats may be NULL.  Returns NEK_OK, or the failure code
  * (also stored in stats->status) -- NEK_ERR_NOCONV when rel_tol > 0 was not
- * reached.
+ * reached.  Inside the solve the vectors are kept with the points of each
+ * element's faces at fixed i gathered at the end of every layer k (the
+ * gather-scatter reads and writes them most); b and dinv are copied into the
+ * workspace in that order, x is written in it while iterating and put back
+ * into the layout of Listing 1 before the call returns.  After a failure other than NEK_ERR_NOCONV and
+ * NEK_ERR_BREAKDOWN, x is unspecified.
  *
  * With opts->dinv set: preconditioned CG with M^-1 = dinv (the preconditioning
  * Sec. VII leaves as future work, in its simplest, Jacobi form):

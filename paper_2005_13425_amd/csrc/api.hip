@@ -12,7 +12,8 @@
 #include "nek_internal.h"
 
 struct nek_gs {
-    nek::GsDevice d;
+    nek::GsDevice d;                 // the layout of Listing 1 (nek_dssum, nek_gs_dot, Jacobi setup)
+    nek::GsDevice cg;                // the CG layout (nek_cg_solve)
     double *partials = nullptr;      // reduction site of nek_gs_dot
     unsigned int *ticket = nullptr;  // its counters
 };
@@ -250,6 +251,7 @@ int nek_bw_probe(int64_t n, int nread, const double *src, double *dst, int grid_
 static void gs_free(nek_gs *h) {
     if (!h) return;
     (void)hipFree(h->d.arena);
+    (void)hipFree(h->cg.arena);
     (void)hipFree(h->partials);
     (void)hipFree(h->ticket);
     delete h;
@@ -259,8 +261,9 @@ static void gs_free(nek_gs *h) {
 
 namespace nek {
 
-int gs_build_host(int64_t E, int N, const int64_t *glo, const uint8_t *dirichlet, GsHost &H,
-                  std::string &msg) {
+namespace {
+int gs_build_std(int64_t E, int N, const int64_t *glo, const uint8_t *dirichlet, GsHost &H,
+                 std::string &msg) {
     const int64_t n3 = n3_of(N);
     const int64_t P = E * n3;
     if (P >= ((int64_t)1 << 31)) {
@@ -382,6 +385,37 @@ int gs_build_host(int64_t E, int N, const int64_t *glo, const uint8_t *dirichlet
     }
     return NEK_OK;
 }
+}  // namespace
+
+// In the CG layout the copies are the same, at other positions: the map is
+// built from the numbering moved to those positions, so rows (ordered by their
+// first copy) follow the CG layout too.  Copies of a node lie in distinct
+// elements, so each row keeps its copies in the same (element) order and
+// sums them in the same order as in the layout of Listing 1.
+int gs_build_host(int64_t E, int N, const int64_t *glo, const uint8_t *dirichlet, bool cg_layout,
+                  GsHost &H, std::string &msg) {
+    if (!cg_layout) return gs_build_std(E, N, glo, dirichlet, H, msg);
+    const int n = N + 1;
+    const int64_t n3 = n3_of(N);
+    if (E * n3 >= ((int64_t)1 << 31)) {
+        msg = "E*(N+1)^3 must be < 2^31";
+        return NEK_ERR_ARG;
+    }
+    std::vector<int32_t> pos((size_t)n3);
+    for (int l = 0; l < (int)n3; ++l) {
+        const int k = l / (n * n), ij = l - k * n * n;
+        pos[(size_t)l] = k * n * n + cgl_col(ij % n, ij / n, n);
+    }
+    std::vector<int64_t> glo_c((size_t)(E * n3));
+    std::vector<uint8_t> dir_c(dirichlet ? (size_t)(E * n3) : 0);
+    for (int64_t e = 0; e < E; ++e)
+        for (int l = 0; l < (int)n3; ++l) {
+            const size_t from = (size_t)(e * n3 + l), to = (size_t)(e * n3 + pos[(size_t)l]);
+            glo_c[to] = glo[from];
+            if (dirichlet) dir_c[to] = dirichlet[from];
+        }
+    return gs_build_std(E, N, glo_c.data(), dirichlet ? dir_c.data() : nullptr, H, msg);
+}
 
 void gs_attach(const GsHost &H, void *arena, size_t own_offset, GsDevice &d) {
     d.E = H.E;
@@ -420,19 +454,28 @@ int nek_gs_create(int64_t E, int N, const int64_t *glo, const uint8_t *dirichlet
     if (E < 1) return fail(NEK_ERR_ARG, "nek_gs_create: E must be >= 1");
     if (N < 1 || N > NEK_MAX_DEGREE) return fail(NEK_ERR_UNSUPPORTED, "nek_gs_create: degree must be in 1..15");
     if (!glo) return fail(NEK_ERR_ARG, "nek_gs_create: glo is null");
-    GsHost H;
+    GsHost H, Hc;
     std::string msg;
-    int rc = gs_build_host(E, N, glo, dirichlet, H, msg);
+    int rc = gs_build_host(E, N, glo, dirichlet, false, H, msg);
+    if (rc == NEK_OK) rc = gs_build_host(E, N, glo, dirichlet, true, Hc, msg);
     if (rc != NEK_OK) return fail(rc, "nek_gs_create: " + msg);
     nek_gs *h = new nek_gs();
-    void *arena = nullptr;
-    hipError_t e = hipMalloc(&arena, H.arena_bytes());
-    if (e == hipSuccess && !H.idx.empty())
-        e = hipMemcpy(arena, H.idx.data(), H.idx.size() * sizeof(int32_t), hipMemcpyHostToDevice);
-    if (e == hipSuccess)
-        e = hipMemcpy((char *)arena + H.idx_bytes(), H.own.data(), H.own.size() * sizeof(uint32_t),
-                      hipMemcpyHostToDevice);
-    h->d.arena = arena;
+    // one arena per map: the index arrays, then the first-copy bits
+    auto upload = [](const GsHost &M, GsDevice &d) -> hipError_t {
+        void *arena = nullptr;
+        hipError_t e = hipMalloc(&arena, M.arena_bytes());
+        if (e != hipSuccess) return e;
+        d.arena = arena;
+        if (!M.idx.empty())
+            e = hipMemcpy(arena, M.idx.data(), M.idx.size() * sizeof(int32_t), hipMemcpyHostToDevice);
+        if (e == hipSuccess)
+            e = hipMemcpy((char *)arena + M.idx_bytes(), M.own.data(), M.own.size() * sizeof(uint32_t),
+                          hipMemcpyHostToDevice);
+        if (e == hipSuccess) gs_attach(M, arena, M.idx_bytes(), d);
+        return e;
+    };
+    hipError_t e = upload(H, h->d);
+    if (e == hipSuccess) e = upload(Hc, h->cg);
     if (e == hipSuccess) e = hipMalloc((void **)&h->partials, RED_SITE_DOUBLES * sizeof(double));
     if (e == hipSuccess) e = hipMalloc((void **)&h->ticket, RED_TICKETS * sizeof(unsigned int));
     if (e == hipSuccess) e = hipMemset(h->ticket, 0, RED_TICKETS * sizeof(unsigned int));
@@ -441,7 +484,6 @@ int nek_gs_create(int64_t E, int N, const int64_t *glo, const uint8_t *dirichlet
         return fail(e == hipErrorOutOfMemory ? NEK_ERR_NOMEM : NEK_ERR_DEVICE,
                     std::string("nek_gs_create: ") + hipGetErrorString(e));
     }
-    gs_attach(H, arena, H.idx_bytes(), h->d);
     *out = h;
     return NEK_OK;
 }
@@ -517,7 +559,7 @@ void nek_cg_default_opts(nek_cg_opts *o) {
 
 size_t nek_cg_workspace_bytes(int64_t E, int N) {
     if (E < 1 || N < 1 || N > NEK_MAX_DEGREE) return 0;
-    return cg_layout(E, N).total;
+    return cg_layout(E, N, 2).total;
 }
 
 namespace {
@@ -572,7 +614,9 @@ int nek_cg_solve(int64_t E, int N, const double *D, const double *g, const nek_g
 
     hipStream_t s = (hipStream_t)stream_v;
     const int64_t P = E * n3_of(N);
-    const size_t need = nek_cg_workspace_bytes(E, N);
+    // b and (with a preconditioner) M^-1 get a copy in the CG layout
+    const int extra = opts.dinv ? 2 : 1;
+    const size_t need = cg_layout(E, N, extra).total;
     char *ws = (char *)opts.workspace;
     bool own_ws = false;
     if (ws) {
@@ -585,7 +629,7 @@ int nek_cg_solve(int64_t E, int N, const double *D, const double *g, const nek_g
                         std::string("nek_cg_solve: workspace allocation: ") + hipGetErrorString(e));
         own_ws = true;
     }
-    const CgWs W = cg_ws(ws, E, N);
+    const CgWs W = cg_ws(ws, E, N, extra);
     double *r = W.r, *p = W.p, *w = W.w, *axp = W.axp, *scratch1 = W.scratch;
     unsigned int *tickets = W.tickets;
     CgScalars *sc = W.sc;
@@ -599,7 +643,8 @@ int nek_cg_solve(int64_t E, int N, const double *D, const double *g, const nek_g
         }
     }
     CgScalars *snap = g_snap.buf;
-    const uint32_t *own = gs->d.own_bits;
+    const uint32_t *own = gs->cg.own_bits;
+    const double *bc = W.b, *dinvc = W.dinv;   // b and M^-1 in the CG layout
     const int64_t ax_parts = ax_blocks(E, N);
 
     // one CG iteration; `first` uses p = b as set by the init kernel
@@ -608,25 +653,28 @@ int nek_cg_solve(int64_t E, int N, const double *D, const double *g, const nek_g
         AxFuse fz;
         fz.sc = sc;
         fz.partials = axp;
+        fz.cg_layout = true;
         if (!first) {
             fz.r = r;
             fz.x = x;
-            fz.dinv = opts.dinv;
+            fz.dinv = dinvc;
         }
         hipError_t e = mixed ? launch_ax_f32(E, N, opts.D32, opts.g_lo, g_dtype, p, w, fz, s)
                              : launch_ax_f64(E, N, D, g, p, w, fz, s);
         if (e != hipSuccess) return e;
-        e = launch_gs(gs->d, w, axp, ax_parts, sc, s);
+        e = launch_gs(gs->cg, w, axp, ax_parts, sc, s);
         if (e != hipSuccess) return e;
-        return launch_cg_update(P, r, w, own, opts.dinv, red_upd, sc, s);
+        return launch_cg_update(P, r, w, own, dinvc, red_upd, sc, s);
     };
+    AxFuse plain_cg;   // A x alone, on CG-layout vectors
+    plain_cg.cg_layout = true;
     // w <- mask(dssum(A64 x)) with x brought up to date first
     auto true_ax = [&]() -> hipError_t {
         hipError_t e = launch_cg_finish(P, x, p, sc, s);
         if (e != hipSuccess) return e;
-        e = launch_ax_f64(E, N, D, g, x, w, AxFuse{}, s);
+        e = launch_ax_f64(E, N, D, g, x, w, plain_cg, s);
         if (e != hipSuccess) return e;
-        return launch_gs(gs->d, w, nullptr, 0, nullptr, s);
+        return launch_gs(gs->cg, w, nullptr, 0, nullptr, s);
     };
 
     int rc = NEK_OK;
@@ -642,7 +690,9 @@ int nek_cg_solve(int64_t E, int N, const double *D, const double *g, const nek_g
     hipEvent_t ev[2] = {nullptr, nullptr};
     {
         CG_TRY(launch_cg_reset(sc, tickets, N_SITES * RED_TICKETS, opts.max_iter, opts.rel_tol, drop, s));
-        CG_TRY(launch_cg_init(P, b, x, r, p, own, opts.dinv, site(SITE_INIT, nullptr, 0), sc, s));
+        CG_TRY(launch_permute(E, N, b, W.b, true, s));
+        if (opts.dinv) CG_TRY(launch_permute(E, N, opts.dinv, W.dinv, true, s));
+        CG_TRY(launch_cg_init(P, bc, x, r, p, own, dinvc, site(SITE_INIT, nullptr, 0), sc, s));
         if (poll) {
             CG_TRY(hipEventCreateWithFlags(&ev[0], hipEventDisableTiming));
             CG_TRY(hipEventCreateWithFlags(&ev[1], hipEventDisableTiming));
@@ -673,7 +723,7 @@ int nek_cg_solve(int64_t E, int N, const double *D, const double *g, const nek_g
                 // per snapshot that asked for it
                 if (mixed && v.need_replace && v.n_replace >= replacements) {
                     CG_TRY(true_ax());
-                    CG_TRY(launch_cg_replace(P, b, w, r, own, site(SITE_REPLACE, nullptr, 0), sc, s));
+                    CG_TRY(launch_cg_replace(P, bc, w, r, own, site(SITE_REPLACE, nullptr, 0), sc, s));
                     ++replacements;
                 }
             }
@@ -681,19 +731,21 @@ int nek_cg_solve(int64_t E, int N, const double *D, const double *g, const nek_g
         }
         CG_TRY(launch_cg_finish(P, x, p, sc, s));
         CG_TRY(hipMemcpyAsync(&snap[2], sc, sizeof(CgScalars), hipMemcpyDeviceToHost, s));
-        CG_TRY(hipStreamSynchronize(s));
-        S = snap[2];
         if (opts.true_residual || mixed) {
             // ||b - mask(dssum(A64 x))|| over unique nodes, in FP64 (x is up to date:
             // the finish kernel above ran; running it again is a no-op only if the
             // lag flag says so, so evaluate A x directly)
-            CG_TRY(launch_ax_f64(E, N, D, g, x, w, AxFuse{}, s));
-            CG_TRY(launch_gs(gs->d, w, nullptr, 0, nullptr, s));
-            CG_TRY(launch_gdiff2(P, b, w, own, site(SITE_RESID, nullptr, 0), scratch1, s));
+            CG_TRY(launch_ax_f64(E, N, D, g, x, w, plain_cg, s));
+            CG_TRY(launch_gs(gs->cg, w, nullptr, 0, nullptr, s));
+            CG_TRY(launch_gdiff2(P, bc, w, own, site(SITE_RESID, nullptr, 0), scratch1, s));
             CG_TRY(hipMemcpyAsync(&snap[3].bb, scratch1, sizeof(double), hipMemcpyDeviceToHost, s));
-            CG_TRY(hipStreamSynchronize(s));
-            true_rel = S.bb > 0.0 ? sqrt(snap[3].bb / S.bb) : 0.0;
         }
+        // x back to the layout of Listing 1 (through w, which is free now)
+        CG_TRY(launch_permute(E, N, x, w, false, s));
+        CG_TRY(hipMemcpyAsync(x, w, (size_t)P * sizeof(double), hipMemcpyDeviceToDevice, s));
+        CG_TRY(hipStreamSynchronize(s));
+        S = snap[2];
+        if (opts.true_residual || mixed) true_rel = S.bb > 0.0 ? sqrt(snap[3].bb / S.bb) : 0.0;
     }
 out:
 #undef CG_TRY

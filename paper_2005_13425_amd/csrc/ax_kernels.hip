@@ -106,7 +106,25 @@ struct GLoad<float, uint16_t, N3> {
     }
 };
 
-// T: compute type (double or float); GT: storage type of g; FUSE: CG fusion.
+// The point (i, j) of a layer at within-layer offset c of the CG layout (the
+// inverse of cgl_col).
+template <int NX>
+__device__ __forceinline__ void cgl_point(int c, int &i, int &j) {
+    constexpr int M = NX - 2;   // interior points per row
+    if (c >= NX * (NX - 1)) {
+        i = NX - 1;
+        j = c - NX * (NX - 1);
+    } else if (c >= NX * M) {
+        i = 0;
+        j = c - NX * M;
+    } else if constexpr (M > 0) {
+        j = c / M;
+        i = c - j * M + 1;
+    }
+}
+
+// T: compute type (double or float); GT: storage type of g; FUSE: CG fusion;
+// CGL: p, r, x, dinv and w in the CG layout (g always in that of Listing 1).
 //
 // Per element, two LDS buffers B0, B1 of n^3 (padded) values.  Thread (a, b)
 // of an element plays three roles: the column (i,j) = (a,b), the r-pencil
@@ -128,7 +146,10 @@ struct GLoad<float, uint16_t, N3> {
 // the workgroup) is live at a time, so it stays in scalar registers.  Two
 // buffers instead of three keep more elements resident per CU (the high
 // degrees were occupancy-bound).  Six workgroup barriers per element.
-template <int NX, typename T, typename GT, bool FUSE>
+// In the CG layout thread (a, b) loads and stores the vector entries at
+// offset c = a + n b of each layer, which belong to another column; they pass
+// through LDS, with one more barrier before w is stored.
+template <int NX, typename T, typename GT, bool FUSE, bool CGL>
 __device__ __forceinline__ void ax_body(int64_t blk, int64_t E, kptr<T> D, gptr<const GT> g,
                                         gptr<double> p, gptr<double> w, const AxFuse &fz)
 {
@@ -137,7 +158,7 @@ __device__ __forceinline__ void ax_body(int64_t blk, int64_t E, kptr<T> D, gptr<
     // from N = 7 up: 8-12% faster at E = 4096 and on the 32.8 M-point boxes
     // (N = 7..15), 9% slower at N = 5.  The CG-fused form re-reads p, r, x
     // and w soon after and keeps the default caching.
-    constexpr bool STREAM = !FUSE && sizeof(T) == 8 && NX >= 8;
+    constexpr bool STREAM = !FUSE && !CGL && sizeof(T) == 8 && NX >= 8;
     constexpr int NN = S::NN;
     constexpr int N3 = S::N3;
     constexpr int EPB = S::EPB;
@@ -169,10 +190,19 @@ __device__ __forceinline__ void ax_body(int64_t blk, int64_t E, kptr<T> D, gptr<
     const int col = b * RS + a;       // column (a,b) within a layer
     const int rpen = b * LS + a * RS; // start of r-pencil (:,a,b)
     const int spen = b * LS + a;      // start of s-pencil (a,:,b), stride RS
+    // Vector entries (p, r, x, dinv, w) this thread moves between HBM and LDS:
+    // offset c + k n^2 of the element, which is point (a, b, k) in the layout
+    // of Listing 1 and point (av, bv, k) in the CG layout.  g is always read
+    // for the thread's own column (a, b).
+    int av = a, bv = b;
+    if constexpr (CGL) cgl_point<NX>(c, av, bv);
+    const int colv = bv * RS + av;
 
     // ---- 1. u column (in the CG: x += alpha p_old and p <- r + beta p_old first)
     const int64_t base = e * N3 + c;
-    double pcol[FUSE ? NX : 1];       // FP64 p of this column, for the interior (p, w) sum
+    // FP64 p at the thread's vector entries, for the (p, w) sum (the CG layout
+    // reads it back from memory at the end instead: fewer registers)
+    double pcol[FUSE && !CGL ? NX : 1];
     {
         double pv[NX];
         if (active) {
@@ -208,13 +238,13 @@ __device__ __forceinline__ void ax_body(int64_t blk, int64_t E, kptr<T> D, gptr<
 #pragma unroll
             for (int k = 0; k < NX; ++k) pv[k] = 0.0;
         }
-        if constexpr (FUSE) {
+        if constexpr (FUSE && !CGL) {
 #pragma unroll
             for (int k = 0; k < NX; ++k) pcol[k] = pv[k];
         }
         if (in_slab) {
 #pragma unroll
-            for (int k = 0; k < NX; ++k) B0[k * LS + col] = (T)pv[k];
+            for (int k = 0; k < NX; ++k) B0[k * LS + colv] = (T)pv[k];
         }
     }
 
@@ -332,13 +362,28 @@ __device__ __forceinline__ void ax_body(int64_t blk, int64_t E, kptr<T> D, gptr<
 #pragma unroll
             for (int l = 0; l < NX; ++l) pt += Di[l] * ut[l];
             const T wv = (B0[i * LS + col] + B1[i * LS + col]) + pt;
-            if constexpr (STREAM) __builtin_nontemporal_store((double)wv, &w[base + i * NN]);
-            else w[base + i * NN] = (double)wv;
-            if constexpr (FUSE) B0[i * LS + col] = wv;   // the column's own slots
+            if constexpr (CGL) {
+                B0[i * LS + col] = wv;                   // stored below, from another thread
+            } else {
+                if constexpr (STREAM) __builtin_nontemporal_store((double)wv, &w[base + i * NN]);
+                else w[base + i * NN] = (double)wv;
+                if constexpr (FUSE) B0[i * LS + col] = wv;   // the column's own slots
+            }
         }
     }
     double pw = 0.0;
-    if constexpr (FUSE) {
+    if constexpr (CGL) {
+        // ---- 6b. w leaves LDS at the thread's CG-layout entries
+        __syncthreads();
+        if (active) {
+#pragma unroll
+            for (int k = 0; k < NX; ++k) {
+                const T wv = B0[k * LS + colv];
+                w[base + k * NN] = (double)wv;
+                if constexpr (FUSE) pw += p[base + k * NN] * (double)wv;   // written by this thread
+            }
+        }
+    } else if constexpr (FUSE) {
         if (active) {
 #pragma unroll
             for (int k = 0; k < NX; ++k) pw += pcol[k] * (double)B0[k * LS + col];
@@ -356,13 +401,13 @@ __device__ __forceinline__ void ax_body(int64_t blk, int64_t E, kptr<T> D, gptr<
     }
 }
 
-template <int NX, typename T, typename GT, bool FUSE>
+template <int NX, typename T, typename GT, bool FUSE, bool CGL>
 __global__ void __launch_bounds__((AxShape<NX, T>::THREADS),
-                                  (FUSE ? AxShape<NX, T>::MINW_FUSED : AxShape<NX, T>::MINW))
+                                  (FUSE || CGL ? AxShape<NX, T>::MINW_FUSED : AxShape<NX, T>::MINW))
 ax_kernel(int64_t E, const T *__restrict__ D, const GT *__restrict__ g, double *__restrict__ p,
           double *__restrict__ w, AxFuse fz)
 {
-    ax_body<NX, T, GT, FUSE>(blockIdx.x, E, (kptr<T>)D, (gptr<const GT>)g, (gptr<double>)p,
+    ax_body<NX, T, GT, FUSE, CGL>(blockIdx.x, E, (kptr<T>)D, (gptr<const GT>)g, (gptr<double>)p,
                              (gptr<double>)w, fz);
 }
 
@@ -375,7 +420,7 @@ __global__ void __launch_bounds__((AxShape<NX, T>::THREADS), (AxShape<NX, T>::MI
 ax_batch_kernel(const AxSlot *__restrict__ slots, int nslots)
 {
     const AxSlot S = slots[batch_slot(slots, nslots, (int64_t)blockIdx.x)];
-    ax_body<NX, T, GT, true>((int64_t)blockIdx.x - S.block0, S.E, (kptr<T>)S.D, (gptr<const GT>)S.g,
+    ax_body<NX, T, GT, true, true>((int64_t)blockIdx.x - S.block0, S.E, (kptr<T>)S.D, (gptr<const GT>)S.g,
                              (gptr<double>)S.p, (gptr<double>)S.w, S.fz);
 }
 
@@ -395,12 +440,21 @@ hipError_t launch_one(int64_t E, const T *D, const GT *g, double *p, double *w, 
     using S = AxShape<NX, T>;
     const int64_t blocks = (E + S::EPB - 1) / S::EPB;
     if (blocks > 0x7fffffff) return hipErrorInvalidValue;
-    if (fz.sc != nullptr)
-        hipLaunchKernelGGL((ax_kernel<NX, T, GT, true>), dim3((unsigned)blocks), dim3(S::THREADS),
+    // the CG-fused form always works in the CG layout
+    if (fz.sc != nullptr) {
+        if (!fz.cg_layout) return hipErrorInvalidValue;
+        hipLaunchKernelGGL((ax_kernel<NX, T, GT, true, true>), dim3((unsigned)blocks), dim3(S::THREADS),
                            0, s, E, D, g, p, w, fz);
-    else
-        hipLaunchKernelGGL((ax_kernel<NX, T, GT, false>), dim3((unsigned)blocks), dim3(S::THREADS),
+    } else if (fz.cg_layout) {
+        if constexpr (sizeof(T) == 8)
+            hipLaunchKernelGGL((ax_kernel<NX, T, GT, false, true>), dim3((unsigned)blocks),
+                               dim3(S::THREADS), 0, s, E, D, g, p, w, fz);
+        else
+            return hipErrorInvalidValue;
+    } else {
+        hipLaunchKernelGGL((ax_kernel<NX, T, GT, false, false>), dim3((unsigned)blocks), dim3(S::THREADS),
                            0, s, E, D, g, p, w, fz);
+    }
     return hipGetLastError();
 }
 

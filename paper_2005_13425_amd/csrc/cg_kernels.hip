@@ -451,7 +451,35 @@ gdot_kernel(int64_t P, const double *__restrict__ a, const double *__restrict__ 
     if (grid_finish<VEC_THREADS>(s, red, &tot, lds) && threadIdx.x == 0) *result = tot;
 }
 
+// ---------------------------------------------------------------- layout conversion
+constexpr int PERM_THREADS = 256;
+constexpr int64_t PERM_MAX_BLOCKS = 65536;
+
+// Workgroups stride over elements; threads over an element's points in the
+// order of Listing 1 (coalesced on that side).
+__global__ void __launch_bounds__(PERM_THREADS)
+permute_kernel(int64_t E, int n, const double *__restrict__ src, double *__restrict__ dst, bool to_cg) {
+    const int n3 = n * n * n;
+    for (int64_t e = blockIdx.x; e < E; e += gridDim.x) {
+        const int64_t base = e * n3;
+        for (int l = threadIdx.x; l < n3; l += PERM_THREADS) {
+            const int nn = n * n, k = l / nn, ij = l - k * nn;
+            const int64_t c = base + k * nn + cgl_col(ij % n, ij / n, n);
+            if (to_cg) dst[c] = src[base + l];
+            else dst[base + l] = src[c];
+        }
+    }
+}
+
 }  // namespace
+
+hipError_t launch_permute(int64_t E, int N, const double *src, double *dst, bool to_cg, hipStream_t s) {
+    if (E < 1) return hipSuccess;
+    const int64_t blocks = E < PERM_MAX_BLOCKS ? E : PERM_MAX_BLOCKS;
+    hipLaunchKernelGGL(permute_kernel, dim3((unsigned)blocks), dim3(PERM_THREADS), 0, s, E, N + 1, src, dst,
+                       to_cg);
+    return hipGetLastError();
+}
 
 int64_t vec_blocks(int64_t P) {
     const int64_t per = (int64_t)VEC_THREADS * VEC_PAIRS * 2;

@@ -28,6 +28,21 @@ inline bool aligned8(const void *p) { return ((uintptr_t)p & 7u) == 0; }
 
 inline int64_t n3_of(int N) { return (int64_t)(N + 1) * (N + 1) * (N + 1); }
 
+// ---------------------------------------------------------------- CG layout
+// Inside the CG every local vector (x, r, p, w, b, M^-1) is stored in the "CG
+// layout": element by element and layer k by layer k as in Listing 1, but
+// within a layer first the points with 0 < i < n-1 (i fastest, then j), then
+// the n points with i = 0, then the n points with i = n-1 (each in j order).
+// The faces at fixed i, which the gather-scatter reads and writes most, become
+// n runs of n contiguous values instead of n^2 values at stride n; the faces
+// at fixed j and k stay runs of at least n-2.  A column (i, j) keeps the
+// stride n^2 in k.  The user's b and x keep the layout of Listing 1; the
+// solver converts on the way in and out.
+// Offset of (i, j, k) within an element: k n^2 + cgl_col(i, j, n).
+__host__ __device__ inline int cgl_col(int i, int j, int n) {
+    return i == 0 ? n * (n - 2) + j : (i == n - 1 ? n * (n - 1) + j : j * (n - 2) + i - 1);
+}
+
 // ---------------------------------------------------------------- CG scalars
 // Device-side CG state (one struct in device memory, written only by the
 // last workgroup of a reduction kernel or by single-thread kernels).
@@ -71,6 +86,9 @@ struct AxFuse {
     double *partials = nullptr;
     const CgScalars *sc = nullptr;
     const double *dinv = nullptr;
+    // vectors p, r, x, dinv and w in the CG layout.  Always the case with
+    // sc != null; without it, FP64 only (the true residual of a CG).
+    bool cg_layout = false;
 };
 
 hipError_t launch_ax_f64(int64_t E, int N, const double *D, const double *g, double *p, double *w,
@@ -159,8 +177,9 @@ struct GsHost {
 
 // Build the host image from glo[P] / dirichlet[P] (NULL = none); returns
 // NEK_OK or an error code with msg set.
-int gs_build_host(int64_t E, int N, const int64_t *glo, const uint8_t *dirichlet, GsHost &out,
-                  std::string &msg);
+// cg_layout: index the copies by their position in the CG layout.
+int gs_build_host(int64_t E, int N, const int64_t *glo, const uint8_t *dirichlet, bool cg_layout,
+                  GsHost &out, std::string &msg);
 
 struct GsDevice;
 // Point a device handle at an arena that holds (or will hold) h's image: the
@@ -228,6 +247,9 @@ hipError_t launch_update_batch(const UpdSlot *slots, int nslots, int64_t blocks,
 // copy the scalars of several solves into one contiguous array
 hipError_t launch_gather_scalars(CgScalars *const *src, int n, CgScalars *dst, hipStream_t s);
 hipError_t launch_cg_finish(int64_t P, double *x, const double *p, const CgScalars *sc, hipStream_t s);
+// dst <- src converted between the layout of Listing 1 and the CG layout
+// (to_cg: Listing 1 -> CG); dst and src must not overlap
+hipError_t launch_permute(int64_t E, int N, const double *src, double *dst, bool to_cg, hipStream_t s);
 hipError_t launch_cg_replace(int64_t P, const double *b, const double *w, double *r,
                              const uint32_t *own, const RedSite &red, CgScalars *sc, hipStream_t s);
 // result <- sum own * a * b / sum own * (a - b)^2, deterministic, one device double
@@ -248,29 +270,34 @@ inline RedSite red_site(double *mem, unsigned int *tickets, const double *extra 
 inline size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 // CG workspace: r, p, w | (p, A_L p) partials of ax | reduction sites |
-// their counters | CG scalars | one scratch double.
+// their counters | CG scalars | one scratch double | `extra` more vectors
+// (nek_cg_solve: b and M^-1 in the CG layout; the server keeps b in its own
+// arena and takes none).
 enum { SITE_INIT, SITE_UPDATE, SITE_REPLACE, SITE_RESID, N_SITES };
 
 struct CgLayout {
-    size_t vec, axp, sites, tickets, scalars, scratch, total;
+    size_t vec, axp, sites, tickets, scalars, scratch, extra, total;
 };
 
-inline CgLayout cg_layout(int64_t E, int N) {
+inline CgLayout cg_layout(int64_t E, int N, int extra) {
     const size_t P = (size_t)(E * n3_of(N));
+    const size_t vb = align256(P * sizeof(double));
     CgLayout L;
     L.vec = 0;
-    L.axp = 3 * align256(P * sizeof(double));
+    L.axp = 3 * vb;
     L.sites = L.axp + align256((size_t)ax_blocks(E, N) * sizeof(double));
     L.tickets = L.sites + align256(N_SITES * RED_SITE_DOUBLES * sizeof(double));
     L.scalars = L.tickets + align256(N_SITES * RED_TICKETS * sizeof(unsigned int));
     L.scratch = L.scalars + align256(sizeof(CgScalars));
-    L.total = L.scratch + align256(sizeof(double));
+    L.extra = L.scratch + align256(sizeof(double));
+    L.total = L.extra + (size_t)extra * vb;
     return L;
 }
 
 // Pointers into one CG workspace.
 struct CgWs {
     double *r, *p, *w, *axp, *site_mem, *scratch;
+    double *b = nullptr, *dinv = nullptr;   // the extra vectors, if any
     unsigned int *tickets;
     CgScalars *sc;
     RedSite site(int k, const double *extra = nullptr, long nextra = 0) const {
@@ -279,8 +306,8 @@ struct CgWs {
     }
 };
 
-inline CgWs cg_ws(void *ws, int64_t E, int N) {
-    const CgLayout L = cg_layout(E, N);
+inline CgWs cg_ws(void *ws, int64_t E, int N, int extra) {
+    const CgLayout L = cg_layout(E, N, extra);
     char *c = (char *)ws;
     const size_t vb = align256((size_t)(E * n3_of(N)) * sizeof(double));
     CgWs W;
@@ -292,6 +319,8 @@ inline CgWs cg_ws(void *ws, int64_t E, int N) {
     W.tickets = (unsigned int *)(c + L.tickets);
     W.sc = (CgScalars *)(c + L.scalars);
     W.scratch = (double *)(c + L.scratch);
+    if (extra >= 1) W.b = (double *)(c + L.extra);
+    if (extra >= 2) W.dinv = (double *)(c + L.extra + vb);
     return W;
 }
 

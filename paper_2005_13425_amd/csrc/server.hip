@@ -50,7 +50,7 @@ Footprint footprint_of(int64_t E, int N, int prec) {
     f.D32 = align256(n2 * sizeof(float));
     f.glo = prec == NEK_PREC_F32G32 ? align256(6 * P * sizeof(float))
           : prec == NEK_PREC_F32GBF16 ? align256(6 * P * sizeof(uint16_t)) : 0;
-    f.ws = cg_layout(E, N).total;
+    f.ws = cg_layout(E, N, 0).total;
     f.arena = f.g + f.b + f.gs + f.D + f.D32 + f.glo + f.ws;
     f.x = align256(P * sizeof(double));
     f.total = f.arena + f.x;
@@ -254,7 +254,7 @@ struct nek_server {
         std::vector<int64_t> glo((size_t)P);
         std::vector<uint8_t> dr((size_t)P);
         nek_box_numbering(q.Ex, q.Ey, q.Ez, q.N, glo.data(), dr.data());
-        R->prep_status = gs_build_host(R->E, q.N, glo.data(), dr.data(), R->gs, R->prep_msg);
+        R->prep_status = gs_build_host(R->E, q.N, glo.data(), dr.data(), true, R->gs, R->prep_msg);
         if (R->prep_status == NEK_OK) {
             const int n = q.N + 1;
             R->off_idx = align256(P * sizeof(double));
@@ -341,10 +341,12 @@ struct nek_server {
         a += f.D32;
         S->glo = f.glo ? (void *)a : nullptr;
         a += f.glo;
-        S->W = cg_ws(a, R->E, q.N);
+        S->W = cg_ws(a, R->E, q.N, 0);
         // uploads (pinned staging) and device setup, all on the server stream
         const char *st = (const char *)R->staging;
-        NEK_HIP(hipMemcpyAsync(S->b, st, (size_t)R->P * sizeof(double), hipMemcpyHostToDevice, stream));
+        // b arrives in the layout of Listing 1 (through w) and is kept in the CG layout
+        NEK_HIP(hipMemcpyAsync(S->W.w, st, (size_t)R->P * sizeof(double), hipMemcpyHostToDevice, stream));
+        NEK_HIP(launch_permute(R->E, q.N, S->W.w, S->b, true, stream));
         const size_t own_off = R->gs.idx_bytes();   // == off_own - off_idx
         NEK_HIP(hipMemcpyAsync(gs_arena, st + R->off_idx, own_off, hipMemcpyHostToDevice, stream));
         NEK_HIP(hipMemcpyAsync(gs_arena + own_off, st + R->off_own, R->gs.own.size() * sizeof(uint32_t),
@@ -448,6 +450,7 @@ struct nek_server {
             A.fz.x = S->x;
             A.fz.partials = S->W.axp;
             A.fz.sc = S->W.sc;
+            A.fz.cg_layout = true;
             G.ax_blocks += ax_blocks(S->req->E, q.N);
             GsSlot &Gs = gsl[i];
             Gs.block0 = G.gs_blocks;
@@ -490,14 +493,24 @@ struct nek_server {
                 if (p == S) p = nullptr;
     }
 
+    // A x alone, on vectors in the CG layout
+    static AxFuse plain_cg() {
+        AxFuse f;
+        f.cg_layout = true;
+        return f;
+    }
+
     int start_finish(Slot *S) {
         forget_in_snapshots(S);
         const nek_request &q = S->req->spec;
         const int64_t E = S->req->E, P = S->req->P;
         NEK_HIP(launch_cg_finish(P, S->x, S->W.p, S->W.sc, stream));
-        NEK_HIP(launch_ax_f64(E, q.N, S->D, S->g, S->x, S->W.w, AxFuse{}, stream));
+        NEK_HIP(launch_ax_f64(E, q.N, S->D, S->g, S->x, S->W.w, plain_cg(), stream));
         NEK_HIP(launch_gs(S->gsd, S->W.w, nullptr, 0, nullptr, stream));
         NEK_HIP(launch_gdiff2(P, S->b, S->W.w, S->gsd.own_bits, S->W.site(SITE_RESID), S->W.scratch, stream));
+        // x back to the layout of Listing 1 (through w)
+        NEK_HIP(launch_permute(E, q.N, S->x, S->W.w, false, stream));
+        NEK_HIP(hipMemcpyAsync(S->x, S->W.w, (size_t)P * sizeof(double), hipMemcpyDeviceToDevice, stream));
         NEK_HIP(hipMemcpyAsync(&fin[S->index].sc, S->W.sc, sizeof(CgScalars), hipMemcpyDeviceToHost, stream));
         NEK_HIP(hipMemcpyAsync(&fin[S->index].t2, S->W.scratch, sizeof(double), hipMemcpyDeviceToHost, stream));
         NEK_HIP(hipEventCreateWithFlags(&S->ev_fin, hipEventDisableTiming));
@@ -511,7 +524,7 @@ struct nek_server {
         const nek_request &q = S->req->spec;
         const int64_t E = S->req->E, P = S->req->P;
         NEK_HIP(launch_cg_finish(P, S->x, S->W.p, S->W.sc, stream));
-        NEK_HIP(launch_ax_f64(E, q.N, S->D, S->g, S->x, S->W.w, AxFuse{}, stream));
+        NEK_HIP(launch_ax_f64(E, q.N, S->D, S->g, S->x, S->W.w, plain_cg(), stream));
         NEK_HIP(launch_gs(S->gsd, S->W.w, nullptr, 0, nullptr, stream));
         NEK_HIP(launch_cg_replace(P, S->b, S->W.w, S->W.r, S->gsd.own_bits, S->W.site(SITE_REPLACE),
                                   S->W.sc, stream));
