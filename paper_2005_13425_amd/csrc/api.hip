@@ -379,9 +379,16 @@ int gs_build_std(int64_t E, int N, const int64_t *glo, const uint8_t *dirichlet,
     }
     const size_t words = (size_t)((P + 31) / 32);
     H.own.assign(words, 0u);
+    H.rowed.assign(words, 0u);
     for (int64_t G = 0; G < U; ++G) {
-        const int32_t L = copies[(size_t)start[(size_t)G]];
+        const int32_t c0 = start[(size_t)G], c1 = start[(size_t)G + 1];
+        const int32_t L = copies[(size_t)c0];
         H.own[(size_t)L >> 5] |= 1u << (L & 31);
+        if (c1 - c0 > 1 || masked[(size_t)G])
+            for (int32_t q = c0; q < c1; ++q) {
+                const int32_t Lq = copies[(size_t)q];
+                H.rowed[(size_t)Lq >> 5] |= 1u << (Lq & 31);
+            }
     }
     return NEK_OK;
 }
@@ -417,7 +424,7 @@ int gs_build_host(int64_t E, int N, const int64_t *glo, const uint8_t *dirichlet
     return gs_build_std(E, N, glo_c.data(), dirichlet ? dir_c.data() : nullptr, H, msg);
 }
 
-void gs_attach(const GsHost &H, void *arena, size_t own_offset, GsDevice &d) {
+void gs_attach(const GsHost &H, void *arena, GsDevice &d) {
     d.E = H.E;
     d.N = H.N;
     d.P = H.P;
@@ -427,7 +434,8 @@ void gs_attach(const GsHost &H, void *arena, size_t own_offset, GsDevice &d) {
     d.n_masked = H.n_masked;
     d.n_zero = H.n_zero;
     d.arena = arena;
-    d.own_bits = (uint32_t *)((char *)arena + own_offset);
+    d.own_bits = (uint32_t *)((char *)arena + H.idx_bytes());
+    d.rowed_bits = (uint32_t *)((char *)arena + H.idx_bytes() + H.own_bytes());
     const int32_t *base = (const int32_t *)arena;
     d.args.ngroups = 0;
     int32_t blocks = 0;
@@ -471,7 +479,10 @@ int nek_gs_create(int64_t E, int N, const int64_t *glo, const uint8_t *dirichlet
         if (e == hipSuccess)
             e = hipMemcpy((char *)arena + M.idx_bytes(), M.own.data(), M.own.size() * sizeof(uint32_t),
                           hipMemcpyHostToDevice);
-        if (e == hipSuccess) gs_attach(M, arena, M.idx_bytes(), d);
+        if (e == hipSuccess)
+            e = hipMemcpy((char *)arena + M.idx_bytes() + M.own_bytes(), M.rowed.data(),
+                          M.rowed.size() * sizeof(uint32_t), hipMemcpyHostToDevice);
+        if (e == hipSuccess) gs_attach(M, arena, d);
         return e;
     };
     hipError_t e = upload(H, h->d);
@@ -512,7 +523,7 @@ int nek_dssum(const nek_gs *gs, double *w, void *stream) {
     clear_error();
     if (!gs || !w) return fail(NEK_ERR_ARG, "nek_dssum: null argument");
     if (!aligned8(w)) return fail(NEK_ERR_ARG, "nek_dssum: misaligned w");
-    NEK_HIP(launch_gs(gs->d, w, nullptr, 0, nullptr, (hipStream_t)stream));
+    NEK_HIP(launch_gs(gs->d, w, (hipStream_t)stream));
     return NEK_OK;
 }
 
@@ -530,7 +541,7 @@ int nek_jacobi_inverse(int64_t E, int N, const double *D, const double *g, const
         return fail(NEK_ERR_ARG, "nek_jacobi_inverse: gather-scatter built for another mesh");
     const hipStream_t s = (hipStream_t)stream;
     NEK_HIP(launch_ax_diag(E, N, D, g, dinv, s));
-    NEK_HIP(launch_gs(gs->d, dinv, nullptr, 0, nullptr, s));   // assembled diagonal, 0 at masked nodes
+    NEK_HIP(launch_gs(gs->d, dinv, s));   // assembled diagonal, 0 at masked nodes
     NEK_HIP(launch_reciprocal(E * n3_of(N), dinv, s));
     return NEK_OK;
 }
@@ -630,7 +641,7 @@ int nek_cg_solve(int64_t E, int N, const double *D, const double *g, const nek_g
         own_ws = true;
     }
     const CgWs W = cg_ws(ws, E, N, extra);
-    double *r = W.r, *p = W.p, *w = W.w, *axp = W.axp, *scratch1 = W.scratch;
+    double *r = W.r, *p = W.p, *w = W.w, *scratch1 = W.scratch;
     unsigned int *tickets = W.tickets;
     CgScalars *sc = W.sc;
     auto site = [&](int k, const double *extra, long nextra) { return W.site(k, extra, nextra); };
@@ -645,14 +656,13 @@ int nek_cg_solve(int64_t E, int N, const double *D, const double *g, const nek_g
     CgScalars *snap = g_snap.buf;
     const uint32_t *own = gs->cg.own_bits;
     const double *bc = W.b, *dinvc = W.dinv;   // b and M^-1 in the CG layout
-    const int64_t ax_parts = ax_blocks(E, N);
 
     // one CG iteration; `first` uses p = b as set by the init kernel
     const RedSite red_upd = site(SITE_UPDATE, nullptr, 0);
     auto iterate = [&](bool first) -> hipError_t {
         AxFuse fz;
         fz.sc = sc;
-        fz.partials = axp;
+        fz.partials = W.axp;
         fz.cg_layout = true;
         if (!first) {
             fz.r = r;
@@ -662,9 +672,7 @@ int nek_cg_solve(int64_t E, int N, const double *D, const double *g, const nek_g
         hipError_t e = mixed ? launch_ax_f32(E, N, opts.D32, opts.g_lo, g_dtype, p, w, fz, s)
                              : launch_ax_f64(E, N, D, g, p, w, fz, s);
         if (e != hipSuccess) return e;
-        e = launch_gs(gs->cg, w, axp, ax_parts, sc, s);
-        if (e != hipSuccess) return e;
-        return launch_cg_update(P, r, w, own, dinvc, red_upd, sc, s);
+        return launch_cg_assemble_update(gs->cg, r, w, dinvc, W.axp, ax_blocks(E, N), red_upd, sc, s);
     };
     AxFuse plain_cg;   // A x alone, on CG-layout vectors
     plain_cg.cg_layout = true;
@@ -674,7 +682,7 @@ int nek_cg_solve(int64_t E, int N, const double *D, const double *g, const nek_g
         if (e != hipSuccess) return e;
         e = launch_ax_f64(E, N, D, g, x, w, plain_cg, s);
         if (e != hipSuccess) return e;
-        return launch_gs(gs->cg, w, nullptr, 0, nullptr, s);
+        return launch_gs(gs->cg, w, s);
     };
 
     int rc = NEK_OK;
@@ -736,7 +744,7 @@ int nek_cg_solve(int64_t E, int N, const double *D, const double *g, const nek_g
             // the finish kernel above ran; running it again is a no-op only if the
             // lag flag says so, so evaluate A x directly)
             CG_TRY(launch_ax_f64(E, N, D, g, x, w, plain_cg, s));
-            CG_TRY(launch_gs(gs->cg, w, nullptr, 0, nullptr, s));
+            CG_TRY(launch_gs(gs->cg, w, s));
             CG_TRY(launch_gdiff2(P, bc, w, own, site(SITE_RESID, nullptr, 0), scratch1, s));
             CG_TRY(hipMemcpyAsync(&snap[3].bb, scratch1, sizeof(double), hipMemcpyDeviceToHost, s));
         }

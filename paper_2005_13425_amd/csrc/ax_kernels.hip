@@ -389,9 +389,9 @@ __device__ __forceinline__ void ax_body(int64_t blk, int64_t E, kptr<T> D, gptr<
             for (int k = 0; k < NX; ++k) pw += pcol[k] * (double)B0[k * LS + col];
         }
     }
-    // ---- 7. CG: per-workgroup sum of p (A_L p) over all local points.  For a
-    // continuous p that vanishes on masked nodes this is (p, mask(dssum(A_L p)))
-    // over unique nodes, so the gather-scatter needs no product of its own.
+    // ---- 7. CG: sum of p (A_L p) over all local points.  For a continuous p
+    // that vanishes on masked nodes this is (p, mask(dssum(A_L p))) over unique
+    // nodes, so the assembly needs no product of its own.
     if constexpr (FUSE) {
         if (fz.partials != nullptr) {
             __shared__ double red[S::THREADS / 64];

@@ -5,11 +5,13 @@
 // structure-of-arrays indices, so a thread handles one node with a fixed trip
 // count and lanes load their indices coalesced.  Copies are summed in
 // ascending local index (the oracle's order), masked nodes are written as 0.
-// In the CG its first workgroup also turns the (p, A_L p) partials of the
-// preceding ax launch into alpha.
+// Inside the CG iteration the same rows feed the residual update directly
+// (assemble-update): the assembled w is never written back.
 //
 // Vector steps: double2 loads, VEC_PAIRS pairs per thread issued together;
 // the first-copy mask is one bit per point.
+#include <algorithm>
+
 #include "nek_internal.h"
 #include "reduce.h"
 
@@ -69,53 +71,21 @@ constexpr int N_XCD = 8;   // gfx950: workgroups are dealt round-robin to 8 XCDs
 
 // XCD-aware work split: the workgroups that land on one XCD (index % 8) walk
 // one contiguous eighth of the virtual blocks, so the copies a row touches
-// and the rows next to it share that XCD's L2.  Local workgroup 0 also turns
-// the (p, A_L p) partials of the preceding ax launch into alpha.
+// and the rows next to it share that XCD's L2.
 // lb / nb: local workgroup index and count (nb a multiple of 8).
-__device__ __forceinline__ void gs_body(int lb, int nb, const GsArgs &a, gptr<double> w,
-                                        gptr<const double> axparts, long nparts,
-                                        gptr<CgScalars> sc) {
-    if (sc != nullptr && sc->done) return;
+template <typename F>
+__device__ __forceinline__ void for_my_vblocks(int lb, int nb, int nvb, F &&f) {
     const int xcd = lb % N_XCD;
     const int per = nb / N_XCD;
     const int lq = lb / N_XCD;
-    const int nvb = a.nblocks;
     const int v0 = (int)(((long)nvb * xcd) / N_XCD);
     const int v1 = (int)(((long)nvb * (xcd + 1)) / N_XCD);
-    for (int vb = v0 + lq; vb < v1; vb += per) gs_vblock(a, vb, w);
-    if (sc == nullptr || lb != 0) return;
-    __shared__ double lds[GS_THREADS / 64];
-    double v = 0.0;
-    for (long q = threadIdx.x; q < nparts; q += GS_THREADS) v += axparts[q];
-    const double tot = block_sum<GS_THREADS>(v, lds);
-    if (threadIdx.x == 0) {
-        sc->pw = tot;
-        if (!(tot > 0.0) || !__builtin_isfinite(tot)) {
-            sc->status = NEK_ERR_BREAKDOWN;
-            sc->done = 1;
-            sc->alpha = 0.0;
-            sc->lag_applied = 1;
-        } else {
-            sc->alpha = sc->rho / tot;
-            sc->lag_applied = 0;
-        }
-    }
+    for (int vb = v0 + lq; vb < v1; vb += per) f(vb);
 }
 
-__global__ void __launch_bounds__(GS_THREADS)
-gs_kernel(GsArgs a, double *__restrict__ w, const double *__restrict__ axparts, long nparts,
-          CgScalars *sc) {
-    gs_body(blockIdx.x, gridDim.x, a, (gptr<double>)w, (gptr<const double>)axparts, nparts,
-            (gptr<CgScalars>)sc);
-}
-
-__global__ void __launch_bounds__(GS_THREADS)
-gs_batch_kernel(const GsSlot *__restrict__ slots, int nslots) {
-    const GsSlot &S = slots[batch_slot(slots, nslots, (int64_t)blockIdx.x)];
-    const int lb = (int)((int64_t)blockIdx.x - S.block0);
-    if (lb >= S.nblocks) return;
-    gs_body(lb, (int)S.nblocks, S.args, (gptr<double>)S.w, (gptr<const double>)S.axparts,
-            (long)S.nparts, (gptr<CgScalars>)S.sc);
+__global__ void __launch_bounds__(GS_THREADS) gs_kernel(GsArgs a, double *__restrict__ w) {
+    const gptr<double> wg = (gptr<double>)w;
+    for_my_vblocks(blockIdx.x, gridDim.x, a.nblocks, [&](int vb) { gs_vblock(a, vb, wg); });
 }
 
 // ---------------------------------------------------------------- CG steps
@@ -240,57 +210,320 @@ cg_init_kernel(int64_t P, const double *__restrict__ b, double *__restrict__ x,
     }
 }
 
-// r -= alpha w; rr = (r, r); rho' = (r, z) with z = M^-1 r (= rr without a
-// preconditioner); beta = rho' / rho; convergence on rr and the iteration cap
+// ---------------------------------------------------------------- assemble-update
+// One unmasked shared node with C copies: the assembled value of w is the sum
+// of its copies (ascending local index), and r - alpha * sum goes to every
+// copy of r (r is continuous, so its first copy stands for all).  The node's
+// contribution to (r, r) and (r, M^-1 r) is taken once.
+template <int C, bool PRE>
+__device__ __forceinline__ void asm_row(gptr<const int32_t> idx, int32_t rows, int32_t row,
+                                        gptr<const double> w, gptr<double> r, gptr<const double> dinv,
+                                        double alpha, double *acc) {
+    int32_t id[C];
+#pragma unroll
+    for (int m = 0; m < C; ++m) id[m] = idx[(int64_t)m * rows + row];
+    double v[C];
+#pragma unroll
+    for (int m = 0; m < C; ++m) v[m] = w[id[m]];
+    const double rv = r[id[0]];
+    double dv = 0.0;
+    if constexpr (PRE) dv = dinv[id[0]];
+    double s = 0.0;
+#pragma unroll
+    for (int m = 0; m < C; ++m) s += v[m];
+    const double nr = rv - alpha * s;
+#pragma unroll
+    for (int m = 0; m < C; ++m) r[id[m]] = nr;
+    acc[0] += nr * nr;
+    if constexpr (PRE) acc[1] += nr * (dv * nr);
+}
+
 template <bool PRE>
-__device__ __forceinline__ void update_body(int lb, int nb, int64_t P, gptr<double> r,
-                                            gptr<const double> w, gptr<const uint32_t> own,
-                                            gptr<const double> dinv, const RedSite &red,
-                                            gptr<CgScalars> sc) {
+__device__ __forceinline__ void asm_vblock(const GsArgs &a, int vb, gptr<const double> w, gptr<double> r,
+                                           gptr<const double> dinv, double alpha, double *acc) {
+    int g = 0;
+    while (g + 1 < a.ngroups && vb >= a.grp[g + 1].block0) ++g;
+    const GsGroup &G = a.grp[g];
+    const int32_t row = (vb - G.block0) * GS_THREADS + (int32_t)threadIdx.x;
+    if (row >= G.rows) return;
+    const gptr<const int32_t> idx = (gptr<const int32_t>)G.idx;
+    switch (G.kind) {
+    case 0: break;   // copies of masked nodes: r stays 0
+    case 2: asm_row<2, PRE>(idx, G.rows, row, w, r, dinv, alpha, acc); break;
+    case 3: asm_row<3, PRE>(idx, G.rows, row, w, r, dinv, alpha, acc); break;
+    case 4: asm_row<4, PRE>(idx, G.rows, row, w, r, dinv, alpha, acc); break;
+    case 5: asm_row<5, PRE>(idx, G.rows, row, w, r, dinv, alpha, acc); break;
+    case 6: asm_row<6, PRE>(idx, G.rows, row, w, r, dinv, alpha, acc); break;
+    case 7: asm_row<7, PRE>(idx, G.rows, row, w, r, dinv, alpha, acc); break;
+    case 8: asm_row<8, PRE>(idx, G.rows, row, w, r, dinv, alpha, acc); break;
+    default: {   // CSR rows with many copies
+        const gptr<const int32_t> off = (gptr<const int32_t>)G.off;
+        const int32_t o0 = off[row], o1 = off[row + 1];
+        double s = 0.0;
+        for (int32_t o = o0; o < o1; ++o) s += w[idx[o]];
+        const int32_t first = idx[o0];
+        const double nr = r[first] - alpha * s;
+        for (int32_t o = o0; o < o1; ++o) r[idx[o]] = nr;
+        acc[0] += nr * nr;
+        if constexpr (PRE) acc[1] += nr * (dinv[first] * nr);
+    }
+    }
+}
+
+// A row of one of the common kinds (2 to 4 copies: faces and edges of a
+// hexahedral mesh), split into its loads and its update so that the loads of
+// several rows and of the other points are in flight together.
+struct RowJob {
+    int C = 0;                // copies; 0: no row
+    int32_t id[4];
+    double v[4];
+    double rv = 0.0, dv = 0.0;
+};
+
+__device__ __forceinline__ bool fast_kind(int kind) { return kind >= 2 && kind <= 4; }
+
+__device__ __forceinline__ void row_setup(const GsArgs &a, int vb, RowJob &J) {
+    int g = 0;
+    while (g + 1 < a.ngroups && vb >= a.grp[g + 1].block0) ++g;
+    const GsGroup &G = a.grp[g];
+    const int32_t row = (vb - G.block0) * GS_THREADS + (int32_t)threadIdx.x;
+    J.C = (fast_kind(G.kind) && row < G.rows) ? G.kind : 0;
+    const gptr<const int32_t> idx = (gptr<const int32_t>)G.idx;
+#pragma unroll
+    for (int m = 0; m < 4; ++m)
+        if (m < J.C) J.id[m] = idx[(int64_t)m * G.rows + row];
+}
+
+template <bool PRE>
+__device__ __forceinline__ void row_load(RowJob &J, gptr<const double> w, gptr<const double> r,
+                                         gptr<const double> dinv) {
+    if (J.C == 0) return;
+#pragma unroll
+    for (int m = 0; m < 4; ++m)
+        if (m < J.C) J.v[m] = w[J.id[m]];
+    J.rv = r[J.id[0]];
+    if constexpr (PRE) J.dv = dinv[J.id[0]];
+}
+
+template <bool PRE>
+__device__ __forceinline__ void row_finish(const RowJob &J, gptr<double> r, double alpha, double *acc) {
+    if (J.C == 0) return;
+    double s = 0.0;
+#pragma unroll
+    for (int m = 0; m < 4; ++m)
+        if (m < J.C) s += J.v[m];
+    const double nr = J.rv - alpha * s;
+#pragma unroll
+    for (int m = 0; m < 4; ++m)
+        if (m < J.C) r[J.id[m]] = nr;
+    acc[0] += nr * nr;
+    if constexpr (PRE) acc[1] += nr * (J.dv * nr);
+}
+
+// The other points of one chunk of pairs: bits first, then values, then update.
+template <bool PRE>
+struct PairChunk {
+    unsigned rb[VEC_PAIRS];
+    double2 rv[VEC_PAIRS], wv[VEC_PAIRS], dv[VEC_PAIRS];
+};
+
+template <bool PRE>
+__device__ __forceinline__ void chunk_bits(int64_t base, int64_t npairs, gptr<const uint32_t> rowed,
+                                           PairChunk<PRE> &Q) {
+#pragma unroll
+    for (int m = 0; m < VEC_PAIRS; ++m) {
+        const int64_t q = base + threadIdx.x + (int64_t)m * VEC_THREADS;
+        Q.rb[m] = q < npairs ? own_pair(rowed, 2 * q) : 3u;
+    }
+}
+
+template <bool PRE>
+__device__ __forceinline__ void chunk_load(int64_t base, gptr<const double> r, gptr<const double> w,
+                                           gptr<const double> dinv, PairChunk<PRE> &Q) {
+#pragma unroll
+    for (int m = 0; m < VEC_PAIRS; ++m) {
+        const int64_t q = base + threadIdx.x + (int64_t)m * VEC_THREADS;
+        if (Q.rb[m] != 3u) {
+            Q.rv[m] = ((gptr<const double2>)r)[q];
+            Q.wv[m] = ((gptr<const double2>)w)[q];
+            if constexpr (PRE) Q.dv[m] = ((gptr<const double2>)dinv)[q];
+        }
+    }
+}
+
+template <bool PRE>
+__device__ __forceinline__ void chunk_finish(int64_t base, gptr<double> r, double alpha, const PairChunk<PRE> &Q,
+                                             double *acc) {
     constexpr int K = PRE ? 2 : 1;
+#pragma unroll
+    for (int m = 0; m < VEC_PAIRS; ++m) {
+        const int64_t q = base + threadIdx.x + (int64_t)m * VEC_THREADS;
+        const unsigned rb = Q.rb[m];
+        if (rb == 3u) continue;
+        double2 nr;
+        nr.x = Q.rv[m].x - alpha * Q.wv[m].x;
+        nr.y = Q.rv[m].y - alpha * Q.wv[m].y;
+        // a copy of a shared node belongs to its row (written there)
+        if (rb == 0u) {
+            ((gptr<double2>)r)[q] = nr;
+        } else if (rb == 2u) {
+            r[2 * q] = nr.x;
+        } else {
+            r[2 * q + 1] = nr.y;
+        }
+        if (!(rb & 1u)) {
+            acc[0] += nr.x * nr.x;
+            if constexpr (PRE) acc[K - 1] += nr.x * (Q.dv[m].x * nr.x);
+        }
+        if (!(rb & 2u)) {
+            acc[0] += nr.y * nr.y;
+            if constexpr (PRE) acc[K - 1] += nr.y * (Q.dv[m].y * nr.y);
+        }
+    }
+}
+
+// The CG step after the operator (see launch_cg_assemble_update).
+//
+// Work split: the workgroups on one XCD (index % 8) take one contiguous eighth
+// of every row group and one contiguous eighth of the chunks of pairs, so an
+// XCD works on about one eighth of the elements for all of them and the
+// cache lines that rows and pairs share stay in its L2 (the row groups are
+// each ordered by element; splitting their concatenation instead cost 25%).
+//
+// Every workgroup first puts in flight the loads that do not depend on
+// anything: the operator's partials (for alpha), the indices of its first two
+// row blocks of the common kinds and the bits of its first chunk of pairs;
+// then the values those select; only then does it wait for alpha.  Further
+// row blocks and chunks (large meshes), rows of rare kinds, then the
+// reduction: rr = (r, r), rho' = (r, z), beta = rho' / rho, convergence on rr
+// and the iteration cap.  lb / nb as in the gather-scatter.
+template <bool PRE>
+__device__ __forceinline__ void assemble_update_body(int lb, int nb, int64_t P, const GsArgs &a,
+                                                     gptr<const uint32_t> rowed, gptr<double> r,
+                                                     gptr<const double> w, gptr<const double> dinv,
+                                                     gptr<const double> axparts, int64_t nparts,
+                                                     const RedSite &red, gptr<CgScalars> sc) {
+    constexpr int K = PRE ? 2 : 1;
+    constexpr int PPT = 8;   // partials loaded per thread at once
     if (sc->done) return;
     __shared__ double lds[VEC_THREADS / 64];
-    const double alpha = sc->alpha;
+    __shared__ double alpha_s;
+    __shared__ int breakdown;
+
+    const int xcd = lb % N_XCD, per = nb / N_XCD, lq = lb / N_XCD;
     const int64_t npairs = P >> 1;
+    // chunks: the workgroups of one XCD take one contiguous eighth
+    const int64_t nch = (npairs + VEC_CHUNK - 1) / VEC_CHUNK;
+    const int64_t c0 = nch * xcd / N_XCD, c1 = nch * (xcd + 1) / N_XCD;
+    const int64_t base0 = (c0 + lq < c1) ? (c0 + lq) * VEC_CHUNK : npairs;
+    // row blocks: of every group, the workgroups of one XCD take one contiguous eighth
+    int vbl[2] = {-1, -1};
+    {
+        int found = 0;
+        for (int g = 0; g < a.ngroups && found < 2; ++g) {
+            const GsGroup &G = a.grp[g];
+            if (!fast_kind(G.kind)) continue;
+            const int gb = (G.rows + GS_THREADS - 1) / GS_THREADS;
+            const int u0 = G.block0 + (int)((long)gb * xcd / N_XCD);
+            const int u1 = G.block0 + (int)((long)gb * (xcd + 1) / N_XCD);
+            for (int vb = u0 + lq; vb < u1 && found < 2; vb += per) vbl[found++] = vb;
+        }
+    }
+
+    // ---- 1. independent loads
+    double part[PPT];
+#pragma unroll
+    for (int m = 0; m < PPT; ++m) {
+        const int64_t q = threadIdx.x + (int64_t)m * VEC_THREADS;
+        part[m] = q < nparts ? axparts[q] : 0.0;
+    }
+    RowJob J0, J1;
+    if (vbl[0] >= 0) row_setup(a, vbl[0], J0);
+    if (vbl[1] >= 0) row_setup(a, vbl[1], J1);
+    PairChunk<PRE> Q;
+    chunk_bits<PRE>(base0, npairs, rowed, Q);
+
+    // ---- 2. loads selected by the indices and bits
+    row_load<PRE>(J0, w, r, dinv);
+    row_load<PRE>(J1, w, r, dinv);
+    chunk_load<PRE>(base0, r, w, dinv, Q);
+
+    // ---- 3. alpha = rho / (p, A p): every workgroup sums the partials in the
+    // same order, so all of them hold the same alpha; workgroup 0 records it
+    {
+        double v = 0.0;
+#pragma unroll
+        for (int m = 0; m < PPT; ++m) v += part[m];
+        for (int64_t q0 = (int64_t)PPT * VEC_THREADS; q0 < nparts; q0 += (int64_t)PPT * VEC_THREADS) {
+            double more[PPT];
+#pragma unroll
+            for (int m = 0; m < PPT; ++m) {
+                const int64_t q = q0 + threadIdx.x + (int64_t)m * VEC_THREADS;
+                more[m] = q < nparts ? axparts[q] : 0.0;
+            }
+#pragma unroll
+            for (int m = 0; m < PPT; ++m) v += more[m];
+        }
+        const double pw = block_sum<VEC_THREADS>(v, lds);
+        if (threadIdx.x == 0) {
+            const bool bad = !(pw > 0.0) || !__builtin_isfinite(pw);
+            breakdown = bad ? 1 : 0;
+            alpha_s = bad ? 0.0 : sc->rho / pw;
+            if (lb == 0) {
+                sc->pw = pw;
+                sc->alpha = alpha_s;
+                sc->lag_applied = bad ? 1 : 0;
+                if (bad) {
+                    sc->status = NEK_ERR_BREAKDOWN;
+                    sc->done = 1;
+                }
+            }
+        }
+        __syncthreads();
+    }
+    if (breakdown) return;
+    const double alpha = alpha_s;
+
+    // ---- 4. updates of what is loaded, then the rest
     double acc[K];
 #pragma unroll
     for (int c = 0; c < K; ++c) acc[c] = 0.0;
-    for (int64_t base = (int64_t)lb * VEC_CHUNK; base < npairs; base += (int64_t)nb * VEC_CHUNK) {
-        double2 rv[VEC_PAIRS], wv[VEC_PAIRS], dv[VEC_PAIRS];
-#pragma unroll
-        for (int m = 0; m < VEC_PAIRS; ++m) {
-            const int64_t q = base + threadIdx.x + (int64_t)m * VEC_THREADS;
-            if (q < npairs) {
-                rv[m] = ((gptr<const double2>)r)[q];
-                wv[m] = ((gptr<const double2>)w)[q];
-                if constexpr (PRE) dv[m] = ((gptr<const double2>)dinv)[q];
-            }
-        }
-#pragma unroll
-        for (int m = 0; m < VEC_PAIRS; ++m) {
-            const int64_t q = base + threadIdx.x + (int64_t)m * VEC_THREADS;
-            if (q < npairs) {
-                double2 nr;
-                nr.x = rv[m].x - alpha * wv[m].x;
-                nr.y = rv[m].y - alpha * wv[m].y;
-                ((gptr<double2>)r)[q] = nr;
-                const unsigned o = own_pair(own, 2 * q);
-                if (o & 1u) {
-                    acc[0] += nr.x * nr.x;
-                    if constexpr (PRE) acc[K - 1] += nr.x * (dv[m].x * nr.x);
-                }
-                if (o & 2u) {
-                    acc[0] += nr.y * nr.y;
-                    if constexpr (PRE) acc[K - 1] += nr.y * (dv[m].y * nr.y);
+    row_finish<PRE>(J0, r, alpha, acc);
+    row_finish<PRE>(J1, r, alpha, acc);
+    chunk_finish<PRE>(base0, r, alpha, Q, acc);
+    {
+        int seen = 0;   // row blocks of the common kinds past the first two
+        for (int g = 0; g < a.ngroups; ++g) {
+            const GsGroup &G = a.grp[g];
+            if (G.kind == 0) continue;
+            const int gb = (G.rows + GS_THREADS - 1) / GS_THREADS;
+            const int u0 = G.block0 + (int)((long)gb * xcd / N_XCD);
+            const int u1 = G.block0 + (int)((long)gb * (xcd + 1) / N_XCD);
+            for (int vb = u0 + lq; vb < u1; vb += per) {
+                if (fast_kind(G.kind)) {
+                    if (seen++ < 2) continue;
+                    RowJob J;
+                    row_setup(a, vb, J);
+                    row_load<PRE>(J, w, r, dinv);
+                    row_finish<PRE>(J, r, alpha, acc);
+                } else {   // rare kinds: corners of 8 elements, many-copy CSR rows
+                    asm_vblock<PRE>(a, vb, w, r, dinv, alpha, acc);
                 }
             }
         }
     }
+    for (int64_t c = c0 + lq + per; c < c1; c += per) {
+        const int64_t base = c * VEC_CHUNK;
+        PairChunk<PRE> Qn;
+        chunk_bits<PRE>(base, npairs, rowed, Qn);
+        chunk_load<PRE>(base, r, w, dinv, Qn);
+        chunk_finish<PRE>(base, r, alpha, Qn, acc);
+    }
     if ((P & 1) && lb == nb - 1 && threadIdx.x == VEC_THREADS - 1) {
         const int64_t t = P - 1;
-        const double nr = r[t] - alpha * w[t];
-        r[t] = nr;
-        if (own_bit(own, t)) {
+        if (!own_bit(rowed, t)) {
+            const double nr = r[t] - alpha * w[t];
+            r[t] = nr;
             acc[0] += nr * nr;
             if constexpr (PRE) acc[K - 1] += nr * (dinv[t] * nr);
         }
@@ -321,19 +554,22 @@ __device__ __forceinline__ void update_body(int lb, int nb, int64_t P, gptr<doub
 
 template <bool PRE>
 __global__ void __launch_bounds__(VEC_THREADS)
-cg_update_kernel(int64_t P, double *__restrict__ r, const double *__restrict__ w,
-                 const uint32_t *__restrict__ own, const double *__restrict__ dinv, RedSite red,
-                 CgScalars *sc) {
-    update_body<PRE>(blockIdx.x, gridDim.x, P, (gptr<double>)r, (gptr<const double>)w,
-                     (gptr<const uint32_t>)own, (gptr<const double>)dinv, red, (gptr<CgScalars>)sc);
+assemble_update_kernel(int64_t P, GsArgs a, const uint32_t *__restrict__ rowed, double *__restrict__ r,
+                       const double *__restrict__ w, const double *__restrict__ dinv,
+                       const double *__restrict__ axparts, int64_t nparts, RedSite red, CgScalars *sc) {
+    assemble_update_body<PRE>(blockIdx.x, gridDim.x, P, a, (gptr<const uint32_t>)rowed, (gptr<double>)r,
+                              (gptr<const double>)w, (gptr<const double>)dinv,
+                              (gptr<const double>)axparts, nparts, red, (gptr<CgScalars>)sc);
 }
 
 __global__ void __launch_bounds__(VEC_THREADS)
-update_batch_kernel(const UpdSlot *__restrict__ slots, int nslots) {
-    const UpdSlot S = slots[batch_slot(slots, nslots, (int64_t)blockIdx.x)];
-    update_body<false>((int)((int64_t)blockIdx.x - S.block0), (int)S.nblocks, S.P, (gptr<double>)S.r,
-                       (gptr<const double>)S.w, (gptr<const uint32_t>)S.own, nullptr, S.red,
-                       (gptr<CgScalars>)S.sc);
+assemble_update_batch_kernel(const AsmSlot *__restrict__ slots, int nslots) {
+    const AsmSlot &S = slots[batch_slot(slots, nslots, (int64_t)blockIdx.x)];
+    const int lb = (int)((int64_t)blockIdx.x - S.block0);
+    if (lb >= S.nblocks) return;
+    assemble_update_body<false>(lb, (int)S.nblocks, S.P, S.args, (gptr<const uint32_t>)S.rowed,
+                                (gptr<double>)S.r, (gptr<const double>)S.w, nullptr,
+                                (gptr<const double>)S.axparts, S.nparts, S.red, (gptr<CgScalars>)S.sc);
 }
 
 __global__ void gather_scalars_kernel(CgScalars *const *src, int n, CgScalars *dst) {
@@ -494,25 +730,37 @@ int64_t gs_grid(const GsDevice &gs) {
     return g < N_XCD ? N_XCD : g;
 }
 
-hipError_t launch_gs(const GsDevice &gs, double *w, const double *axparts, int64_t nparts,
-                     CgScalars *sc, hipStream_t s) {
-    if (gs.args.nblocks == 0 && sc == nullptr) return hipSuccess;
-    hipLaunchKernelGGL(gs_kernel, dim3((unsigned)gs_grid(gs)), dim3(GS_THREADS), 0, s, gs.args, w,
-                       axparts, (long)nparts, sc);
+hipError_t launch_gs(const GsDevice &gs, double *w, hipStream_t s) {
+    if (gs.args.nblocks == 0) return hipSuccess;
+    hipLaunchKernelGGL(gs_kernel, dim3((unsigned)gs_grid(gs)), dim3(GS_THREADS), 0, s, gs.args, w);
     return hipGetLastError();
 }
 
-hipError_t launch_gs_batch(const GsSlot *slots, int nslots, int64_t blocks, hipStream_t s) {
-    if (nslots < 1 || nslots > BATCH_MAX_SLOTS || blocks < 1 || blocks > 0x7fffffff)
-        return hipErrorInvalidValue;
-    hipLaunchKernelGGL(gs_batch_kernel, dim3((unsigned)blocks), dim3(GS_THREADS), 0, s, slots, nslots);
+static_assert(GS_THREADS == VEC_THREADS, "assemble-update takes one row per thread of a virtual block");
+
+int64_t asm_blocks(const GsDevice &gs) {
+    int64_t g = std::max(vec_blocks(gs.P), gs_grid(gs));
+    g = (g + N_XCD - 1) / N_XCD * N_XCD;
+    return g > RED_MAX_BLOCKS ? RED_MAX_BLOCKS : g;
+}
+
+hipError_t launch_cg_assemble_update(const GsDevice &gs, double *r, const double *w, const double *dinv,
+                                     const double *axparts, int64_t nparts, const RedSite &red,
+                                     CgScalars *sc, hipStream_t s) {
+    const dim3 grid((unsigned)asm_blocks(gs));
+    if (dinv != nullptr)
+        hipLaunchKernelGGL(assemble_update_kernel<true>, grid, dim3(VEC_THREADS), 0, s, gs.P, gs.args,
+                           gs.rowed_bits, r, w, dinv, axparts, nparts, red, sc);
+    else
+        hipLaunchKernelGGL(assemble_update_kernel<false>, grid, dim3(VEC_THREADS), 0, s, gs.P, gs.args,
+                           gs.rowed_bits, r, w, dinv, axparts, nparts, red, sc);
     return hipGetLastError();
 }
 
-hipError_t launch_update_batch(const UpdSlot *slots, int nslots, int64_t blocks, hipStream_t s) {
+hipError_t launch_assemble_update_batch(const AsmSlot *slots, int nslots, int64_t blocks, hipStream_t s) {
     if (nslots < 1 || nslots > BATCH_MAX_SLOTS || blocks < 1 || blocks > 0x7fffffff)
         return hipErrorInvalidValue;
-    hipLaunchKernelGGL(update_batch_kernel, dim3((unsigned)blocks), dim3(VEC_THREADS), 0, s, slots,
+    hipLaunchKernelGGL(assemble_update_batch_kernel, dim3((unsigned)blocks), dim3(VEC_THREADS), 0, s, slots,
                        nslots);
     return hipGetLastError();
 }
@@ -539,17 +787,6 @@ hipError_t launch_cg_init(int64_t P, const double *b, double *x, double *r, doub
     else
         hipLaunchKernelGGL(cg_init_kernel<false>, dim3((unsigned)vec_blocks(P)), dim3(VEC_THREADS), 0, s,
                            P, b, x, r, p, own, dinv, red, sc);
-    return hipGetLastError();
-}
-
-hipError_t launch_cg_update(int64_t P, double *r, const double *w, const uint32_t *own,
-                            const double *dinv, const RedSite &red, CgScalars *sc, hipStream_t s) {
-    if (dinv != nullptr)
-        hipLaunchKernelGGL(cg_update_kernel<true>, dim3((unsigned)vec_blocks(P)), dim3(VEC_THREADS), 0,
-                           s, P, r, w, own, dinv, red, sc);
-    else
-        hipLaunchKernelGGL(cg_update_kernel<false>, dim3((unsigned)vec_blocks(P)), dim3(VEC_THREADS), 0,
-                           s, P, r, w, own, dinv, red, sc);
     return hipGetLastError();
 }
 

@@ -78,7 +78,8 @@ constexpr double RELIABLE_DROP_DEFAULT = 0.3;
 //   dinv != null (with r) : p <- dinv r + beta p (Jacobi-preconditioned CG);
 //   x != null : x += alpha p_old first, if sc->lag_applied == 0;
 //   partials != null : per-workgroup sum of p * (A_L p) over all local
-//                      points, at partials[blockIdx];
+//                      points, at partials[blockIdx] (the assemble-update
+//                      launch that follows turns them into alpha);
 //   sc != null : skip everything once sc->done is set.
 struct AxFuse {
     const double *r = nullptr;
@@ -171,8 +172,10 @@ struct GsHost {
     std::vector<int32_t> idx;
     std::vector<GsHostGroup> groups;
     std::vector<uint32_t> own;
+    std::vector<uint32_t> rowed;   // P bits: copy of a shared node or of a masked node
     size_t idx_bytes() const { return ((idx.size() * sizeof(int32_t) + 4) + 255) & ~(size_t)255; }
-    size_t arena_bytes() const { return idx_bytes() + own.size() * sizeof(uint32_t); }
+    size_t own_bytes() const { return ((own.size() * sizeof(uint32_t)) + 255) & ~(size_t)255; }
+    size_t arena_bytes() const { return idx_bytes() + own_bytes() + rowed.size() * sizeof(uint32_t); }
 };
 
 // Build the host image from glo[P] / dirichlet[P] (NULL = none); returns
@@ -183,8 +186,10 @@ int gs_build_host(int64_t E, int N, const int64_t *glo, const uint8_t *dirichlet
 
 struct GsDevice;
 // Point a device handle at an arena that holds (or will hold) h's image: the
-// index arrays at the start, the first-copy bits at own_offset.
-void gs_attach(const GsHost &h, void *arena, size_t own_offset, GsDevice &d);
+// index arrays at the start, then the first-copy bits, then the bits of the
+// points that are copies of shared or masked nodes (h.idx_bytes() and
+// h.own_bytes() give the offsets).
+void gs_attach(const GsHost &h, void *arena, GsDevice &d);
 
 struct GsDevice {
     int64_t E = 0;
@@ -197,26 +202,13 @@ struct GsDevice {
     int64_t n_zero = 0;      // copies of masked nodes
     GsArgs args{};
     void *arena = nullptr;   // one allocation holding every index array
-    uint32_t *own_bits = nullptr;  // P bits: first copy of every node
+    uint32_t *own_bits = nullptr;    // P bits: first copy of every node
+    uint32_t *rowed_bits = nullptr;  // P bits: copy of a shared or of a masked node
 };
 
-// dssum + mask in place.  With sc != null, workgroup 0 also sums the nparts
-// partials of (p, A_L p) left by the ax launch, in index order, into
-// sc->pw and sc->alpha (or flags a breakdown).
-hipError_t launch_gs(const GsDevice &gs, double *w, const double *axparts, int64_t nparts,
-                     CgScalars *sc, hipStream_t s);
+// dssum + mask in place
+hipError_t launch_gs(const GsDevice &gs, double *w, hipStream_t s);
 int64_t gs_grid(const GsDevice &gs);   // a multiple of 8
-
-struct GsSlot {
-    int64_t block0;      // a multiple of 8, so a slot's workgroups keep their XCD order
-    int64_t nblocks;     // gs_grid of this solve
-    GsArgs args;
-    double *w;
-    const double *axparts;
-    int64_t nparts;
-    CgScalars *sc;
-};
-hipError_t launch_gs_batch(const GsSlot *slots, int nslots, int64_t blocks, hipStream_t s);
 
 // ---------------------------------------------------------------- CG vector steps
 constexpr int VEC_THREADS = 256;
@@ -229,20 +221,34 @@ hipError_t launch_cg_reset(CgScalars *sc, unsigned int *tickets, int nticket, in
 hipError_t launch_cg_init(int64_t P, const double *b, double *x, double *r, double *p,
                           const uint32_t *own, const double *dinv, const RedSite &red, CgScalars *sc,
                           hipStream_t s);
-hipError_t launch_cg_update(int64_t P, double *r, const double *w, const uint32_t *own,
-                            const double *dinv, const RedSite &red, CgScalars *sc, hipStream_t s);
+// The CG step after the operator, with the dssum folded in: w holds the
+// unassembled A_L p.  For every unmasked shared node the copies of w are
+// summed (ascending local index, as nek_dssum does) and r <- r - alpha * sum
+// is written to every copy of r; every unshared unmasked point gets
+// r <- r - alpha w; copies of masked nodes are left alone (r is 0 there).
+// Then rr = (r, r), rho' = (r, z) with z = M^-1 r, beta, convergence.  The
+// assembled w itself is never stored.  alpha = rho / (p, A p), from the nparts
+// per-workgroup partials of (p, A_L p) left by the ax launch, summed in index
+// order by every workgroup (workgroup 0 records it, or flags a breakdown).
+hipError_t launch_cg_assemble_update(const GsDevice &gs, double *r, const double *w,
+                                     const double *dinv, const double *axparts, int64_t nparts,
+                                     const RedSite &red, CgScalars *sc, hipStream_t s);
+int64_t asm_blocks(const GsDevice &gs);   // its grid: a multiple of 8, <= RED_MAX_BLOCKS
 
-struct UpdSlot {
-    int64_t block0;
-    int64_t nblocks;     // vec_blocks(P) of this solve
+struct AsmSlot {
+    int64_t block0;      // a multiple of 8, so a slot's workgroups keep their XCD order
+    int64_t nblocks;     // asm_blocks of this solve
     int64_t P;
+    GsArgs args;
+    const uint32_t *rowed;
     double *r;
     const double *w;
-    const uint32_t *own;
+    const double *axparts;
+    int64_t nparts;
     RedSite red;
     CgScalars *sc;
 };
-hipError_t launch_update_batch(const UpdSlot *slots, int nslots, int64_t blocks, hipStream_t s);
+hipError_t launch_assemble_update_batch(const AsmSlot *slots, int nslots, int64_t blocks, hipStream_t s);
 
 // copy the scalars of several solves into one contiguous array
 hipError_t launch_gather_scalars(CgScalars *const *src, int n, CgScalars *dst, hipStream_t s);

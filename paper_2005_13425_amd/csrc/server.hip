@@ -33,8 +33,9 @@ constexpr int PREP_THREADS = 4;   // host threads preparing submitted requests
 bool is_mixed(int prec) { return prec == NEK_PREC_F32G32 || prec == NEK_PREC_F32GBF16; }
 
 // Device bytes of one admitted request (arena + solution vector).  The
-// gather-scatter part is bounded by one int32 per local point plus the
-// first-copy bits (every local point appears in at most one group).
+// gather-scatter part is bounded by one int32 per local point plus two bit
+// sets (first copies; copies of shared or masked nodes): every local point
+// appears in at most one group.
 struct Footprint {
     size_t g, b, gs, D, D32, glo, ws, arena, x, total;
 };
@@ -45,7 +46,7 @@ Footprint footprint_of(int64_t E, int N, int prec) {
     Footprint f;
     f.g = align256(6 * P * sizeof(double));
     f.b = align256(P * sizeof(double));
-    f.gs = align256(P * sizeof(int32_t) + 4) + align256((P + 31) / 32 * sizeof(uint32_t));
+    f.gs = align256(P * sizeof(int32_t) + 4) + 2 * align256((P + 31) / 32 * sizeof(uint32_t));
     f.D = align256(n2 * sizeof(double));
     f.D32 = align256(n2 * sizeof(float));
     f.glo = prec == NEK_PREC_F32G32 ? align256(6 * P * sizeof(float))
@@ -70,7 +71,7 @@ struct Request {
     GsHost gs;                    // group metadata; index arrays dropped once staged
     void *staging = nullptr;      // pinned: b | gs idx | own bits | D | D32
     size_t staging_bytes = 0;
-    size_t off_idx = 0, off_own = 0, off_D = 0, off_D32 = 0;
+    size_t off_idx = 0, off_own = 0, off_rowed = 0, off_D = 0, off_D32 = 0;
 };
 
 // Pinned host buffers, reused once their upload has completed.
@@ -146,7 +147,7 @@ struct TableSet {       // slot tables of one step, host (pinned) and device
 struct Group {
     int N, precision, size_class;
     int first, count;            // range in the slot tables
-    int64_t ax_blocks, gs_blocks, upd_blocks;
+    int64_t ax_blocks, asm_blocks;
     int64_t points;              // local points of its solves
     int extra = 0;               // iterations per step beyond the common count
 };
@@ -198,7 +199,7 @@ void assign_extra(std::vector<Group> &groups, int iters) {
 }
 
 constexpr size_t TABLE_BYTES =
-    MAX_SLOTS * (sizeof(AxSlot) + sizeof(GsSlot) + sizeof(UpdSlot) + sizeof(CgScalars *));
+    MAX_SLOTS * (sizeof(AxSlot) + sizeof(AsmSlot) + sizeof(CgScalars *));
 
 }  // namespace
 }  // namespace nek
@@ -259,7 +260,8 @@ struct nek_server {
             const int n = q.N + 1;
             R->off_idx = align256(P * sizeof(double));
             R->off_own = R->off_idx + align256(R->gs.idx.size() * sizeof(int32_t) + 4);
-            R->off_D = R->off_own + align256(R->gs.own.size() * sizeof(uint32_t));
+            R->off_rowed = R->off_own + align256(R->gs.own.size() * sizeof(uint32_t));
+            R->off_D = R->off_rowed + align256(R->gs.rowed.size() * sizeof(uint32_t));
             R->off_D32 = R->off_D + align256((size_t)n * n * sizeof(double));
             R->staging_bytes = R->off_D32 + align256((size_t)n * n * sizeof(float));
             R->staging = pinned.get(R->staging_bytes);
@@ -271,6 +273,7 @@ struct nek_server {
                 memcpy(st, q.b, (size_t)P * sizeof(double));   // the caller's b, read once
                 if (!R->gs.idx.empty()) memcpy(st + R->off_idx, R->gs.idx.data(), R->gs.idx.size() * sizeof(int32_t));
                 memcpy(st + R->off_own, R->gs.own.data(), R->gs.own.size() * sizeof(uint32_t));
+                memcpy(st + R->off_rowed, R->gs.rowed.data(), R->gs.rowed.size() * sizeof(uint32_t));
                 double D[(NEK_MAX_DEGREE + 1) * (NEK_MAX_DEGREE + 1)];
                 gll_host(q.N, nullptr, nullptr, D);
                 memcpy(st + R->off_D, D, (size_t)n * n * sizeof(double));
@@ -349,15 +352,18 @@ struct nek_server {
         NEK_HIP(launch_permute(R->E, q.N, S->W.w, S->b, true, stream));
         const size_t own_off = R->gs.idx_bytes();   // == off_own - off_idx
         NEK_HIP(hipMemcpyAsync(gs_arena, st + R->off_idx, own_off, hipMemcpyHostToDevice, stream));
+        NEK_HIP(hipMemcpyAsync(gs_arena + own_off + R->gs.own_bytes(), st + R->off_rowed,
+                               R->gs.rowed.size() * sizeof(uint32_t), hipMemcpyHostToDevice, stream));
         NEK_HIP(hipMemcpyAsync(gs_arena + own_off, st + R->off_own, R->gs.own.size() * sizeof(uint32_t),
                                hipMemcpyHostToDevice, stream));
         NEK_HIP(hipMemcpyAsync(S->D, st + R->off_D, R->off_D32 - R->off_D, hipMemcpyHostToDevice, stream));
         NEK_HIP(hipMemcpyAsync(S->D32, st + R->off_D32, R->staging_bytes - R->off_D32, hipMemcpyHostToDevice, stream));
         NEK_HIP(hipEventCreateWithFlags(&S->ev_upload, hipEventDisableTiming));
         NEK_HIP(hipEventRecord(S->ev_upload, stream));
-        gs_attach(R->gs, gs_arena, own_off, S->gsd);
+        gs_attach(R->gs, gs_arena, S->gsd);
         std::vector<int32_t>().swap(R->gs.idx);
         std::vector<uint32_t>().swap(R->gs.own);
+        std::vector<uint32_t>().swap(R->gs.rowed);
         GllTable tab;
         memset(&tab, 0, sizeof(tab));
         gll_host(q.N, tab.z, tab.w, tab.D);
@@ -425,9 +431,8 @@ struct nek_server {
             return size_class(a->req->P) < size_class(b->req->P);
         });
         AxSlot *ax = (AxSlot *)T.host;
-        GsSlot *gsl = (GsSlot *)(T.host + MAX_SLOTS * sizeof(AxSlot));
-        UpdSlot *up = (UpdSlot *)(T.host + MAX_SLOTS * (sizeof(AxSlot) + sizeof(GsSlot)));
-        CgScalars **scp = (CgScalars **)(T.host + MAX_SLOTS * (sizeof(AxSlot) + sizeof(GsSlot) + sizeof(UpdSlot)));
+        AsmSlot *asl = (AsmSlot *)(T.host + MAX_SLOTS * sizeof(AxSlot));
+        CgScalars **scp = (CgScalars **)(T.host + MAX_SLOTS * (sizeof(AxSlot) + sizeof(AsmSlot)));
         groups.clear();
         for (size_t i = 0; i < act.size(); ++i) {
             Slot *S = act[i];
@@ -452,25 +457,19 @@ struct nek_server {
             A.fz.sc = S->W.sc;
             A.fz.cg_layout = true;
             G.ax_blocks += ax_blocks(S->req->E, q.N);
-            GsSlot &Gs = gsl[i];
-            Gs.block0 = G.gs_blocks;
-            Gs.nblocks = gs_grid(S->gsd);
-            Gs.args = S->gsd.args;
-            Gs.w = S->W.w;
-            Gs.axparts = S->W.axp;
-            Gs.nparts = ax_blocks(S->req->E, q.N);
-            Gs.sc = S->W.sc;
-            G.gs_blocks += Gs.nblocks;
-            UpdSlot &U = up[i];
-            U.block0 = G.upd_blocks;
-            U.nblocks = vec_blocks(S->req->P);
+            AsmSlot &U = asl[i];
+            U.block0 = G.asm_blocks;
+            U.nblocks = asm_blocks(S->gsd);
             U.P = S->req->P;
+            U.args = S->gsd.args;
+            U.rowed = S->gsd.rowed_bits;
             U.r = S->W.r;
             U.w = S->W.w;
-            U.own = S->gsd.own_bits;
+            U.axparts = S->W.axp;
+            U.nparts = ax_blocks(S->req->E, q.N);
             U.red = S->W.site(SITE_UPDATE);
             U.sc = S->W.sc;
-            G.upd_blocks += U.nblocks;
+            G.asm_blocks += U.nblocks;
             scp[i] = S->W.sc;
             G.count++;
         }
@@ -506,7 +505,7 @@ struct nek_server {
         const int64_t E = S->req->E, P = S->req->P;
         NEK_HIP(launch_cg_finish(P, S->x, S->W.p, S->W.sc, stream));
         NEK_HIP(launch_ax_f64(E, q.N, S->D, S->g, S->x, S->W.w, plain_cg(), stream));
-        NEK_HIP(launch_gs(S->gsd, S->W.w, nullptr, 0, nullptr, stream));
+        NEK_HIP(launch_gs(S->gsd, S->W.w, stream));
         NEK_HIP(launch_gdiff2(P, S->b, S->W.w, S->gsd.own_bits, S->W.site(SITE_RESID), S->W.scratch, stream));
         // x back to the layout of Listing 1 (through w)
         NEK_HIP(launch_permute(E, q.N, S->x, S->W.w, false, stream));
@@ -525,7 +524,7 @@ struct nek_server {
         const int64_t E = S->req->E, P = S->req->P;
         NEK_HIP(launch_cg_finish(P, S->x, S->W.p, S->W.sc, stream));
         NEK_HIP(launch_ax_f64(E, q.N, S->D, S->g, S->x, S->W.w, plain_cg(), stream));
-        NEK_HIP(launch_gs(S->gsd, S->W.w, nullptr, 0, nullptr, stream));
+        NEK_HIP(launch_gs(S->gsd, S->W.w, stream));
         NEK_HIP(launch_cg_replace(P, S->b, S->W.w, S->W.r, S->gsd.own_bits, S->W.site(SITE_REPLACE),
                                   S->W.sc, stream));
         S->replacements++;
@@ -587,16 +586,14 @@ struct nek_server {
         if (!table_slots.empty()) {
             const TableSet &T = tables[cur_table];
             const AxSlot *ax = (const AxSlot *)T.dev;
-            const GsSlot *gsl = (const GsSlot *)(T.dev + MAX_SLOTS * sizeof(AxSlot));
-            const UpdSlot *up = (const UpdSlot *)(T.dev + MAX_SLOTS * (sizeof(AxSlot) + sizeof(GsSlot)));
-            CgScalars *const *scp = (CgScalars *const *)(T.dev + MAX_SLOTS * (sizeof(AxSlot) + sizeof(GsSlot) + sizeof(UpdSlot)));
+            const AsmSlot *asl = (const AsmSlot *)(T.dev + MAX_SLOTS * sizeof(AxSlot));
+            CgScalars *const *scp = (CgScalars *const *)(T.dev + MAX_SLOTS * (sizeof(AxSlot) + sizeof(AsmSlot)));
             const int base_iters = std::max(1, iters);
             assign_extra(groups, base_iters);
             for (const Group &G : groups) {
                 for (int it = 0; it < base_iters + G.extra; ++it) {
                     NEK_HIP(launch_ax_batch(G.N, G.precision, ax + G.first, G.count, G.ax_blocks, stream));
-                    NEK_HIP(launch_gs_batch(gsl + G.first, G.count, G.gs_blocks, stream));
-                    NEK_HIP(launch_update_batch(up + G.first, G.count, G.upd_blocks, stream));
+                    NEK_HIP(launch_assemble_update_batch(asl + G.first, G.count, G.asm_blocks, stream));
                 }
             }
             // snapshot of every active solve's scalars into buffer q; the snapshot
