@@ -69,23 +69,18 @@ __device__ __forceinline__ void gs_vblock(const GsArgs &a, int vb, gptr<double> 
 
 constexpr int N_XCD = 8;   // gfx950: workgroups are dealt round-robin to 8 XCDs
 
-// XCD-aware work split: the workgroups that land on one XCD (index % 8) walk
-// one contiguous eighth of the virtual blocks, so the copies a row touches
-// and the rows next to it share that XCD's L2.
-// lb / nb: local workgroup index and count (nb a multiple of 8).
-template <typename F>
-__device__ __forceinline__ void for_my_vblocks(int lb, int nb, int nvb, F &&f) {
-    const int xcd = lb % N_XCD;
-    const int per = nb / N_XCD;
-    const int lq = lb / N_XCD;
-    const int v0 = (int)(((long)nvb * xcd) / N_XCD);
-    const int v1 = (int)(((long)nvb * (xcd + 1)) / N_XCD);
-    for (int vb = v0 + lq; vb < v1; vb += per) f(vb);
-}
-
+// The standalone gather-scatter splits every group by XCD the same way (the
+// groups are each ordered by element).
 __global__ void __launch_bounds__(GS_THREADS) gs_kernel(GsArgs a, double *__restrict__ w) {
     const gptr<double> wg = (gptr<double>)w;
-    for_my_vblocks(blockIdx.x, gridDim.x, a.nblocks, [&](int vb) { gs_vblock(a, vb, wg); });
+    const int lb = blockIdx.x, per = gridDim.x / N_XCD, xcd = lb % N_XCD, lq = lb / N_XCD;
+    for (int g = 0; g < a.ngroups; ++g) {
+        const GsGroup &G = a.grp[g];
+        const int gb = (G.rows + GS_THREADS - 1) / GS_THREADS;
+        const int u0 = G.block0 + (int)((long)gb * xcd / N_XCD);
+        const int u1 = G.block0 + (int)((long)gb * (xcd + 1) / N_XCD);
+        for (int vb = u0 + lq; vb < u1; vb += per) gs_vblock(a, vb, wg);
+    }
 }
 
 // ---------------------------------------------------------------- CG steps
