@@ -206,7 +206,7 @@ def main():
         "roofline": {"bound": "hbm", "achieved": round(ax_gbs, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(ax_gbs / HBM_PEAK_GBS, 4),
                      "traffic": traffic_bytes(N, E),
-                     "kernel": f"ax_kernel<{n},double,double,false> (nek_ax)",
+                     "kernel": f"ax_kernel<{n},double,double,false,false> (nek_ax)",
                      "bytes_per_launch": ax_bytes, "launches": reps,
                      "duration_us": round(ax_us_cold, 2)},
         "ax_e": {"us_per_call_cold": round(ax_us_cold, 2), "us_per_call_warm": round(ax_us_warm, 2),
