@@ -242,8 +242,8 @@ int nek_jacobi_inverse(int64_t E, int N, const double *D, const double *g, const
 /* A solve service: requests (box meshes of any size and degree) arrive over
  * time; each is admitted when its whole device footprint fits in the HBM
  * budget, its CG state then stays resident, and every server step advances
- * all admitted solves by CG iterations in shared launches (one operator,
- * one gather-scatter and one update launch per (degree, precision) group).
+ * all admitted solves by CG iterations in shared launches (one operator
+ * and one assemble-update launch per (degree, precision, size) group).
  * Each solve's arithmetic is the same as when it runs alone.  The method is
  * the one of nek_cg_solve (Sec. III, Sec. V); the service around it is not
  * in the paper. */

@@ -1,8 +1,8 @@
 // server.hip -- served Poisson solves: requests arrive over time, are admitted
 // when their whole device footprint fits the budget, keep their CG state
 // resident, and advance together: every step runs CG iterations of all
-// admitted solves with one operator, one gather-scatter and one update launch
-// per (degree, precision) group.  A solve's workgroups do exactly what its own
+// admitted solves with one operator and one assemble-update launch per
+// (degree, precision, size) group.  A solve's workgroups do exactly what its own
 // launch would do (per-solve reductions and tickets), so its result does not
 // depend on which other solves share the launches.
 #include <math.h>
