@@ -399,7 +399,9 @@ __device__ __forceinline__ void assemble_update_body(int lb, int nb, int64_t P, 
                                                      gptr<const double> axparts, int64_t nparts,
                                                      const RedSite &red, gptr<CgScalars> sc) {
     constexpr int K = PRE ? 2 : 1;
-    constexpr int PPT = 8;   // partials loaded per thread at once
+    // partials loaded per thread at once (all of them up to E = 4096 at N = 9;
+    // fewer with a preconditioner, whose chunk holds dinv too)
+    constexpr int PPT = PRE ? 8 : 16;
     if (sc->done) return;
     __shared__ double lds[VEC_THREADS / 64];
     __shared__ double alpha_s;
