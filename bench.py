@@ -19,6 +19,9 @@ uniform in [-1, 1] per global node, zero Dirichlet boundary.
 * jacobi: time to ||r||/||b|| <= 1e-10 with and without the Jacobi
   preconditioner on the 16x8x8 and 16x16x16 boxes at N = 9.
 * sweep: ax_e alone for N = 5..15 at about 32.8 M points each.
+* ablation: ax_e alone with the earlier GPU designs of Sec. IV (original,
+  shared-memory 3D, the paper's 2D-thread layer kernel) beside the pencil
+  kernel, E = 64..4096 at N = 9.
 * serve: a seeded stream of box-mesh solves of mixed sizes and degrees
   (to 1e-10) through the served form, against the same solves one after
   another with nek_cg_solve: capacity (solves/s) and p50/p99 latency under
@@ -60,6 +63,7 @@ def parse():
     ap.add_argument("--no-sweep", action="store_true")
     ap.add_argument("--no-jacobi", action="store_true")
     ap.add_argument("--serve-iters-per-step", type=int, default=4)
+    ap.add_argument("--no-ablation", action="store_true")
     return ap.parse_args()
 
 
@@ -239,6 +243,8 @@ def main():
         out["jacobi"] = jacobi_leg(nek, torch, dev)
     if not args.no_sweep:
         out["sweep"] = sweep_leg(nek, torch, dev, stream)
+    if not args.no_ablation:
+        out["ablation"] = ablation_leg(nek, torch, dev, stream)
     if not args.no_serve:
         out["serve"] = serve_leg(nek, torch, args.serve_requests, args.serve_budget_gb,
                                  args.serve_iters_per_step)
@@ -333,6 +339,46 @@ def jacobi_leg(nek, torch, dev, tol=1e-10, N=9):
         out[f"E{E}"] = leg
         gs.close()
         del g, b, x, ws, dinv
+    torch.cuda.empty_cache()
+    return out
+
+
+def ablation_leg(nek, torch, dev, stream, N=9, reps=30):
+    """ax_e alone with the earlier GPU designs of Sec. IV (nek_ax_variant) beside
+    the pencil kernel, over the element counts of the paper's Fig. 2 (E = 64 to
+    4096, N = 9): median of `reps` launches back to back on one buffer set,
+    each between HIP events on the launch stream.  ORIGINAL allocates its
+    scratch inside every call, as the entry point does."""
+    import synth
+    names = {"pencil": nek.NEK_AX_PENCIL, "layer2d": nek.NEK_AX_LAYER2D,
+             "shared3d": nek.NEK_AX_SHARED3D, "original": nek.NEK_AX_ORIGINAL}
+    n = N + 1
+    out = {"N": N, "timing": "warm (one buffer set), median of %d launches" % reps, "E": {}}
+    D = torch.from_numpy(nek.gll(N)[2]).to(dev)
+    for box in ((4, 4, 4), (8, 8, 8), (16, 8, 8), (16, 16, 8), (16, 16, 16)):
+        E = box[0] * box[1] * box[2]
+        P = E * n ** 3
+        g, _, _ = nek.box_geometry(*box, N, synth.AMP, synth.geom_coeffs())
+        u = torch.from_numpy(synth.local_uniform(P)).to(dev)
+        w = torch.empty_like(u)
+        row = {}
+        for name, v in names.items():
+            for _ in range(3):
+                nek.ax_variant(u, D, g, N, v, out=w)
+            ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(reps)]
+            for a, b in ev:
+                a.record(stream)
+                nek.ax_variant(u, D, g, N, v, out=w)
+                b.record(stream)
+            torch.cuda.synchronize()
+            t = sorted(a.elapsed_time(b) * 1e3 for a, b in ev)
+            us = t[len(t) // 2]
+            row[name] = {"us": round(us, 2), "gflops": round((12 * n + 15) * P / us / 1e3, 1),
+                         "gbs": round(64 * P / us / 1e3, 1)}
+        for name in names:
+            row[name]["vs_pencil"] = round(row["pencil"]["us"] / row[name]["us"], 3)
+        out["E"][str(E)] = row
+        del g, u, w
     torch.cuda.empty_cache()
     return out
 

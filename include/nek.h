@@ -120,6 +120,26 @@ int nek_ax(int64_t E, int N, const double *u, const double *D, const double *g,
 int nek_ax_f32(int64_t E, int N, const double *u, const float *D32, const void *g_lo,
                int g_dtype, double *w, void *stream);
 
+/* The earlier GPU designs of the same operator that Sec. IV describes, for
+ * comparison with nek_ax (which is NEK_AX_PENCIL).  FP64, the layouts and
+ * argument rules of nek_ax, the same result to rounding:
+ *   NEK_AX_ORIGINAL (Sec. IV-A): one workgroup per element, threads striding
+ *     over its points, every operand in global memory; the intermediates
+ *     ur, us, ut go to a scratch of 3*P doubles that the call allocates and
+ *     frees on `stream` (stream-ordered);
+ *   NEK_AX_SHARED3D (Sec. IV-B): one thread per node, the element in LDS;
+ *     n^3 <= 1024 threads per workgroup, so N <= 9 (NEK_ERR_UNSUPPORTED
+ *     above);
+ *   NEK_AX_LAYER2D (Sec. IV-C, the paper's kernel): one thread per (i, j)
+ *     column marching through the k layers, two barriers per layer.
+ * Allocates nothing except ORIGINAL's scratch.  Asynchronous. */
+#define NEK_AX_PENCIL   0
+#define NEK_AX_ORIGINAL 1
+#define NEK_AX_SHARED3D 2
+#define NEK_AX_LAYER2D  3
+int nek_ax_variant(int64_t E, int N, const double *u, const double *D, const double *g,
+                   double *w, int variant, void *stream);
+
 /* Round g (6*P FP64 values, device) to FP32 or BF16 (round to nearest even;
  * BF16 through FP32) into g_lo (device, 6*P values of the chosen type).
  * Paired layout of g_lo: per element, three planes q = 0, 1, 2 of n^3 pairs

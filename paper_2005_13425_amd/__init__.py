@@ -42,6 +42,10 @@ NEK_G_BF16 = 2
 NEK_PREC_F64 = 0
 NEK_PREC_F32G32 = 1
 NEK_PREC_F32GBF16 = 2
+NEK_AX_PENCIL = 0
+NEK_AX_ORIGINAL = 1
+NEK_AX_SHARED3D = 2
+NEK_AX_LAYER2D = 3
 
 _vp = ctypes.c_void_p
 _i64 = ctypes.c_int64
@@ -90,6 +94,7 @@ _sig("nek_gll", _ci, [_ci, _vp, _vp, _vp])
 _sig("nek_box_numbering", _ci, [_ci, _ci, _ci, _ci, _vp, _vp])
 _sig("nek_box_geometry", _ci, [_ci, _ci, _ci, _ci, ctypes.c_double, _vp, _vp, _vp, _vp, _vp])
 _sig("nek_ax", _ci, [_i64, _ci, _vp, _vp, _vp, _vp, _vp])
+_sig("nek_ax_variant", _ci, [_i64, _ci, _vp, _vp, _vp, _vp, _ci, _vp])
 _sig("nek_ax_f32", _ci, [_i64, _ci, _vp, _vp, _vp, _ci, _vp, _vp])
 _sig("nek_convert_g", _ci, [_i64, _ci, _vp, _ci, _vp, _vp])
 _sig("nek_gs_create", _ci, [_i64, _ci, _vp, _vp, ctypes.POINTER(_vp)])
@@ -217,6 +222,22 @@ def ax(u, D, g, N: int, out=None, stream=None):
     _check(_lib.nek_ax(E, N, _dev(u, torch.float64, "u"), _dev(D, torch.float64, "D", (N + 1) ** 2),
                        _dev(g, torch.float64, "g", 6 * E * n3), _dev(out, torch.float64, "w", E * n3),
                        _stream_ptr(stream)), "nek_ax")
+    return out
+
+
+def ax_variant(u, D, g, N: int, variant: int, out=None, stream=None):
+    """w = A_e u with one of the earlier GPU designs of Sec. IV (NEK_AX_ORIGINAL,
+    NEK_AX_SHARED3D, NEK_AX_LAYER2D) or the pencil kernel (NEK_AX_PENCIL)."""
+    torch = _torch()
+    n3 = (N + 1) ** 3
+    if u.numel() % n3:
+        raise ValueError("u size is not a multiple of (N+1)^3")
+    E = u.numel() // n3
+    if out is None:
+        out = torch.empty_like(u)
+    _check(_lib.nek_ax_variant(E, N, _dev(u, torch.float64, "u"), _dev(D, torch.float64, "D", (N + 1) ** 2),
+                               _dev(g, torch.float64, "g", 6 * E * n3), _dev(out, torch.float64, "w", E * n3),
+                               int(variant), _stream_ptr(stream)), "nek_ax_variant")
     return out
 
 

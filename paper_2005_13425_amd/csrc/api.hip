@@ -205,6 +205,35 @@ int nek_ax(int64_t E, int N, const double *u, const double *D, const double *g, 
     return NEK_OK;
 }
 
+int nek_ax_variant(int64_t E, int N, const double *u, const double *D, const double *g, double *w,
+                   int variant, void *stream) {
+    clear_error();
+    int rc = check_ax_args("nek_ax_variant", E, N, u, D, g, w, sizeof(double));
+    if (rc) return rc;
+    if (!aligned8(D) || !aligned8(g)) return fail(NEK_ERR_ARG, "nek_ax_variant: misaligned D or g");
+    const hipStream_t s = (hipStream_t)stream;
+    if (variant == NEK_AX_PENCIL) {
+        NEK_HIP(launch_ax_f64(E, N, D, g, const_cast<double *>(u), w, AxFuse{}, s));
+        return NEK_OK;
+    }
+    if (variant != NEK_AX_ORIGINAL && variant != NEK_AX_SHARED3D && variant != NEK_AX_LAYER2D)
+        return fail(NEK_ERR_UNSUPPORTED, "nek_ax_variant: unknown variant");
+    if (variant == NEK_AX_SHARED3D && N > 9)
+        return fail(NEK_ERR_UNSUPPORTED, "nek_ax_variant: SHARED3D takes n^3 <= 1024 threads, N <= 9");
+    if (E > 0x7fffffff) return fail(NEK_ERR_ARG, "nek_ax_variant: E must be < 2^31");
+    double *scratch = nullptr;
+    if (variant == NEK_AX_ORIGINAL) {
+        const hipError_t e = hipMallocAsync((void **)&scratch, (size_t)(3 * E * n3_of(N)) * sizeof(double), s);
+        if (e != hipSuccess)
+            return fail(e == hipErrorOutOfMemory ? NEK_ERR_NOMEM : NEK_ERR_DEVICE,
+                        std::string("nek_ax_variant: scratch allocation: ") + hipGetErrorString(e));
+    }
+    const hipError_t e = launch_ax_variant(variant, E, N, D, g, u, w, scratch, s);
+    if (scratch) (void)hipFreeAsync(scratch, s);
+    NEK_HIP(e);
+    return NEK_OK;
+}
+
 int nek_ax_f32(int64_t E, int N, const double *u, const float *D32, const void *g_lo, int g_dtype,
                double *w, void *stream) {
     clear_error();

@@ -96,6 +96,9 @@ hipError_t launch_ax_f64(int64_t E, int N, const double *D, const double *g, dou
                          const AxFuse &fz, hipStream_t s);
 hipError_t launch_ax_f32(int64_t E, int N, const float *D32, const void *g_lo, int g_dtype,
                          double *p, double *w, const AxFuse &fz, hipStream_t s);
+// the comparison designs of nek_ax_variant (ORIGINAL needs a scratch of 3P doubles)
+hipError_t launch_ax_variant(int variant, int64_t E, int N, const double *D, const double *g, const double *u,
+                             double *w, double *scratch, hipStream_t s);
 // number of workgroups of an ax launch (one partial each)
 int64_t ax_blocks(int64_t E, int N);
 

@@ -70,6 +70,15 @@ def test_argument_errors_before_device_work(nek):
     assert lib.nek_ax(4, 9, fake, fake, fake, ctypes.c_void_p(0x1008), None) == nek.NEK_ERR_ARG
     assert "overlap" in lib.nek_last_error().decode()
     assert lib.nek_ax_f32(4, 9, fake, fake, fake, 7, ctypes.c_void_p(0x9000000), None) == nek.NEK_ERR_UNSUPPORTED
+    # the comparison designs: unknown variant, SHARED3D above N = 9, the nek_ax checks
+    far = ctypes.c_void_p(0x9000000)
+    assert lib.nek_ax_variant(4, 9, fake, fake, fake, far, 7, None) == nek.NEK_ERR_UNSUPPORTED
+    assert lib.nek_ax_variant(4, 10, fake, fake, fake, far, nek.NEK_AX_SHARED3D, None) == nek.NEK_ERR_UNSUPPORTED
+    assert "N <= 9" in lib.nek_last_error().decode()
+    assert lib.nek_ax_variant(4, 9, fake, fake, fake, ctypes.c_void_p(0x1008), nek.NEK_AX_LAYER2D,
+                              None) == nek.NEK_ERR_ARG
+    assert lib.nek_ax_variant(0, 9, fake, fake, fake, far, nek.NEK_AX_ORIGINAL, None) == nek.NEK_ERR_ARG
+    assert lib.nek_ax_variant(4, 16, fake, fake, fake, far, nek.NEK_AX_ORIGINAL, None) == nek.NEK_ERR_UNSUPPORTED
     assert lib.nek_dssum(None, fake, None) == nek.NEK_ERR_ARG
     assert lib.nek_gs_destroy(None) == nek.NEK_OK
     h = ctypes.c_void_p()
