@@ -19,6 +19,8 @@ uniform in [-1, 1] per global node, zero Dirichlet boundary.
 * jacobi: time to ||r||/||b|| <= 1e-10 with and without the Jacobi
   preconditioner on the 16x8x8 and 16x16x16 boxes at N = 9.
 * sweep: ax_e alone for N = 5..15 at about 32.8 M points each.
+* cg_by_E: the 100-iteration CG step for E = 64..4096 at N = 9 (the range
+  of the paper's Fig. 2).
 * ablation: ax_e alone with the earlier GPU designs of Sec. IV (original,
   shared-memory 3D, the paper's 2D-thread layer kernel) beside the pencil
   kernel, E = 64..4096 at N = 9.
@@ -64,6 +66,7 @@ def parse():
     ap.add_argument("--no-jacobi", action="store_true")
     ap.add_argument("--serve-iters-per-step", type=int, default=4)
     ap.add_argument("--no-ablation", action="store_true")
+    ap.add_argument("--no-cg-by-e", action="store_true")
     return ap.parse_args()
 
 
@@ -245,6 +248,8 @@ def main():
         out["sweep"] = sweep_leg(nek, torch, dev, stream)
     if not args.no_ablation:
         out["ablation"] = ablation_leg(nek, torch, dev, stream)
+    if not args.no_cg_by_e:
+        out["cg_by_E"] = cg_by_e_leg(nek, torch, dev, stream, N)
     if not args.no_serve:
         out["serve"] = serve_leg(nek, torch, args.serve_requests, args.serve_budget_gb,
                                  args.serve_iters_per_step)
@@ -339,6 +344,43 @@ def jacobi_leg(nek, torch, dev, tol=1e-10, N=9):
         out[f"E{E}"] = leg
         gs.close()
         del g, b, x, ws, dinv
+    torch.cuda.empty_cache()
+    return out
+
+
+def cg_by_e_leg(nek, torch, dev, stream, N, iters=100, reps=3):
+    """The CG step of 100 iterations over the element counts of the paper's
+    Fig. 2 (E = 64 to 4096 at N = 9, the boxes of synth.box_for), counted with
+    eq. (1) like `value`: mean of `reps` solves between HIP events."""
+    import synth
+    n = N + 1
+    out = {"N": N, "iters": iters}
+    _, _, Dh = nek.gll(N)
+    D = torch.from_numpy(Dh).to(dev)
+    for E in (64, 512, 1024, 2048, 4096):
+        box = synth.box_for(E)
+        P = E * n ** 3
+        g, _, _ = nek.box_geometry(*box, N, synth.AMP, synth.geom_coeffs())
+        glo, dr = nek.box_numbering(*box, N)
+        gs = nek.GatherScatter(E, N, glo, dr)
+        bh = synth.lattice_uniform(*box, N)[glo]
+        bh[dr == 1] = 0.0
+        b = torch.from_numpy(bh).to(dev)
+        x = torch.empty_like(b)
+        ws = nek.cg_workspace(E, N)
+        nek.cg_solve(D, g, gs, b, x, max_iter=iters, workspace=ws)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        e0.record(stream)
+        for _ in range(reps):
+            nek.cg_solve(D, g, gs, b, x, max_iter=iters, workspace=ws)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / reps
+        out[str(E)] = {"box": list(box), "ms": round(ms, 3), "us_per_iter": round(1e3 * ms / iters, 2),
+                       "gflops": round(iters * P * (12 * n + 34) / (ms * 1e-3) / 1e9, 1)}
+        gs.close()
+        del g, b, x, ws
     torch.cuda.empty_cache()
     return out
 
