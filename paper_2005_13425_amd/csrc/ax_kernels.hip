@@ -154,10 +154,12 @@ __device__ __forceinline__ void ax_body(int64_t blk, int64_t E, kptr<T> D, gptr<
                                         gptr<double> p, gptr<double> w, const AxFuse &fz)
 {
     using S = AxShape<NX, T>;
-    // The plain FP64 operator streams u, g and w with the non-temporal hint
-    // from N = 7 up: 8-12% faster at E = 4096 and on the 32.8 M-point boxes
-    // (N = 7..15), 9% slower at N = 5.  The CG-fused form re-reads p, r, x
-    // and w soon after and keeps the default caching.
+    // The plain FP64 operator streams g and w with the non-temporal hint from
+    // N = 7 up: 8-12% faster at E = 4096 and on the 32.8 M-point boxes
+    // (N = 7..15), 9% slower at N = 5.  u keeps plain loads: a layer of n^2
+    // columns splits over two waves inside a cache line, and with the hint
+    // that line was fetched twice (2% slower at E = 4096).  The CG-fused form
+    // re-reads p, r, x and w soon after and keeps the default caching.
     constexpr bool STREAM = !FUSE && !CGL && sizeof(T) == 8 && NX >= 8;
     constexpr int NN = S::NN;
     constexpr int N3 = S::N3;
@@ -208,7 +210,7 @@ __device__ __forceinline__ void ax_body(int64_t blk, int64_t E, kptr<T> D, gptr<
         if (active) {
 #pragma unroll
             for (int k = 0; k < NX; ++k)
-                pv[k] = STREAM ? __builtin_nontemporal_load(&p[base + k * NN]) : p[base + k * NN];
+                pv[k] = p[base + k * NN];
             if constexpr (FUSE) {
                 if (fx != nullptr && sc->lag_applied == 0) {
                     const double al = sc->alpha;
