@@ -32,12 +32,13 @@ constexpr int round64(int x) { return (x + 63) / 64 * 64; }
 
 // Work shape: EPB elements per workgroup, n^2 threads per element (rounded
 // up to whole wavefronts).  LDS rows are padded to an odd number of words so
-// that lanes walking pencils with stride RS hit distinct banks.
-template <int NX, typename T>
+// that lanes walking pencils with stride RS hit distinct banks.  WIDE: two
+// elements per workgroup at n = 10 (see AxShapeFor).
+template <int NX, typename T, bool WIDE = false>
 struct AxShape {
     static constexpr int NN = NX * NX;
     static constexpr int N3 = NN * NX;
-    static constexpr int EPB = NN >= 64 ? 1 : 256 / NN;
+    static constexpr int EPB = WIDE ? 2 : (NN >= 64 ? 1 : 256 / NN);
     static constexpr int THREADS = round64(EPB * NN);
     static constexpr int RS = NX | 1;                                  // row stride (elements)
     static constexpr int LS = NX * RS;                                 // layer stride
@@ -58,6 +59,13 @@ struct AxShape {
     static constexpr int PF = 4 < NX ? 4 : NX;
 #endif
 };
+
+// The plain FP64 operator at n = 10 runs two elements per workgroup: 2048
+// workgroups at E = 4096 are resident at once, where 4096 took two rounds and
+// the second round's stragglers set the end (3.5% faster; the CG-fused form
+// is 1% slower that way and keeps one element per workgroup).
+template <int NX, typename T, bool FUSE, bool CGL>
+using AxShapeFor = AxShape<NX, T, !FUSE && !CGL && sizeof(T) == 8 && NX == 10>;
 
 // Loading the six geometric factors of one point of layer k.
 //   FP64 g: the layout of Listing 1, six planes of n^3 per element (six loads).
@@ -153,7 +161,7 @@ template <int NX, typename T, typename GT, bool FUSE, bool CGL>
 __device__ __forceinline__ void ax_body(int64_t blk, int64_t E, kptr<T> D, gptr<const GT> g,
                                         gptr<double> p, gptr<double> w, const AxFuse &fz)
 {
-    using S = AxShape<NX, T>;
+    using S = AxShapeFor<NX, T, FUSE, CGL>;
     // The plain FP64 operator streams g and w with the non-temporal hint from
     // N = 7 up: 8-12% faster at E = 4096 and on the 32.8 M-point boxes
     // (N = 7..15), 9% slower at N = 5.  u keeps plain loads: a layer of n^2
@@ -413,8 +421,9 @@ __device__ __forceinline__ void ax_body(int64_t blk, int64_t E, kptr<T> D, gptr<
 }
 
 template <int NX, typename T, typename GT, bool FUSE, bool CGL>
-__global__ void __launch_bounds__((AxShape<NX, T>::THREADS),
-                                  (FUSE || CGL ? AxShape<NX, T>::MINW_FUSED : AxShape<NX, T>::MINW))
+__global__ void __launch_bounds__((AxShapeFor<NX, T, FUSE, CGL>::THREADS),
+                                  (FUSE || CGL ? AxShapeFor<NX, T, FUSE, CGL>::MINW_FUSED
+                                               : AxShapeFor<NX, T, FUSE, CGL>::MINW))
 ax_kernel(int64_t E, const T *__restrict__ D, const GT *__restrict__ g, double *__restrict__ p,
           double *__restrict__ w, AxFuse fz)
 {
@@ -448,21 +457,28 @@ template <int NX, typename T, typename GT>
 hipError_t launch_one(int64_t E, const T *D, const GT *g, double *p, double *w, const AxFuse &fz,
                       hipStream_t s)
 {
-    using S = AxShape<NX, T>;
-    const int64_t blocks = (E + S::EPB - 1) / S::EPB;
-    if (blocks > 0x7fffffff) return hipErrorInvalidValue;
     // the CG-fused form always works in the CG layout
     if (fz.sc != nullptr) {
         if (!fz.cg_layout) return hipErrorInvalidValue;
+        using S = AxShapeFor<NX, T, true, true>;
+        const int64_t blocks = (E + S::EPB - 1) / S::EPB;
+        if (blocks > 0x7fffffff) return hipErrorInvalidValue;
         hipLaunchKernelGGL((ax_kernel<NX, T, GT, true, true>), dim3((unsigned)blocks), dim3(S::THREADS),
                            0, s, E, D, g, p, w, fz);
     } else if (fz.cg_layout) {
-        if constexpr (sizeof(T) == 8)
+        if constexpr (sizeof(T) == 8) {
+            using S = AxShapeFor<NX, T, false, true>;
+            const int64_t blocks = (E + S::EPB - 1) / S::EPB;
+            if (blocks > 0x7fffffff) return hipErrorInvalidValue;
             hipLaunchKernelGGL((ax_kernel<NX, T, GT, false, true>), dim3((unsigned)blocks),
                                dim3(S::THREADS), 0, s, E, D, g, p, w, fz);
-        else
+        } else {
             return hipErrorInvalidValue;
+        }
     } else {
+        using S = AxShapeFor<NX, T, false, false>;
+        const int64_t blocks = (E + S::EPB - 1) / S::EPB;
+        if (blocks > 0x7fffffff) return hipErrorInvalidValue;
         hipLaunchKernelGGL((ax_kernel<NX, T, GT, false, false>), dim3((unsigned)blocks), dim3(S::THREADS),
                            0, s, E, D, g, p, w, fz);
     }
