@@ -684,7 +684,8 @@ int nek_cg_solve(int64_t E, int N, const double *D, const double *g, const nek_g
     }
     CgScalars *snap = g_snap.buf;
     const uint32_t *own = gs->cg.own_bits;
-    const double *bc = W.b, *dinvc = W.dinv;   // b and M^-1 in the CG layout
+    const double *bc = W.b;        // b in the CG layout
+    const float *dinvc = W.dinv;   // M^-1 in the CG layout, rounded to FP32
 
     // one CG iteration; `first` uses p = b as set by the init kernel
     const RedSite red_upd = site(SITE_UPDATE, nullptr, 0);
@@ -728,7 +729,7 @@ int nek_cg_solve(int64_t E, int N, const double *D, const double *g, const nek_g
     {
         CG_TRY(launch_cg_reset(sc, tickets, N_SITES * RED_TICKETS, opts.max_iter, opts.rel_tol, drop, s));
         CG_TRY(launch_permute(E, N, b, W.b, true, s));
-        if (opts.dinv) CG_TRY(launch_permute(E, N, opts.dinv, W.dinv, true, s));
+        if (opts.dinv) CG_TRY(launch_permute_to_cg_f32(E, N, opts.dinv, W.dinv, s));
         CG_TRY(launch_cg_init(P, bc, x, r, p, own, dinvc, site(SITE_INIT, nullptr, 0), sc, s));
         if (poll) {
             CG_TRY(hipEventCreateWithFlags(&ev[0], hipEventDisableTiming));

@@ -181,7 +181,7 @@ __device__ __forceinline__ void ax_body(int64_t blk, int64_t E, kptr<T> D, gptr<
     const kptr<CgScalars> sc = (kptr<CgScalars>)fz.sc;
     const gptr<const double> fr = (gptr<const double>)fz.r;
     const gptr<double> fx = (gptr<double>)fz.x;
-    const gptr<const double> fdinv = (gptr<const double>)fz.dinv;
+    const gptr<const float> fdinv = (gptr<const float>)fz.dinv;
     if (FUSE && sc->done) return;   // uniform: CG already finished
 
     __shared__ T lds[EPB * 2 * BUF];
@@ -244,7 +244,7 @@ __device__ __forceinline__ void ax_body(int64_t blk, int64_t E, kptr<T> D, gptr<
                     for (int k = 0; k < NX; ++k) rr[k] = fr[base + k * NN];
                     if (fdinv != nullptr) {   // z = M^-1 r, formed on the way in
 #pragma unroll
-                        for (int k = 0; k < NX; ++k) rr[k] = fdinv[base + k * NN] * rr[k];
+                        for (int k = 0; k < NX; ++k) rr[k] = (double)fdinv[base + k * NN] * rr[k];
                     }
 #pragma unroll
                     for (int k = 0; k < NX; ++k) {

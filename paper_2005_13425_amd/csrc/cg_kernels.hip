@@ -133,7 +133,7 @@ template <bool PRE>
 __global__ void __launch_bounds__(VEC_THREADS)
 cg_init_kernel(int64_t P, const double *__restrict__ b, double *__restrict__ x,
                double *__restrict__ r, double *__restrict__ p, const uint32_t *__restrict__ own,
-               const double *__restrict__ dinv, RedSite red, CgScalars *sc) {
+               const float *__restrict__ dinv, RedSite red, CgScalars *sc) {
     constexpr int K = PRE ? 2 : 1;
     __shared__ double lds[VEC_THREADS / 64];
     const int64_t npairs = P >> 1;
@@ -148,7 +148,8 @@ cg_init_kernel(int64_t P, const double *__restrict__ b, double *__restrict__ x,
             if (q < npairs) {
                 bv[m] = ((const double2 *)b)[q];
                 if constexpr (PRE) {
-                    const double2 dv = ((const double2 *)dinv)[q];
+                    const float2 df = ((const float2 *)dinv)[q];
+                    const double2 dv = make_double2(df.x, df.y);
                     zv[m] = make_double2(dv.x * bv[m].x, dv.y * bv[m].y);
                 } else {
                     zv[m] = bv[m];
@@ -177,7 +178,7 @@ cg_init_kernel(int64_t P, const double *__restrict__ b, double *__restrict__ x,
     if (owns_tail(P)) {
         const int64_t t = P - 1;
         const double bv = b[t];
-        const double zv = PRE ? dinv[t] * bv : bv;
+        const double zv = PRE ? (double)dinv[t] * bv : bv;
         x[t] = 0.0;
         r[t] = bv;
         p[t] = zv;
@@ -214,7 +215,7 @@ cg_init_kernel(int64_t P, const double *__restrict__ b, double *__restrict__ x,
 // contribution to (r, r) and (r, M^-1 r) is taken once.
 template <int C, bool PRE>
 __device__ __forceinline__ void asm_row(gptr<const int32_t> idx, int32_t rows, int32_t row,
-                                        gptr<const double> w, gptr<double> r, gptr<const double> dinv,
+                                        gptr<const double> w, gptr<double> r, gptr<const float> dinv,
                                         double alpha, double *acc) {
     int32_t id[C];
 #pragma unroll
@@ -237,7 +238,7 @@ __device__ __forceinline__ void asm_row(gptr<const int32_t> idx, int32_t rows, i
 
 template <bool PRE>
 __device__ __forceinline__ void asm_vblock(const GsArgs &a, int vb, gptr<const double> w, gptr<double> r,
-                                           gptr<const double> dinv, double alpha, double *acc) {
+                                           gptr<const float> dinv, double alpha, double *acc) {
     int g = 0;
     while (g + 1 < a.ngroups && vb >= a.grp[g + 1].block0) ++g;
     const GsGroup &G = a.grp[g];
@@ -293,7 +294,7 @@ __device__ __forceinline__ void row_setup(const GsArgs &a, int vb, RowJob &J) {
 
 template <bool PRE>
 __device__ __forceinline__ void row_load(RowJob &J, gptr<const double> w, gptr<const double> r,
-                                         gptr<const double> dinv) {
+                                         gptr<const float> dinv) {
     if (J.C == 0) return;
 #pragma unroll
     for (int m = 0; m < 4; ++m)
@@ -336,14 +337,17 @@ __device__ __forceinline__ void chunk_bits(int64_t base, int64_t npairs, gptr<co
 
 template <bool PRE>
 __device__ __forceinline__ void chunk_load(int64_t base, gptr<const double> r, gptr<const double> w,
-                                           gptr<const double> dinv, PairChunk<PRE> &Q) {
+                                           gptr<const float> dinv, PairChunk<PRE> &Q) {
 #pragma unroll
     for (int m = 0; m < VEC_PAIRS; ++m) {
         const int64_t q = base + threadIdx.x + (int64_t)m * VEC_THREADS;
         if (Q.rb[m] != 3u) {
             Q.rv[m] = ((gptr<const double2>)r)[q];
             Q.wv[m] = ((gptr<const double2>)w)[q];
-            if constexpr (PRE) Q.dv[m] = ((gptr<const double2>)dinv)[q];
+            if constexpr (PRE) {
+                const float2 df = ((gptr<const float2>)dinv)[q];
+                Q.dv[m] = make_double2(df.x, df.y);
+            }
         }
     }
 }
@@ -402,7 +406,7 @@ __device__ __forceinline__ void chunk_finish(int64_t base, gptr<double> r, doubl
 template <bool PRE>
 __device__ __forceinline__ void assemble_update_body(int lb, int nb, int64_t P, const GsArgs &a,
                                                      gptr<const uint32_t> rowed, gptr<double> r,
-                                                     gptr<const double> w, gptr<const double> dinv,
+                                                     gptr<const double> w, gptr<const float> dinv,
                                                      gptr<const double> axparts, int64_t nparts,
                                                      const RedSite &red, gptr<CgScalars> sc) {
     constexpr int K = PRE ? 2 : 1;
@@ -559,10 +563,10 @@ __device__ __forceinline__ void assemble_update_body(int lb, int nb, int64_t P, 
 template <bool PRE>
 __global__ void __launch_bounds__(VEC_THREADS)
 assemble_update_kernel(int64_t P, GsArgs a, const uint32_t *__restrict__ rowed, double *__restrict__ r,
-                       const double *__restrict__ w, const double *__restrict__ dinv,
+                       const double *__restrict__ w, const float *__restrict__ dinv,
                        const double *__restrict__ axparts, int64_t nparts, RedSite red, CgScalars *sc) {
     assemble_update_body<PRE>(blockIdx.x, gridDim.x, P, a, (gptr<const uint32_t>)rowed, (gptr<double>)r,
-                              (gptr<const double>)w, (gptr<const double>)dinv,
+                              (gptr<const double>)w, (gptr<const float>)dinv,
                               (gptr<const double>)axparts, nparts, red, (gptr<CgScalars>)sc);
 }
 
@@ -697,16 +701,17 @@ constexpr int64_t PERM_MAX_BLOCKS = 65536;
 
 // Workgroups stride over elements; threads over an element's points in the
 // order of Listing 1 (coalesced on that side).
+template <typename DT>
 __global__ void __launch_bounds__(PERM_THREADS)
-permute_kernel(int64_t E, int n, const double *__restrict__ src, double *__restrict__ dst, bool to_cg) {
+permute_kernel(int64_t E, int n, const double *__restrict__ src, DT *__restrict__ dst, bool to_cg) {
     const int n3 = n * n * n;
     for (int64_t e = blockIdx.x; e < E; e += gridDim.x) {
         const int64_t base = e * n3;
         for (int l = threadIdx.x; l < n3; l += PERM_THREADS) {
             const int nn = n * n, k = l / nn, ij = l - k * nn;
             const int64_t c = base + k * nn + cgl_col(ij % n, ij / n, n);
-            if (to_cg) dst[c] = src[base + l];
-            else dst[base + l] = src[c];
+            if (to_cg) dst[c] = (DT)src[base + l];
+            else dst[base + l] = (DT)src[c];
         }
     }
 }
@@ -716,8 +721,16 @@ permute_kernel(int64_t E, int n, const double *__restrict__ src, double *__restr
 hipError_t launch_permute(int64_t E, int N, const double *src, double *dst, bool to_cg, hipStream_t s) {
     if (E < 1) return hipSuccess;
     const int64_t blocks = E < PERM_MAX_BLOCKS ? E : PERM_MAX_BLOCKS;
-    hipLaunchKernelGGL(permute_kernel, dim3((unsigned)blocks), dim3(PERM_THREADS), 0, s, E, N + 1, src, dst,
-                       to_cg);
+    hipLaunchKernelGGL(permute_kernel<double>, dim3((unsigned)blocks), dim3(PERM_THREADS), 0, s, E, N + 1, src,
+                       dst, to_cg);
+    return hipGetLastError();
+}
+
+hipError_t launch_permute_to_cg_f32(int64_t E, int N, const double *src, float *dst, hipStream_t s) {
+    if (E < 1) return hipSuccess;
+    const int64_t blocks = E < PERM_MAX_BLOCKS ? E : PERM_MAX_BLOCKS;
+    hipLaunchKernelGGL(permute_kernel<float>, dim3((unsigned)blocks), dim3(PERM_THREADS), 0, s, E, N + 1, src,
+                       dst, true);
     return hipGetLastError();
 }
 
@@ -748,7 +761,7 @@ int64_t asm_blocks(const GsDevice &gs) {
     return g > RED_MAX_BLOCKS ? RED_MAX_BLOCKS : g;
 }
 
-hipError_t launch_cg_assemble_update(const GsDevice &gs, double *r, const double *w, const double *dinv,
+hipError_t launch_cg_assemble_update(const GsDevice &gs, double *r, const double *w, const float *dinv,
                                      const double *axparts, int64_t nparts, const RedSite &red,
                                      CgScalars *sc, hipStream_t s) {
     const dim3 grid((unsigned)asm_blocks(gs));
@@ -783,7 +796,7 @@ hipError_t launch_cg_reset(CgScalars *sc, unsigned int *tickets, int nticket, in
 }
 
 hipError_t launch_cg_init(int64_t P, const double *b, double *x, double *r, double *p,
-                          const uint32_t *own, const double *dinv, const RedSite &red, CgScalars *sc,
+                          const uint32_t *own, const float *dinv, const RedSite &red, CgScalars *sc,
                           hipStream_t s) {
     if (dinv != nullptr)
         hipLaunchKernelGGL(cg_init_kernel<true>, dim3((unsigned)vec_blocks(P)), dim3(VEC_THREADS), 0, s,

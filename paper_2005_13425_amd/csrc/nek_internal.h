@@ -75,7 +75,8 @@ constexpr double RELIABLE_DROP_DEFAULT = 0.3;
 // ---------------------------------------------------------------- ax_e
 // Optional CG fusion of the local-operator launch (all device pointers):
 //   r != null : p <- r + beta p on the way in (beta from sc);
-//   dinv != null (with r) : p <- dinv r + beta p (Jacobi-preconditioned CG);
+//   dinv != null (with r) : p <- dinv r + beta p (Jacobi-preconditioned CG;
+//                           dinv held in FP32);
 //   x != null : x += alpha p_old first, if sc->lag_applied == 0;
 //   partials != null : per-workgroup sum of p * (A_L p) over all local
 //                      points, at partials[blockIdx] (the assemble-update
@@ -86,7 +87,7 @@ struct AxFuse {
     double *x = nullptr;
     double *partials = nullptr;
     const CgScalars *sc = nullptr;
-    const double *dinv = nullptr;
+    const float *dinv = nullptr;
     // vectors p, r, x, dinv and w in the CG layout.  Always the case with
     // sc != null; without it, FP64 only (the true residual of a CG).
     bool cg_layout = false;
@@ -220,9 +221,11 @@ int64_t vec_blocks(int64_t P);          // workgroups of the vector kernels (<= 
 
 hipError_t launch_cg_reset(CgScalars *sc, unsigned int *tickets, int nticket, int max_iter,
                            double rel_tol, double drop, hipStream_t s);
-// dinv (may be null): the Jacobi preconditioner M^-1 as a continuous local vector
+// dinv (may be null): the Jacobi preconditioner M^-1 as a continuous local
+// vector, in FP32 (a fixed SPD diagonal: its rounding changes the
+// preconditioner, not the system solved)
 hipError_t launch_cg_init(int64_t P, const double *b, double *x, double *r, double *p,
-                          const uint32_t *own, const double *dinv, const RedSite &red, CgScalars *sc,
+                          const uint32_t *own, const float *dinv, const RedSite &red, CgScalars *sc,
                           hipStream_t s);
 // The CG step after the operator, with the dssum folded in: w holds the
 // unassembled A_L p.  For every unmasked shared node the copies of w are
@@ -234,7 +237,7 @@ hipError_t launch_cg_init(int64_t P, const double *b, double *x, double *r, doub
 // per-workgroup partials of (p, A_L p) left by the ax launch, summed in index
 // order by every workgroup (workgroup 0 records it, or flags a breakdown).
 hipError_t launch_cg_assemble_update(const GsDevice &gs, double *r, const double *w,
-                                     const double *dinv, const double *axparts, int64_t nparts,
+                                     const float *dinv, const double *axparts, int64_t nparts,
                                      const RedSite &red, CgScalars *sc, hipStream_t s);
 int64_t asm_blocks(const GsDevice &gs);   // its grid: a multiple of 8, <= RED_MAX_BLOCKS
 
@@ -259,6 +262,8 @@ hipError_t launch_cg_finish(int64_t P, double *x, const double *p, const CgScala
 // dst <- src converted between the layout of Listing 1 and the CG layout
 // (to_cg: Listing 1 -> CG); dst and src must not overlap
 hipError_t launch_permute(int64_t E, int N, const double *src, double *dst, bool to_cg, hipStream_t s);
+// the same, Listing 1 -> CG layout, rounding to FP32
+hipError_t launch_permute_to_cg_f32(int64_t E, int N, const double *src, float *dst, hipStream_t s);
 hipError_t launch_cg_replace(int64_t P, const double *b, const double *w, double *r,
                              const uint32_t *own, const RedSite &red, CgScalars *sc, hipStream_t s);
 // result <- sum own * a * b / sum own * (a - b)^2, deterministic, one device double
@@ -306,7 +311,8 @@ inline CgLayout cg_layout(int64_t E, int N, int extra) {
 // Pointers into one CG workspace.
 struct CgWs {
     double *r, *p, *w, *axp, *site_mem, *scratch;
-    double *b = nullptr, *dinv = nullptr;   // the extra vectors, if any
+    double *b = nullptr;                    // the extra vectors, if any
+    float *dinv = nullptr;
     unsigned int *tickets;
     CgScalars *sc;
     RedSite site(int k, const double *extra = nullptr, long nextra = 0) const {
@@ -329,7 +335,7 @@ inline CgWs cg_ws(void *ws, int64_t E, int N, int extra) {
     W.sc = (CgScalars *)(c + L.scalars);
     W.scratch = (double *)(c + L.scratch);
     if (extra >= 1) W.b = (double *)(c + L.extra);
-    if (extra >= 2) W.dinv = (double *)(c + L.extra + vb);
+    if (extra >= 2) W.dinv = (float *)(c + L.extra + vb);
     return W;
 }
 

@@ -5,7 +5,9 @@
   (each entry is a short sum of O(n) positive terms and a reciprocal),
   exact zeros at masked nodes;
 * preconditioned CG after 100 iterations: rel-L2 <= 1e-12 against the oracle
-  (the FP64 bar of the plain solver);
+  (the FP64 bar of the plain solver).  The solver holds M^-1 in FP32, so both
+  sides get the oracle's inverse and the oracle applies it rounded to FP32
+  (round to nearest even, as the solver's conversion does);
 * to a tolerance: the same iteration count (+-3) and the converged solution;
 * the identity preconditioner (the mask) reproduces plain CG bitwise: same
   kernels, the second sum of the paired reduction equals the first;
@@ -66,11 +68,12 @@ def _pcg_case(nek, box, N, iters, rel_tol=0.0):
     b = oracle.lattice_to_local(m, synth.lattice_uniform(*box, N))
     gs = nek.GatherScatter(m.E, N, m.glo, m.dirichlet)
     Dt, gt = _dev(m.D), _dev(m.g)
-    dinv = nek.jacobi_inverse(Dt, gt, gs)
-    x, res = nek.cg_solve(Dt, gt, gs, _dev(b), max_iter=iters, rel_tol=rel_tol, dinv=dinv,
+    dinv = oracle.jacobi_inverse(m)
+    x, res = nek.cg_solve(Dt, gt, gs, _dev(b), max_iter=iters, rel_tol=rel_tol, dinv=_dev(dinv),
                           true_residual=True)
     torch.cuda.synchronize()
-    ref = oracle.pcg(m, b, oracle.jacobi_inverse(m), max_iter=iters, rel_tol=rel_tol)
+    dinv32 = dinv.astype(np.float32).astype(np.float64)
+    ref = oracle.pcg(m, b, dinv32, max_iter=iters, rel_tol=rel_tol)
     gs.close()
     return m, x, res, ref
 
