@@ -7,21 +7,21 @@
 //
 // Work layout (gfx950, wave64, 160 KB LDS per CU):
 //   * a workgroup holds EPB whole elements (n^2 threads each, small degrees
-//     packed so a workgroup has about 256 threads); the whole element is
-//     staged in LDS (three padded n^3 buffers), which the large LDS of gfx950
-//     allows, instead of one layer at a time as in the paper's 2D-thread
-//     kernel (Sec. IV-C);
+//     packed so a workgroup has about 256 threads, two elements at n = 10 in
+//     the plain FP64 form); the whole element is staged in LDS (two padded
+//     n^3 buffers), which the large LDS of gfx950 allows, instead of one layer
+//     at a time as in the paper's 2D-thread kernel (Sec. IV-C);
 //   * the t-direction contractions run on a register column per thread
-//     (thread (i,j) holds u(i,j,:) and accumulates w(i,j,:));
+//     (thread (i,j) holds u(i,j,:) and forms w(i,j,:));
 //   * the r- and s-direction contractions run as pencils: one thread applies
 //     the whole n x n matrix to one line of n values, so the matrix entry is
 //     the same for every lane and comes through the scalar cache, and each
-//     LDS value is read once per direction (about 16 LDS accesses per point
+//     LDS value is read once per direction (about 18 LDS accesses per point
 //     instead of ~4n for a per-lane gather);
-//   * the six geometric factors (75% of the HBM bytes) are loaded two layers
+//   * the six geometric factors (75% of the HBM bytes) are loaded four layers
 //     ahead of use;
-//   * optionally the CG direction update p <- r + beta p is fused into the
-//     load of u, writing p back once.
+//   * in the CG the updates x += alpha p and p <- r + beta p are fused into
+//     the load of u, and the (p, A_L p) partial comes out of the same pass.
 #include "nek_internal.h"
 #include "reduce.h"
 
