@@ -28,8 +28,8 @@ COMMON = [
     "-Wno-unused-command-line-argument",
 ]
 
-SOURCES = ["ablation_kernels.hip", "api.hip", "ax_kernels.hip", "cg_kernels.hip", "geom_kernels.hip",
-           "jacobi_kernels.hip", "probe_kernels.hip", "server.hip"]
+SOURCES = ["ablation_kernels.hip", "api.hip", "ax_kernels.hip", "cg_kernels.hip", "cg_node_kernels.hip",
+           "geom_kernels.hip", "jacobi_kernels.hip", "probe_kernels.hip", "server.hip"]
 
 
 def _compile(src: str) -> str:

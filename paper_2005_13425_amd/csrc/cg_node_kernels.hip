@@ -1,0 +1,128 @@
+// cg_node_kernels.hip -- the CG's fused operator for small meshes: one thread
+// per node, the element's p and the three intermediates ur, us, ut in LDS
+// (the shared-memory design of Sec. IV-B).  With few elements the pencil
+// kernel's n^2 threads per element leave most of the GPU idle and each
+// element's n layers form one long latency chain; n^3 threads per element
+// take every layer at once.
+//
+// Same contract as the CG-fused pencil operator: AxFuse with sc, r, x, dinv
+// and partials; the vectors p, r, x, dinv and w in the CG layout, g in the
+// layout of Listing 1.  FP64, n = 8..10 (n^3 <= 1024 threads), one workgroup
+// per element, so the partials of (p, A_L p) land where the pencil kernel
+// puts them (it also runs one element per workgroup at these degrees).
+#include "nek_internal.h"
+#include "reduce.h"
+
+namespace nek {
+namespace {
+
+constexpr int node_threads(int nx) { return (nx * nx * nx + 63) / 64 * 64; }
+
+template <int NX>
+__global__ void __launch_bounds__(node_threads(NX))
+ax_node_fused_kernel(const double *__restrict__ D_, const double *__restrict__ g_, double *__restrict__ p_,
+                     double *__restrict__ w_, AxFuse fz) {
+    constexpr int NN = NX * NX, N3 = NN * NX, NT = node_threads(NX);
+    // the CG scalars are written only by other launches
+    const kptr<CgScalars> sc = (kptr<CgScalars>)fz.sc;
+    if (sc->done) return;   // uniform: CG already finished
+    __shared__ double su[N3], sr[N3], ss[N3], st[N3], sD[NN];
+    __shared__ double red[NT / 64];
+    const gptr<const double> D = (gptr<const double>)D_;
+    const gptr<double> p = (gptr<double>)p_, w = (gptr<double>)w_;
+    const gptr<const double> fr = (gptr<const double>)fz.r;
+    const gptr<double> fx = (gptr<double>)fz.x;
+    const gptr<const float> fdinv = (gptr<const float>)fz.dinv;
+
+    const int64_t e = blockIdx.x;
+    const int t = threadIdx.x;   // node (i, j, k) in the order of Listing 1
+    const bool on = t < N3;
+    const int i = t % NX, j = (t / NX) % NX, k = t / NN;
+    const int64_t at = e * N3 + (int64_t)k * NN + cgl_col(i, j, NX);   // its entry of the CG vectors
+
+    // geometric factors first: they do not depend on anything else
+    double gv[6];
+    {
+        const gptr<const double> ge = (gptr<const double>)g_ + e * (6 * N3) + t;
+#pragma unroll
+        for (int q = 0; q < 6; ++q) gv[q] = on ? ge[q * N3] : 0.0;
+    }
+    // x += alpha p_old, p <- r + beta p_old (dinv r + beta p_old with Jacobi)
+    double pv = 0.0;
+    if (on) {
+        pv = p[at];
+        if (fx != nullptr && sc->lag_applied == 0) {
+            const double xv = __builtin_nontemporal_load(&fx[at]);
+            __builtin_nontemporal_store(xv + sc->alpha * pv, &fx[at]);
+        }
+        if (fr != nullptr) {
+            double rv = fr[at];
+            if (fdinv != nullptr) rv = (double)fdinv[at] * rv;
+            pv = rv + sc->beta * pv;
+            p[at] = pv;
+        }
+        su[t] = pv;
+    }
+    if (t < NN) sD[t] = D[t];
+    __syncthreads();
+
+    // forward contractions with dxm1 (D[i + n l] = dxm1(i, l)), then the
+    // geometric multiply
+    if (on) {
+        double wr = 0.0, ws = 0.0, wt = 0.0;
+#pragma unroll
+        for (int l = 0; l < NX; ++l) {
+            wr += sD[i + NX * l] * su[l + NX * j + NN * k];
+            ws += sD[j + NX * l] * su[i + NX * l + NN * k];
+            wt += sD[k + NX * l] * su[i + NX * j + NN * l];
+        }
+        sr[t] = gv[0] * wr + gv[1] * ws + gv[2] * wt;
+        ss[t] = gv[1] * wr + gv[3] * ws + gv[4] * wt;
+        st[t] = gv[2] * wr + gv[4] * ws + gv[5] * wt;
+    }
+    __syncthreads();
+
+    // transposed contractions summed (dxtm1(i, l) = dxm1(l, i))
+    double pw = 0.0;
+    if (on) {
+        double s = 0.0;
+#pragma unroll
+        for (int l = 0; l < NX; ++l)
+            s += sD[l + NX * i] * sr[l + NX * j + NN * k] + sD[l + NX * j] * ss[i + NX * l + NN * k] +
+                 sD[l + NX * k] * st[i + NX * j + NN * l];
+        w[at] = s;
+        pw = pv * s;
+    }
+    // this element's share of sum p (A_L p), as the pencil kernel leaves it
+    if (fz.partials != nullptr) {
+        const double bs = block_sum<NT>(pw, red);
+        if (t == 0) ((gptr<double>)fz.partials)[blockIdx.x] = bs;
+    }
+}
+
+template <int NX>
+hipError_t launch_node(int64_t E, const double *D, const double *g, double *p, double *w, const AxFuse &fz,
+                       hipStream_t s) {
+    hipLaunchKernelGGL(ax_node_fused_kernel<NX>, dim3((unsigned)E), dim3(node_threads(NX)), 0, s, D, g, p, w,
+                       fz);
+    return hipGetLastError();
+}
+
+}  // namespace
+
+bool ax_node_fused_fits(int64_t E, int N) {
+    return N >= 7 && N <= 9 && E >= 1 && E <= AX_NODE_MAX_POINTS / n3_of(N);
+}
+
+hipError_t launch_ax_node_fused(int64_t E, int N, const double *D, const double *g, double *p, double *w,
+                                const AxFuse &fz, hipStream_t s) {
+    if (!ax_node_fused_fits(E, N) || fz.sc == nullptr || !fz.cg_layout) return hipErrorInvalidValue;
+    switch (N) {
+    case 7: return launch_node<8>(E, D, g, p, w, fz, s);
+    case 8: return launch_node<9>(E, D, g, p, w, fz, s);
+    case 9: return launch_node<10>(E, D, g, p, w, fz, s);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+}  // namespace nek

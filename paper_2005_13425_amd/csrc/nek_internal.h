@@ -97,6 +97,20 @@ hipError_t launch_ax_f64(int64_t E, int N, const double *D, const double *g, dou
                          const AxFuse &fz, hipStream_t s);
 hipError_t launch_ax_f32(int64_t E, int N, const float *D32, const void *g_lo, int g_dtype,
                          double *p, double *w, const AxFuse &fz, hipStream_t s);
+// The CG-fused operator with one thread per node, for small meshes
+// (cg_node_kernels.hip): same arguments and results as launch_ax_f64 with a
+// CG AxFuse, for N = 7..9 and at most AX_NODE_MAX_POINTS local points
+// (ax_node_fused_fits).  Measured against the pencil operator (CG iteration
+// time): 5-13% faster up to E = 256 at N = 7, 8, 9 and at E = 512 for N = 7,
+// 8 (262 144 and 373 248 points); 2% slower at E = 512, N = 9 (512 000).
+#ifdef NEK_AX_NODE_MAX_POINTS
+constexpr int64_t AX_NODE_MAX_POINTS = NEK_AX_NODE_MAX_POINTS;
+#else
+constexpr int64_t AX_NODE_MAX_POINTS = 400000;
+#endif
+bool ax_node_fused_fits(int64_t E, int N);
+hipError_t launch_ax_node_fused(int64_t E, int N, const double *D, const double *g, double *p, double *w,
+                                const AxFuse &fz, hipStream_t s);
 // the comparison designs of nek_ax_variant (ORIGINAL needs a scratch of 3P doubles)
 hipError_t launch_ax_variant(int variant, int64_t E, int N, const double *D, const double *g, const double *u,
                              double *w, double *scratch, hipStream_t s);
