@@ -25,7 +25,9 @@ ax_node_fused_kernel(const double *__restrict__ D_, const double *__restrict__ g
     constexpr int NN = NX * NX, N3 = NN * NX, NT = node_threads(NX);
     // the CG scalars are written only by other launches
     const kptr<CgScalars> sc = (kptr<CgScalars>)fz.sc;
-    if (sc->done) return;   // uniform: CG already finished
+    // uniform: the CG has finished (tested once the loads are in flight,
+    // before the first store)
+    const int done = sc->done;
     __shared__ double su[N3], sr[N3], ss[N3], st[N3], sD[NN];
     __shared__ double red[NT / 64];
     const gptr<const double> D = (gptr<const double>)D_;
@@ -48,22 +50,27 @@ ax_node_fused_kernel(const double *__restrict__ D_, const double *__restrict__ g
         for (int q = 0; q < 6; ++q) gv[q] = on ? ge[q * N3] : 0.0;
     }
     // x += alpha p_old, p <- r + beta p_old (dinv r + beta p_old with Jacobi)
-    double pv = 0.0;
+    const bool upd_x = fx != nullptr && sc->lag_applied == 0;
+    double pv = 0.0, rv = 0.0, xv = 0.0;
     if (on) {
         pv = p[at];
-        if (fx != nullptr && sc->lag_applied == 0) {
-            const double xv = __builtin_nontemporal_load(&fx[at]);
-            __builtin_nontemporal_store(xv + sc->alpha * pv, &fx[at]);
-        }
+        if (upd_x) xv = __builtin_nontemporal_load(&fx[at]);
         if (fr != nullptr) {
-            double rv = fr[at];
+            rv = fr[at];
             if (fdinv != nullptr) rv = (double)fdinv[at] * rv;
+        }
+    }
+    const double dv = t < NN ? D[t] : 0.0;
+    if (done) return;
+    if (on) {
+        if (upd_x) __builtin_nontemporal_store(xv + sc->alpha * pv, &fx[at]);
+        if (fr != nullptr) {
             pv = rv + sc->beta * pv;
             p[at] = pv;
         }
         su[t] = pv;
     }
-    if (t < NN) sD[t] = D[t];
+    if (t < NN) sD[t] = dv;
     __syncthreads();
 
     // forward contractions with dxm1 (D[i + n l] = dxm1(i, l)), then the
