@@ -688,8 +688,8 @@ int nek_cg_solve(int64_t E, int N, const double *D, const double *g, const nek_g
     const float *dinvc = W.dinv;   // M^-1 in the CG layout, rounded to FP32
 
     // one CG iteration; `first` uses p = b as set by the init kernel.  Small
-    // FP64 meshes take the one-thread-per-node operator (both leave one
-    // partial per element at these degrees)
+    // FP64 meshes take the one-thread-per-node operator, which leaves one
+    // partial of (p, A_L p) per element
     const RedSite red_upd = site(SITE_UPDATE, nullptr, 0);
     const bool node_op = !mixed && ax_node_fused_fits(E, N);
     auto iterate = [&](bool first) -> hipError_t {
@@ -706,7 +706,8 @@ int nek_cg_solve(int64_t E, int N, const double *D, const double *g, const nek_g
                              : (node_op ? launch_ax_node_fused(E, N, D, g, p, w, fz, s)
                                         : launch_ax_f64(E, N, D, g, p, w, fz, s));
         if (e != hipSuccess) return e;
-        return launch_cg_assemble_update(gs->cg, r, w, dinvc, W.axp, ax_blocks(E, N), red_upd, sc, s);
+        return launch_cg_assemble_update(gs->cg, r, w, dinvc, W.axp, node_op ? E : ax_blocks(E, N), red_upd,
+                                         sc, s);
     };
     AxFuse plain_cg;   // A x alone, on CG-layout vectors
     plain_cg.cg_layout = true;

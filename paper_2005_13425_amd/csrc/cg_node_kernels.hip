@@ -7,9 +7,10 @@
 //
 // Same contract as the CG-fused pencil operator: AxFuse with sc, r, x, dinv
 // and partials; the vectors p, r, x, dinv and w in the CG layout, g in the
-// layout of Listing 1.  FP64, n = 8..10 (n^3 <= 1024 threads), one workgroup
-// per element, so the partials of (p, A_L p) land where the pencil kernel
-// puts them (it also runs one element per workgroup at these degrees).
+// layout of Listing 1.  FP64, n = 4..10 (n^3 <= 1024 threads), one workgroup
+// per element, each leaving its element's partial of (p, A_L p): E partials,
+// where the pencil kernel leaves one per workgroup of several elements at
+// n < 8.
 #include "nek_internal.h"
 #include "reduce.h"
 
@@ -118,13 +119,17 @@ hipError_t launch_node(int64_t E, const double *D, const double *g, double *p, d
 }  // namespace
 
 bool ax_node_fused_fits(int64_t E, int N) {
-    return N >= 7 && N <= 9 && E >= 1 && E <= AX_NODE_MAX_POINTS / n3_of(N);
+    return N >= AX_NODE_MIN_N && N <= 9 && E >= 1 && E <= AX_NODE_MAX_POINTS / n3_of(N);
 }
 
 hipError_t launch_ax_node_fused(int64_t E, int N, const double *D, const double *g, double *p, double *w,
                                 const AxFuse &fz, hipStream_t s) {
     if (!ax_node_fused_fits(E, N) || fz.sc == nullptr || !fz.cg_layout) return hipErrorInvalidValue;
     switch (N) {
+    case 3: return launch_node<4>(E, D, g, p, w, fz, s);
+    case 4: return launch_node<5>(E, D, g, p, w, fz, s);
+    case 5: return launch_node<6>(E, D, g, p, w, fz, s);
+    case 6: return launch_node<7>(E, D, g, p, w, fz, s);
     case 7: return launch_node<8>(E, D, g, p, w, fz, s);
     case 8: return launch_node<9>(E, D, g, p, w, fz, s);
     case 9: return launch_node<10>(E, D, g, p, w, fz, s);

@@ -5,6 +5,7 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <algorithm>
 #include <string>
 #include <vector>
 
@@ -99,10 +100,17 @@ hipError_t launch_ax_f32(int64_t E, int N, const float *D32, const void *g_lo, i
                          double *p, double *w, const AxFuse &fz, hipStream_t s);
 // The CG-fused operator with one thread per node, for small meshes
 // (cg_node_kernels.hip): same arguments and results as launch_ax_f64 with a
-// CG AxFuse, for N = 7..9 and at most AX_NODE_MAX_POINTS local points
-// (ax_node_fused_fits).  Measured against the pencil operator (CG iteration
-// time): 5-13% faster up to E = 256 at N = 7, 8, 9 and at E = 512 for N = 7,
-// 8 (262 144 and 373 248 points); 2% slower at E = 512, N = 9 (512 000).
+// CG AxFuse, for N = 3..9 and at most AX_NODE_MAX_POINTS local points
+// (ax_node_fused_fits); it leaves one partial of (p, A_L p) per element.
+// Measured against the pencil operator (CG iteration time): 10-19% faster
+// at E = 64..512 for N = 3..6, 5-13% up to E = 256 at N = 7, 8, 9 and at
+// E = 512 for N = 7, 8 (262 144 and 373 248 points), even near the bound at
+// lower degrees; 2% slower at E = 512, N = 9 (512 000 points).
+#ifdef NEK_AX_NODE_MIN_N
+constexpr int AX_NODE_MIN_N = NEK_AX_NODE_MIN_N;
+#else
+constexpr int AX_NODE_MIN_N = 3;
+#endif
 #ifdef NEK_AX_NODE_MAX_POINTS
 constexpr int64_t AX_NODE_MAX_POINTS = NEK_AX_NODE_MAX_POINTS;
 #else
@@ -313,7 +321,10 @@ inline CgLayout cg_layout(int64_t E, int N, int extra) {
     CgLayout L;
     L.vec = 0;
     L.axp = 3 * vb;
-    L.sites = L.axp + align256((size_t)ax_blocks(E, N) * sizeof(double));
+    // one partial per operator workgroup: ax_blocks, or one per element with
+    // the one-thread-per-node operator
+    const size_t nparts = (size_t)std::max<int64_t>(ax_blocks(E, N), E);
+    L.sites = L.axp + align256(nparts * sizeof(double));
     L.tickets = L.sites + align256(N_SITES * RED_SITE_DOUBLES * sizeof(double));
     L.scalars = L.tickets + align256(N_SITES * RED_TICKETS * sizeof(unsigned int));
     L.scratch = L.scalars + align256(sizeof(CgScalars));

@@ -21,9 +21,9 @@ not:
 * the solution comes back in the layout of Listing 1: x after 0 iterations is
   0, and after one iteration it equals alpha * b exactly as the oracle
   computes it (to rounding);
-* at N = 7 and 8 on E = 1024, above the range of the one-thread-per-node
-  operator that the small meshes here use, the pencil operator: 30
-  iterations within 1e-12 of the oracle.
+* at N = 5 on E = 2048 and N = 7, 8 on E = 1024, above the range of the
+  one-thread-per-node operator that the small meshes here use at N = 3..9,
+  the pencil operator: 30 iterations within 1e-12 of the oracle.
 """
 import dataclasses
 
@@ -85,18 +85,17 @@ def test_cg_every_degree(nek, N):
     assert abs(res.rel_res - ref.res_hist[-1]) <= 1e-9 * ref.res_hist[-1] + 1e-14
 
 
-@pytest.mark.parametrize("N", [7, 8])
-def test_cg_pencil_operator_above_the_node_range(nek, N):
+@pytest.mark.parametrize("N,box", [(5, (16, 16, 8)), (7, (16, 8, 8)), (8, (16, 8, 8))])
+def test_cg_pencil_operator_above_the_node_range(nek, N, box):
     # Up to 400 000 local points the solver runs the operator with one thread
-    # per node at N = 7..9 (the small meshes above); at E = 1024 (524 288 and
-    # 746 496 points) it takes the pencil operator
-    box = (16, 8, 8)
+    # per node at N = 3..9 (the small meshes above); above that (442 368,
+    # 524 288 and 746 496 points here) it takes the pencil operator
     m = _mesh(box, N)
     b = oracle.lattice_to_local(m, synth.lattice_uniform(*box, N))
     x, res = _solve(nek, m, b, 30)
     ref = oracle.cg(m, b, max_iter=30)
     err = _rel(x, ref.x)
-    print(f"CG E=1024 N={N}: rel-L2 {err:.2e}", flush=True)
+    print(f"CG box={box} N={N}: rel-L2 {err:.2e}", flush=True)
     assert res.iters == ref.iters == 30
     assert err <= 1e-12
 
