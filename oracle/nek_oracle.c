@@ -20,9 +20,11 @@
  *                 Jacobian; also the diagonal mass w * det J.
  *   or_box_glonum global node numbering of the box lattice and the Dirichlet
  *                 flags of the domain boundary.
- *   or_ax         Listing 1 literally: three contractions with dxm1, the
- *                 symmetric 3x3 geometric multiply, three contractions with
- *                 dxtm1, per element, no summation across elements.
+ *   or_ax         the local operator of Sec. III (Listing 1) from its
+ *                 definition D^T G D: the reference gradient by three
+ *                 one-dimensional derivatives, the geometric factors applied
+ *                 per point, the transposed derivatives accumulated; per
+ *                 element, no summation across elements.
  *   or_dssum      direct-stiffness summation: the second step of Ax in
  *                 Sec. III (local results are communicated to the elements
  *                 that share the node): every copy of a global node receives
@@ -257,11 +259,41 @@ void or_box_glonum(int Ex, int Ey, int Ez, int N, int64_t *glo, uint8_t *dirichl
     }
 }
 
-/* Listing 1, element by element.  First loop: wr, ws, wt from dxm1, then
- * ur, us, ut from the symmetric geometric factors.  Second loop: w from
- * dxtm1(i,l) = dxm1(l,i).  Loops run i fastest, then j, then k.  Elements
- * are independent, so the element loop may be shared among threads; every
- * element's arithmetic is the same whatever the thread count. */
+/* One-dimensional derivative along direction dir (0: r, index i; 1: s,
+ * index j; 2: t, index k) of an n^3 block f in the layout of Listing 1:
+ *   out(p) = sum over m of M(p_dir, m) f(p with its dir index set to m)
+ * with M = dxm1 (transpose = 0), or M = dxtm1 = dxm1^T (transpose = 1), the
+ * transposed derivative of the weak form.  With accumulate the sum is added
+ * to out(p), else it replaces it. */
+static void derivative_1d(int n, const double *D, int transpose, int dir,
+                          const double *f, double *out, int accumulate)
+{
+    const int64_t stride = dir == 0 ? 1 : (dir == 1 ? n : (int64_t)n * n);
+    const int64_t n3 = (int64_t)n * n * n;
+    for (int64_t p = 0; p < n3; ++p) {
+        int q = (int)((p / stride) % n);            /* index of p along dir */
+        int64_t line = p - (int64_t)q * stride;     /* the point of the line with index 0 */
+        double sum = 0.0;
+        for (int m = 0; m < n; ++m) {
+            /* dxm1(q,m) = D[q + n m]; dxtm1(q,m) = dxm1(m,q) = D[m + n q] */
+            double coef = transpose ? D[m + n * q] : D[q + n * m];
+            sum = sum + coef * f[line + m * stride];
+        }
+        out[p] = accumulate ? out[p] + sum : sum;
+    }
+}
+
+/* The local Poisson operator of Sec. III (Listing 1 is its reference form):
+ * per element, w = sum over a, b of D_a^T G_ab D_b u, where D_a is the
+ * derivative along reference direction a and G is the symmetric 3x3 field
+ * of geometric factors.  Written out from that definition in three passes:
+ *   1. the reference gradient (D_r u, D_s u, D_t u), one derivative at a
+ *      time, into three whole arrays;
+ *   2. the flux G grad u at every point;
+ *   3. w = D_r^T flux_r, then + D_s^T flux_s, then + D_t^T flux_t.
+ * Elements are independent, so the element loop may be shared among
+ * threads; every element's arithmetic is the same whatever the thread
+ * count. */
 void or_ax(int64_t E, int N, const double *D, const double *g,
            const double *u, double *w, int nthreads)
 {
@@ -272,44 +304,35 @@ void or_ax(int64_t E, int N, const double *D, const double *g,
 #pragma omp parallel num_threads(nthreads)
 #endif
     {
-        double *ur = (double *)malloc(sizeof(double) * n3);
-        double *us = (double *)malloc(sizeof(double) * n3);
-        double *ut = (double *)malloc(sizeof(double) * n3);
+        double *grad = (double *)malloc(sizeof(double) * 3 * n3);
+        double *flux = (double *)malloc(sizeof(double) * 3 * n3);
 #ifdef _OPENMP
 #pragma omp for schedule(static)
 #endif
         for (int64_t e = 0; e < E; ++e) {
             const double *ue = u + n3 * e;
-            const double *ge = g + 6 * n3 * e;
+            const double *ge = g + 6 * n3 * e;   /* rr, rs, rt, ss, st, tt */
             double *we = w + n3 * e;
-            for (int k = 0; k < n; ++k)
-            for (int j = 0; j < n; ++j)
-            for (int i = 0; i < n; ++i) {
-                double wr = 0.0, ws = 0.0, wt = 0.0;
-                for (int l = 0; l < n; ++l) {
-                    wr = wr + D[i + n * l] * ue[l + n * (j + n * k)];
-                    ws = ws + D[j + n * l] * ue[i + n * (l + n * k)];
-                    wt = wt + D[k + n * l] * ue[i + n * (j + n * l)];
+            for (int a = 0; a < 3; ++a)
+                derivative_1d(n, D, 0, a, ue, grad + a * n3, 0);
+            for (int64_t p = 0; p < n3; ++p) {
+                double G[3][3];
+                G[0][0] = ge[0 * n3 + p];
+                G[0][1] = G[1][0] = ge[1 * n3 + p];
+                G[0][2] = G[2][0] = ge[2 * n3 + p];
+                G[1][1] = ge[3 * n3 + p];
+                G[1][2] = G[2][1] = ge[4 * n3 + p];
+                G[2][2] = ge[5 * n3 + p];
+                for (int a = 0; a < 3; ++a) {
+                    double f = 0.0;
+                    for (int b = 0; b < 3; ++b) f = f + G[a][b] * grad[b * n3 + p];
+                    flux[a * n3 + p] = f;
                 }
-                int64_t p = i + n * (j + n * k);
-                ur[p] = ge[0 * n3 + p] * wr + ge[1 * n3 + p] * ws + ge[2 * n3 + p] * wt;
-                us[p] = ge[1 * n3 + p] * wr + ge[3 * n3 + p] * ws + ge[4 * n3 + p] * wt;
-                ut[p] = ge[2 * n3 + p] * wr + ge[4 * n3 + p] * ws + ge[5 * n3 + p] * wt;
             }
-            for (int k = 0; k < n; ++k)
-            for (int j = 0; j < n; ++j)
-            for (int i = 0; i < n; ++i) {
-                double acc = 0.0;
-                for (int l = 0; l < n; ++l) {
-                    /* dxtm1(i,l) = dxm1(l,i) = D[l + n*i] */
-                    acc = acc + D[l + n * i] * ur[l + n * (j + n * k)]
-                              + D[l + n * j] * us[i + n * (l + n * k)]
-                              + D[l + n * k] * ut[i + n * (j + n * l)];
-                }
-                we[i + n * (j + n * k)] = acc;
-            }
+            for (int a = 0; a < 3; ++a)
+                derivative_1d(n, D, 1, a, flux + a * n3, we, a > 0);
         }
-        free(ur); free(us); free(ut);
+        free(grad); free(flux);
     }
 }
 
