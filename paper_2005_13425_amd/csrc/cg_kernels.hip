@@ -413,9 +413,14 @@ __device__ __forceinline__ void assemble_update_body(int lb, int nb, int64_t P, 
     // partials loaded per thread at once (all of them up to E = 4096 at N = 9;
     // fewer with a preconditioner, whose chunk holds dinv too)
     constexpr int PPT = PRE ? 8 : 16;
-    // a launch queued after the solve finished exits before its first store;
-    // the flag is tested once the loads below are in flight
-    const int done = sc->done;
+    // A launch queued after the solve finished exits before its second round
+    // of loads.  Thread 0 alone reads the flag, with the first loads in
+    // flight, and passes it on through LDS: every wave of a workgroup takes
+    // the same decision even when workgroup 0 of this launch flags a
+    // breakdown meanwhile (every workgroup then finds the same breakdown
+    // from the same partials).
+    __shared__ int done_s;
+    if (threadIdx.x == 0) done_s = sc->done;
     __shared__ double lds[VEC_THREADS / 64];
     __shared__ double alpha_s;
     __shared__ int breakdown;
@@ -452,7 +457,8 @@ __device__ __forceinline__ void assemble_update_body(int lb, int nb, int64_t P, 
     if (vbl[1] >= 0) row_setup(a, vbl[1], J1);
     PairChunk<PRE> Q;
     chunk_bits<PRE>(base0, npairs, rowed, Q);
-    if (done) return;
+    __syncthreads();
+    if (done_s) return;
 
     // ---- 2. loads selected by the indices and bits
     row_load<PRE>(J0, w, r, dinv);
