@@ -168,30 +168,24 @@ def main():
     ax_flops = (12 * n + 15) * P
     ax_gbs = ax_bytes / (ax_us_cold * 1e-6) / 1e9
 
-    # ---------------- measured roofline at the same footprint (the method of Sec. V):
-    # a streaming kernel with the operator's 7:1 read:write mix, and a copy,
-    # rotating two buffer sets (cold) like the operator timing above; each with
-    # plain and with non-temporal loads and stores, the better one counting
-    def probe(nread, streaming, reps=40):
-        srcs = [torch.empty(nread * P, dtype=torch.float64, device=dev).uniform_() for _ in range(2)]
-        dsts = [torch.empty(P, dtype=torch.float64, device=dev) for _ in range(2)]
-        ptrs = [(ctypes.c_void_p(srcs[q].data_ptr()), ctypes.c_void_p(dsts[q].data_ptr())) for q in range(2)]
-        pr = nek._lib.nek_bw_probe
-        for q in range(2):
-            pr(P, nread, ptrs[q][0], ptrs[q][1], 0, streaming, sp)
-        torch.cuda.synchronize()
-        a0.record(stream)
-        for r in range(reps):
-            pr(P, nread, ptrs[r % 2][0], ptrs[r % 2][1], 0, streaming, sp)
-        a1.record(stream)
-        torch.cuda.synchronize()
-        us_ = 1e3 * a0.elapsed_time(a1) / reps
-        return (nread + 1) * 8 * P / (us_ * 1e-6) / 1e9, us_
-    stream7_plain, _ = probe(7, 0)
-    stream7_nt, _ = probe(7, 1)
-    stream7_gbs = max(stream7_plain, stream7_nt)
-    copy_gbs = max(probe(1, 0)[0], probe(1, 1)[0])
+    # ---------------- measured roofline at the same footprint (the method of Sec. V)
+    probes = probe_sweep(nek, torch, dev, stream, P)
+    stream7_gbs = probes["best_7r1w_gbs"]
+    copy_gbs = probes["best_copy_gbs"]
     memcpy_gbs = memcpy_rate(torch, dev, stream)
+    # the ceiling the operator is graded against: the best rate anything in
+    # this run reached at this footprint (the probes, or the operator itself
+    # if it outruns them)
+    meas_roof = max(stream7_gbs, probes["best_read_only_gbs"], copy_gbs, ax_gbs)
+
+    # the CG step's own bytes: the fused operator moves 96 B per point (p, r,
+    # x and g in; p, x and w out), the assemble-update 24 B per single-copy
+    # point, 20 B per copy of a shared node plus 8 B per node (r in) and one
+    # bit per point
+    n_unique, n_rows, n_entries, n_masked = gs.info()
+    n_zero = int(dirichlet.sum())
+    asm_bytes = 24 * (P - n_entries - n_zero) + 20 * n_entries + 8 * n_rows + P // 8
+    cg_bytes_iter = 96 * P + asm_bytes
 
     out = {
         "metric": "ax_e GFLOP/s + % HBM roofline at E=4096 N=9; CG solves/s, p50/p99 latency",
@@ -224,17 +218,18 @@ def main():
                  "us_per_call_cold_p90": round(float(np.percentile(ax_per, 90)), 2),
                  "gbs_cold": round(ax_gbs, 1),
                  "gbs_warm": round(ax_bytes / (ax_us_warm * 1e-6) / 1e9, 1),
-                 "measured_roofline_gbs": round(stream7_gbs, 1),
-                 "frac_of_measured_roofline": round(ax_gbs / stream7_gbs, 4),
+                 "measured_roofline_gbs": round(meas_roof, 1),
+                 "frac_of_measured_roofline": round(ax_gbs / meas_roof, 4),
+                 "frac_of_best_7r1w_probe": round(ax_gbs / stream7_gbs, 4),
                  "flops_per_point": 12 * n + 15, "bytes_per_point": 64},
         "cg": {"ms_per_solve": round(cg_ms, 4), "solves_per_s": round(1e3 / ms_per_step, 3),
                "us_per_iter": round(1e3 * cg_ms / iters, 2),
-               "paper_model_gbs": round(iters * P * 240 / (ms_per_step * 1e-3) / 1e9, 1),
+               "fused_algorithmic_bytes_per_iter": cg_bytes_iter,
+               "fused_algorithmic_gbs": round(iters * cg_bytes_iter / (ms_per_step * 1e-3) / 1e9, 1),
+               "fused_frac_of_hbm_peak": round(iters * cg_bytes_iter / (ms_per_step * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+               "paper_model_bytes_per_iter": 240 * P,
                "final_rel_res": last.rel_res if last else None},
-        "measured_stream7_gbs": round(stream7_gbs, 1),
-        "measured_stream7_plain_gbs": round(stream7_plain, 1),
-        "measured_stream7_nontemporal_gbs": round(stream7_nt, 1),
-        "measured_copy_gbs": round(copy_gbs, 1),
+        "probes": probes,
         "measured_memcpy_dtod_gbs": round(memcpy_gbs, 1),
     }
     del us, gsets, wsets
@@ -444,6 +439,66 @@ def memcpy_rate(torch, dev, stream, nbytes=1 << 30, reps=20):
     return 2 * nbytes * reps / t / 1e9
 
 
+def staggered_stride(n):
+    """A stream stride of at least n doubles that is an odd multiple of 256
+    bytes, so that the streams do not sit a large power of two apart."""
+    s = (n + 31) // 32 * 32
+    if (s // 32) % 2 == 0:
+        s += 32
+    return s
+
+
+def probe_rate(nek, torch, dev, stream, n, nread, stride, grid, streaming, read_only, reps=40):
+    """HBM rate of one probe shape: two buffer sets rotating (cold), `reps`
+    launches between HIP events on the launch stream; bytes read + written."""
+    import ctypes
+    sp = ctypes.c_void_p(stream.cuda_stream)
+    flags = (nek.NEK_PROBE_NT if streaming else 0) | (nek.NEK_PROBE_READ_ONLY if read_only else 0)
+    srcs = [torch.empty((nread - 1) * stride + n, dtype=torch.float64, device=dev).uniform_() for _ in range(2)]
+    dsts = [torch.empty(n, dtype=torch.float64, device=dev) for _ in range(2)]
+    ptrs = [(ctypes.c_void_p(srcs[q].data_ptr()), ctypes.c_void_p(dsts[q].data_ptr())) for q in range(2)]
+    pr = nek._lib.nek_bw_probe
+    for q in range(2):
+        assert pr(n, nread, ptrs[q][0], stride, ptrs[q][1], grid, flags, sp) == 0
+    a0, a1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    a0.record(stream)
+    for r in range(reps):
+        pr(n, nread, ptrs[r % 2][0], stride, ptrs[r % 2][1], grid, flags, sp)
+    a1.record(stream)
+    torch.cuda.synchronize()
+    us = 1e3 * a0.elapsed_time(a1) / reps
+    nbytes = (nread + (0 if read_only else 1)) * 8 * (n - (n & 1))
+    del srcs, dsts
+    return nbytes / (us * 1e-6) / 1e9
+
+
+def probe_sweep(nek, torch, dev, stream, n, grids=(0, 1024, 2048, 4096, 8192)):
+    """The probes at one footprint: 7 read streams + 1 write stream (the
+    operator's mix), 7 read streams alone, and a copy; plain and non-temporal;
+    streams a power of two apart (aliased) and staggered; one pass or a
+    capped grid striding over the data.  Every rate and the best of each kind."""
+    st = staggered_stride(n)
+    rows = []
+    for nread, ro in ((7, False), (7, True), (1, False)):
+        for streaming in (False, True):
+            for stride, sname in ((n, "aliased"), (st, "staggered")):
+                if nread == 1 and sname == "staggered":
+                    continue
+                for grid in grids:
+                    rows.append({"reads": nread, "write": not ro, "nontemporal": streaming, "streams": sname,
+                                 "grid": grid or "one pass",
+                                 "gbs": round(probe_rate(nek, torch, dev, stream, n, nread, stride, grid,
+                                                         streaming, ro), 1)})
+    torch.cuda.empty_cache()
+    best = lambda f: max((r for r in rows if f(r)), key=lambda r: r["gbs"])
+    b7 = best(lambda r: r["reads"] == 7 and r["write"])
+    bro = best(lambda r: r["reads"] == 7 and not r["write"])
+    bc = best(lambda r: r["reads"] == 1)
+    return {"points": n, "best_7r1w_gbs": b7["gbs"], "best_7r1w": b7, "best_read_only_gbs": bro["gbs"],
+            "best_read_only": bro, "best_copy_gbs": bc["gbs"], "best_copy": bc, "all": rows}
+
+
 def sweep_leg(nek, torch, dev, stream, reps=20):
     """ax_e alone over the degree sweep N = 5..15: per N a box of about 32.8 M
     local points (u + g + w about 2.1 GB, far above the 256 MB last-level
@@ -477,18 +532,8 @@ def sweep_leg(nek, torch, dev, stream, reps=20):
         torch.cuda.synchronize()
         per = np.array([1e3 * evs[r].elapsed_time(evs[r + 1]) for r in range(reps)])
         del g, u, w
-        src = torch.empty(7 * P, dtype=torch.float64, device=dev).uniform_()
-        dst = torch.empty(P, dtype=torch.float64, device=dev)
-        probe_gbs = 0.0
-        for streaming in (0, 1):      # plain and non-temporal, the better one counting
-            nek._lib.nek_bw_probe(P, 7, vp(src), vp(dst), 0, streaming, sp)
-            evs[0].record(stream)
-            for r in range(reps):
-                nek._lib.nek_bw_probe(P, 7, vp(src), vp(dst), 0, streaming, sp)
-            evs[1].record(stream)
-            torch.cuda.synchronize()
-            probe_gbs = max(probe_gbs, 64 * P * reps / (1e-3 * evs[0].elapsed_time(evs[1])) / 1e9)
-        del src, dst
+        probe_gbs = max(probe_rate(nek, torch, dev, stream, P, 7, stride, 0, streaming, False, reps)
+                        for streaming in (False, True) for stride in (P, staggered_stride(P)))
         torch.cuda.empty_cache()
         t = float(per.mean()) * 1e-6
         gbs = 64 * P / t / 1e9
@@ -498,8 +543,14 @@ def sweep_leg(nek, torch, dev, stream, reps=20):
                        "us_p90": round(float(np.percentile(per, 90)), 2),
                        "gbs": round(gbs, 1), "gflops": round((12 * n + 15) * P / t / 1e9, 1),
                        "frac_of_hbm_peak": round(gbs / HBM_PEAK_GBS, 4),
-                       "measured_stream7_gbs": round(probe_gbs, 1),
-                       "frac_of_measured_roofline": round(gbs / probe_gbs, 4)}
+                       "best_7r1w_probe_gbs": round(probe_gbs, 1),
+                       "frac_of_7r1w_probe": round(gbs / probe_gbs, 4)}
+    # the measured roofline of the sweep: the best rate anything reached at
+    # these footprints, a probe or the operator at some degree
+    roof = max(max(v["best_7r1w_probe_gbs"], v["gbs"]) for v in out.values())
+    for v in out.values():
+        v["frac_of_measured_roofline"] = round(v["gbs"] / roof, 4)
+    out["measured_roofline_gbs"] = round(roof, 1)
     return out
 
 
@@ -660,14 +711,60 @@ def traffic_bytes(N, E):
     return float(m_b.group(1))
 
 
+def cpu_model():
+    """Model name of the host CPU (/proc/cpuinfo), its logical CPUs and the
+    ones this process may run on."""
+    name = "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    name = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return {"model": name, "logical_cpus": os.cpu_count(), "usable_cpus": len(os.sched_getaffinity(0))}
+
+
 def cpu_baseline(Ex, Ey, Ez, N, budget_s):
-    """The FP64 oracle, as it stands, on this host: CG iterations on the same
-    workload shape, as many as fit in about budget_s seconds (at least 1)."""
+    """The FP64 oracle, as it stands, on this host, compiled here with
+    -O3 -march=native -fopenmp (oracle.TIMED_FLAGS; the same results as the
+    test build):
+    * ax_e alone (Listing 1, OpenMP over elements) on the paper's boxes
+      E = 1024, 2048, 4096 at this degree, median of 10 calls;
+    * the 100-iteration CG step of the GPU leg on the same mesh, whole solves
+      repeated for about budget_s seconds, counted with eq. (1) like `value`;
+    * the same CG on one thread, 30 iterations."""
+    import tempfile
+
     import numpy as np
 
     import oracle
     import synth
-    mesh = oracle.box_mesh(Ex, Ey, Ez, N, synth.AMP, synth.geom_coeffs())
+    lib_path = oracle.use_timed_build(tempfile.mkdtemp(prefix="nek_oracle_"))
+    n = N + 1
+    threads = oracle.max_threads()
+    ax_rows = {}
+    mesh = None
+    for box in ((16, 8, 8), (16, 16, 8), (16, 16, 16)):
+        E = box[0] * box[1] * box[2]
+        m = oracle.box_mesh(*box, N, synth.AMP, synth.geom_coeffs())
+        u = synth.local_uniform(m.P)
+        oracle.ax(E, N, m.D, m.g, u)
+        ts = []
+        for _ in range(10):
+            t0 = time.perf_counter()
+            oracle.ax(E, N, m.D, m.g, u)
+            ts.append(time.perf_counter() - t0)
+        t = float(np.median(ts))
+        ax_rows[str(E)] = {"box": list(box), "ms_median": round(1e3 * t, 3),
+                           "gflops": round((12 * n + 15) * m.P / t / 1e9, 2),
+                           "gbs": round(64 * m.P / t / 1e9, 2)}
+        if box == (Ex, Ey, Ez):
+            mesh = m
+        del u
+    if mesh is None:
+        mesh = oracle.box_mesh(Ex, Ey, Ez, N, synth.AMP, synth.geom_coeffs())
     b = oracle.lattice_to_local(mesh, synth.lattice_uniform(Ex, Ey, Ez, N))
     # whole 100-iteration solves (the timed step of the GPU leg), repeated while
     # the budget lasts
@@ -680,20 +777,21 @@ def cpu_baseline(Ex, Ey, Ez, N, budget_s):
         if time.perf_counter() - t0 >= budget_s:
             break
     dt = time.perf_counter() - t0
-    n = N + 1
     gflops = k * mesh.P * (12 * n + 34) / dt / 1e9
-    # the same on one core, over fewer iterations
-    k1 = 10
+    k1 = 30
     t1 = time.perf_counter()
     oracle.cg(mesh, b, max_iter=k1, nthreads=1)
     dt1 = time.perf_counter() - t1
-    return {"value": round(gflops, 3), "unit": "GFLOP/s", "cores": oracle.max_threads(),
+    return {"value": round(gflops, 3), "unit": "GFLOP/s", "cores": threads,
+            "cpu": cpu_model(),
+            "build": "gcc " + " ".join(oracle.TIMED_FLAGS) + " (" + os.path.basename(lib_path) + ")",
+            "ax_e_alone": ax_rows,
             "single_core_value": round(k1 * mesh.P * (12 * n + 34) / dt1 / 1e9, 3),
             "single_core_sample": f"{k1} FP64 CG iterations of the oracle on one thread ({dt1:.1f} s)",
             "kind": "oracle",
             "sample": f"{solves} x 100 FP64 CG iterations of the oracle on the same E={mesh.E} N={N} "
-                      f"mesh ({dt:.1f} s; OpenMP threads over elements in the local operator, the rest "
-                      "serial); counted with eq. (1) like the GPU value"}
+                      f"mesh ({dt:.1f} s; {threads} OpenMP threads over elements in the local operator, "
+                      "the rest serial); counted with eq. (1) like the GPU value"}
 
 
 if __name__ == "__main__":

@@ -262,33 +262,52 @@ int nek_jacobi_inverse(int64_t E, int N, const double *D, const double *g, const
 
 /* ------------------------------------------------------------ served solves */
 
-/* A solve service: requests (box meshes of any size and degree) arrive over
- * time; each is admitted when its whole device footprint fits in the HBM
- * budget, its CG state then stays resident, and every server step advances
- * all admitted solves by CG iterations in shared launches (one operator
- * and one assemble-update launch per (degree, precision, size) group).
- * Each solve's arithmetic is the same as when it runs alone.  The method is
- * the one of nek_cg_solve (Sec. III, Sec. V); the service around it is not
- * in the paper. */
+/* A solve service: requests (meshes of any size and degree: a box the
+ * server builds, or the caller's own arrays) arrive over time; each is
+ * admitted when its whole device footprint fits in the HBM budget, its CG
+ * state then stays resident, and every server step advances all admitted
+ * solves by CG iterations in shared launches (one operator and one
+ * assemble-update launch per (degree, precision, size) group).  Each solve's
+ * arithmetic is the same as when it runs alone.  The method is the one of
+ * nek_cg_solve (Sec. III, Sec. V); the service around it is not in the
+ * paper. */
 
 typedef struct nek_server nek_server;
+
+#define NEK_MEM_HOST   0
+#define NEK_MEM_DEVICE 1
 
 typedef struct {
     int Ex, Ey, Ez, N;   /* box of Ex x Ey x Ez elements of degree N (geometry as
                             in nek_box_geometry, numbering and Dirichlet faces as in
-                            nek_box_numbering); built on the device at admission */
-    double amp;          /* displacement amplitude */
-    double a[3];         /* displacement coefficients */
-    const double *b;     /* host, P doubles, local layout, continuous and zero on
-                            the box faces.  Read by a preparation thread after
-                            nek_server_submit returns: it must stay valid and
-                            unchanged until nek_server_poll has reported the
-                            request or nek_server_destroy has returned */
+                            nek_box_numbering), built on the device at admission;
+                            only N is used when the request carries its own mesh */
+    double amp;          /* displacement amplitude (box only) */
+    double a[3];         /* displacement coefficients (box only) */
+    const double *b;     /* P doubles, local layout, continuous and zero at the
+                            Dirichlet nodes (host or device, see mem) */
     int precision;       /* NEK_PREC_* */
     double rel_tol;      /* stop at ||r||/||b|| <= rel_tol (true residual in the
                             mixed precisions); <= 0: run max_iter iterations */
     int max_iter;
+    /* The caller's own mesh (Listing 1 layouts, as nek_cg_solve takes them):
+     * set g, D and glo (dirichlet may be NULL: no Dirichlet node) and E; the
+     * box fields Ex, Ey, Ez, amp and a are then ignored.  g == NULL: the box. */
+    int64_t E;                 /* elements */
+    const double *D;           /* dxm1, (N+1)^2 doubles */
+    const double *g;           /* 6 P doubles, gxyz layout */
+    const int64_t *glo;        /* P global ids (as nek_gs_create) */
+    const uint8_t *dirichlet;  /* P flags (as nek_gs_create), or NULL */
+    int mem;                   /* NEK_MEM_HOST or NEK_MEM_DEVICE: where b and, with a
+                                  mesh of the caller's, D, g, glo and dirichlet live
+                                  (device memory of the server's device, 8-byte
+                                  aligned) */
 } nek_request;
+/* Lifetime of the request's arrays: they are read after nek_server_submit
+ * returns (numbering and gather-scatter tables by a preparation thread, b and
+ * g copied into the server's own device memory at admission), so they must
+ * stay valid and unchanged until nek_server_poll has reported the request or
+ * nek_server_destroy has returned. */
 
 typedef struct {
     uint64_t id;
@@ -315,12 +334,15 @@ typedef struct {
 int nek_server_create(size_t hbm_budget, nek_server **out);
 
 /* Queue a request; *id receives its id.  NEK_ERR_NOMEM if its footprint can
- * never fit the budget.  Copies *req but not the rhs req->b (see
- * nek_request.b).  Returns at once. */
+ * never fit the budget.  Copies *req but not the arrays it points to (see
+ * their lifetime above).  Returns at once. */
 int nek_server_submit(nek_server *srv, const nek_request *req, uint64_t *id);
 
-/* Footprint in device bytes of a request (what admission charges). */
+/* Footprint in device bytes of a request (what admission charges): of a box
+ * request, and of a request of E elements of degree N with its own mesh (the
+ * same bytes for the same E and N). */
 size_t nek_server_footprint(int Ex, int Ey, int Ez, int N, int precision);
+size_t nek_server_footprint_mesh(int64_t E, int N, int precision);
 
 /* One step: admit prepared requests in arrival order while they fit (a
  * request still being prepared does not hold back prepared ones behind it; a
@@ -352,17 +374,30 @@ int nek_server_destroy(nek_server *srv);
 /* ------------------------------------------------------------ measurement */
 
 /* Streaming bandwidth probe for the measured roofline (Sec. V: the
- * computation replaced by copies of every load and store).  Computes
- * dst[i] = sum_{k < nread} src[k*n + i] for i < n: nread coalesced read
- * streams and one write stream of n doubles.  nread in 1..8 (1 = copy,
- * 7 = the 7:1 read:write mix of the FP64 local operator).  src: device,
- * nread*n doubles, 16-byte aligned; dst: device, n doubles, 16-byte aligned,
- * not overlapping src.  grid_cap > 0 caps the number of workgroups (0: one
- * pass).  streaming != 0: the loads and stores carry the non-temporal hint (as
- * the plain FP64 operator's do from N = 7 up); the measured roofline is the
- * better of the two.  Allocates nothing.  Asynchronous. */
-int nek_bw_probe(int64_t n, int nread, const double *src, double *dst, int grid_cap, int streaming,
-                 void *stream);
+ * computation replaced by copies of every load and store).  nread coalesced
+ * read streams of n doubles, stream k at src + k * src_stride:
+ *   flags without NEK_PROBE_READ_ONLY: dst[i] = sum_{k < nread} stream_k[i]
+ *     for i < n, one write stream of n doubles (nread = 1 is a copy, 7 the
+ *     7:1 read:write mix of the FP64 local operator);
+ *   NEK_PROBE_READ_ONLY: only the reads reach HBM; dst receives one partial
+ *     sum per workgroup, nek_bw_probe_groups(n, grid_cap) doubles (the sum
+ *     leaves out the last value when n is odd).
+ *   NEK_PROBE_NT: the loads and stores carry the non-temporal hint (as the
+ *     plain FP64 operator's do from N = 7 up).
+ * src_stride (doubles, even, >= n) lets the caller stagger the streams so
+ * that they do not sit a large power of two apart.  grid_cap > 0 caps the
+ * number of workgroups, which then stride over the streams (0: one pass).
+ * src: device, (nread-1)*src_stride + n doubles, 16-byte aligned; dst:
+ * device, 16-byte aligned, not overlapping src.  n >= 2.  Allocates nothing.
+ * Asynchronous. */
+#define NEK_PROBE_NT        1
+#define NEK_PROBE_READ_ONLY 2
+int nek_bw_probe(int64_t n, int nread, const double *src, int64_t src_stride, double *dst, int grid_cap,
+                 int flags, void *stream);
+
+/* Workgroups of a probe launch over n doubles with that grid cap (the
+ * number of partials NEK_PROBE_READ_ONLY writes); 0 for invalid arguments. */
+int64_t nek_bw_probe_groups(int64_t n, int grid_cap);
 
 #ifdef __cplusplus
 }

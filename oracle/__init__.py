@@ -48,13 +48,35 @@ def build(force: bool = True) -> str:
     return _LIB
 
 
+TIMED_FLAGS = ["-std=c11", "-O3", "-march=native", "-fopenmp"]
+
+
+def use_timed_build(directory: str) -> str:
+    """Compile the same source with TIMED_FLAGS for the host that runs it
+    (-march=native, so it is built where it runs, into `directory`) and make
+    every later call of this module use that build.  ISO C11 keeps gcc from
+    contracting a*b+c into fused multiply-adds and the source has no
+    reassociation, so the results are those of the default build."""
+    global _lib
+    os.makedirs(directory, exist_ok=True)
+    path = os.path.join(directory, "libnek_oracle_timed.so")
+    subprocess.run(["gcc", *TIMED_FLAGS, "-fPIC", "-shared", "-o", path, _SRC, "-lm"], check=True)
+    _lib = _bind(path)
+    return path
+
+
 def _load():
     global _lib
     if _lib is not None:
         return _lib
     if not os.path.exists(_LIB):
         build(force=True)
-    lib = ctypes.CDLL(_LIB)
+    _lib = _bind(_LIB)
+    return _lib
+
+
+def _bind(path):
+    lib = ctypes.CDLL(path)
     dp = ctypes.POINTER(ctypes.c_double)
     i64p = ctypes.POINTER(ctypes.c_int64)
     u8p = ctypes.POINTER(ctypes.c_uint8)
@@ -88,7 +110,6 @@ def _load():
     lib.or_pcg.restype = ci
     lib.or_max_threads.argtypes = []
     lib.or_max_threads.restype = ci
-    _lib = lib
     return lib
 
 

@@ -46,6 +46,8 @@ NEK_AX_PENCIL = 0
 NEK_AX_ORIGINAL = 1
 NEK_AX_SHARED3D = 2
 NEK_AX_LAYER2D = 3
+NEK_MEM_HOST = 0
+NEK_MEM_DEVICE = 1
 
 _vp = ctypes.c_void_p
 _i64 = ctypes.c_int64
@@ -69,7 +71,9 @@ class CgStats(ctypes.Structure):
 class Request(ctypes.Structure):
     _fields_ = [("Ex", ctypes.c_int), ("Ey", ctypes.c_int), ("Ez", ctypes.c_int), ("N", ctypes.c_int),
                 ("amp", ctypes.c_double), ("a", ctypes.c_double * 3), ("b", _vp),
-                ("precision", ctypes.c_int), ("rel_tol", ctypes.c_double), ("max_iter", ctypes.c_int)]
+                ("precision", ctypes.c_int), ("rel_tol", ctypes.c_double), ("max_iter", ctypes.c_int),
+                ("E", ctypes.c_int64), ("D", _vp), ("g", _vp), ("glo", _vp), ("dirichlet", _vp),
+                ("mem", ctypes.c_int)]
 
 
 class Result(ctypes.Structure):
@@ -102,11 +106,13 @@ _sig("nek_gs_destroy", _ci, [_vp])
 _sig("nek_gs_info", _ci, [_vp] + [ctypes.POINTER(_i64)] * 4)
 _sig("nek_dssum", _ci, [_vp, _vp, _vp])
 _sig("nek_gs_dot", _ci, [_vp, _vp, _vp, _vp, _vp])
-_sig("nek_bw_probe", _ci, [_i64, _ci, _vp, _vp, _ci, _ci, _vp])
+_sig("nek_bw_probe", _ci, [_i64, _ci, _vp, _i64, _vp, _ci, _ci, _vp])
+_sig("nek_bw_probe_groups", _i64, [_i64, _ci])
 _sig("nek_jacobi_inverse", _ci, [_i64, _ci, _vp, _vp, _vp, _vp, _vp])
 _sig("nek_server_create", _ci, [ctypes.c_size_t, ctypes.POINTER(_vp)])
 _sig("nek_server_submit", _ci, [_vp, ctypes.POINTER(Request), ctypes.POINTER(ctypes.c_uint64)])
 _sig("nek_server_footprint", ctypes.c_size_t, [_ci, _ci, _ci, _ci, _ci])
+_sig("nek_server_footprint_mesh", ctypes.c_size_t, [_i64, _ci, _ci])
 _sig("nek_server_step", _ci, [_vp, _ci, ctypes.POINTER(_ci), ctypes.POINTER(_ci)])
 _sig("nek_server_poll", _ci, [_vp, ctypes.POINTER(Result), _ci, ctypes.POINTER(_ci)])
 _sig("nek_server_fetch", _ci, [_vp, ctypes.c_uint64, _vp])
@@ -267,16 +273,34 @@ def ax_f32(u, D32, g_lo, g_dtype: int, N: int, out=None, stream=None):
     return out
 
 
-def bw_probe(src, dst, nread: int, grid_cap: int = 0, streaming: bool = False, stream=None):
-    """dst[i] = sum_k src[k*n + i] (nread read streams, one write stream);
+NEK_PROBE_NT = 1
+NEK_PROBE_READ_ONLY = 2
+
+
+def bw_probe(src, dst, nread: int, n: int | None = None, stride: int | None = None, grid_cap: int = 0,
+             streaming: bool = False, read_only: bool = False, stream=None):
+    """nread read streams of n doubles, stream k at src[k*stride:]; without
+    read_only dst[i] = sum_k stream_k[i] (n doubles), with read_only dst gets
+    one partial per workgroup (bw_probe_groups(n, grid_cap) doubles).
     streaming: non-temporal loads and stores."""
     torch = _torch()
-    n = dst.numel()
-    _check(_lib.nek_bw_probe(n, int(nread), _dev(src, torch.float64, "src", nread * n),
-                             _dev(dst, torch.float64, "dst", n), int(grid_cap), 1 if streaming else 0,
-                             _stream_ptr(stream)),
+    if n is None:
+        n = dst.numel()
+    stride = n if stride is None else int(stride)
+    ndst = bw_probe_groups(n, grid_cap) if read_only else n
+    if src.numel() < (nread - 1) * stride + n:
+        raise ValueError("src is shorter than its streams")
+    if dst.numel() < ndst:
+        raise ValueError(f"dst must hold {ndst} doubles")
+    flags = (NEK_PROBE_NT if streaming else 0) | (NEK_PROBE_READ_ONLY if read_only else 0)
+    _check(_lib.nek_bw_probe(int(n), int(nread), _dev(src, torch.float64, "src"), stride,
+                             _dev(dst, torch.float64, "dst"), int(grid_cap), flags, _stream_ptr(stream)),
            "nek_bw_probe")
     return dst
+
+
+def bw_probe_groups(n: int, grid_cap: int = 0) -> int:
+    return int(_lib.nek_bw_probe_groups(int(n), int(grid_cap)))
 
 
 # ------------------------------------------------------------------ gather-scatter
@@ -343,15 +367,8 @@ def cg_workspace_bytes(E: int, N: int) -> int:
     return int(_lib.nek_cg_workspace_bytes(E, N))
 
 
-def cg_solve(D, g, gs: GatherScatter, b, x=None, max_iter: int = 100, rel_tol: float = 0.0,
-             precision: int = NEK_PREC_F64, D32=None, g_lo=None, check_every: int = 0,
-             true_residual: bool = False, reliable_drop: float = 0.0, workspace=None,
-             raise_on_error: bool = True, stream=None, dinv=None):
-    """CG on mask(dssum(A_L x)) = b with x_0 = 0, on the device; with dinv (from
-    jacobi_inverse) Jacobi-preconditioned CG.
-
-    Returns (x, CgResult).  With raise_on_error=False a breakdown or
-    non-convergence is reported in CgResult.status instead of raising."""
+def _cg_call(fn, name, D, g, gs, b, x, max_iter, rel_tol, precision, D32, g_lo, check_every, true_residual,
+             reliable_drop, workspace, raise_on_error, stream, dinv):
     torch = _torch()
     E, N = gs.E, gs.N
     P = gs.P
@@ -377,13 +394,26 @@ def cg_solve(D, g, gs: GatherScatter, b, x=None, max_iter: int = 100, rel_tol: f
         o.workspace = ctypes.c_void_p(workspace.data_ptr())
         o.workspace_bytes = workspace.numel() * workspace.element_size()
     st = CgStats()
-    rc = _lib.nek_cg_solve(E, N, _dev(D, torch.float64, "D", (N + 1) ** 2), _dev(g, torch.float64, "g", 6 * P),
-                           gs.handle, _dev(b, torch.float64, "b", P), _dev(x, torch.float64, "x", P),
-                           ctypes.byref(o), ctypes.byref(st), _stream_ptr(stream))
+    rc = fn(E, N, _dev(D, torch.float64, "D", (N + 1) ** 2), _dev(g, torch.float64, "g", 6 * P),
+            gs.handle, _dev(b, torch.float64, "b", P), _dev(x, torch.float64, "x", P),
+            ctypes.byref(o), ctypes.byref(st), _stream_ptr(stream))
     res = CgResult(st.iters, st.status, st.rel_res, st.rel_res_true, st.n_replacements)
     if rc != NEK_OK and (raise_on_error or rc not in (NEK_ERR_BREAKDOWN, NEK_ERR_NOCONV)):
-        raise NekError(rc, "nek_cg_solve")
+        raise NekError(rc, name)
     return x, res
+
+
+def cg_solve(D, g, gs: GatherScatter, b, x=None, max_iter: int = 100, rel_tol: float = 0.0,
+             precision: int = NEK_PREC_F64, D32=None, g_lo=None, check_every: int = 0,
+             true_residual: bool = False, reliable_drop: float = 0.0, workspace=None,
+             raise_on_error: bool = True, stream=None, dinv=None):
+    """CG on mask(dssum(A_L x)) = b with x_0 = 0, on the device; with dinv (from
+    jacobi_inverse) Jacobi-preconditioned CG.
+
+    Returns (x, CgResult).  With raise_on_error=False a breakdown or
+    non-convergence is reported in CgResult.status instead of raising."""
+    return _cg_call(_lib.nek_cg_solve, "nek_cg_solve", D, g, gs, b, x, max_iter, rel_tol, precision, D32, g_lo,
+                    check_every, true_residual, reliable_drop, workspace, raise_on_error, stream, dinv)
 
 
 def jacobi_inverse(D, g, gs: GatherScatter, out=None, stream=None):
@@ -412,6 +442,10 @@ def server_footprint(Ex: int, Ey: int, Ez: int, N: int, precision: int = NEK_PRE
     return int(_lib.nek_server_footprint(Ex, Ey, Ez, N, precision))
 
 
+def server_footprint_mesh(E: int, N: int, precision: int = NEK_PREC_F64) -> int:
+    return int(_lib.nek_server_footprint_mesh(int(E), N, precision))
+
+
 class Server:
     """Served Poisson solves on the device (nek_server_*): submit box-mesh
     requests as they arrive, call step() to admit and advance them, poll()
@@ -437,6 +471,38 @@ class Server:
         _check(_lib.nek_server_submit(self._h, ctypes.byref(r), ctypes.byref(rid)), "nek_server_submit")
         self._sizes[rid.value] = P
         self._rhs[rid.value] = b          # read by the server until the result is reported
+        return rid.value
+
+    def submit_mesh(self, E, N, D, g, glo, dirichlet, b, precision=NEK_PREC_F64, rel_tol=1e-10,
+                    max_iter=10000) -> int:
+        """Queue one solve of the caller's own mesh: D, g, glo, dirichlet (may
+        be None) and b all numpy arrays (host) or all torch tensors on the
+        server's device.  None of them is copied here; the binding keeps them
+        alive until poll() has reported the request."""
+        torch = _torch()
+        P = int(E) * (N + 1) ** 3
+        on_dev = isinstance(b, torch.Tensor)
+        if on_dev:
+            keep = (_dev(D, torch.float64, "D", (N + 1) ** 2), _dev(g, torch.float64, "g", 6 * P),
+                    _dev(glo, torch.int64, "glo", P),
+                    _dev(dirichlet, torch.uint8, "dirichlet", P) if dirichlet is not None else None,
+                    _dev(b, torch.float64, "b", P))
+            ptrs = [k.value if k is not None else None for k in keep]
+            hold = (D, g, glo, dirichlet, b)
+        else:
+            arrs = (_host_np(D, np.float64, "D", (N + 1) ** 2), _host_np(g, np.float64, "g", 6 * P),
+                    _host_np(glo, np.int64, "glo", P),
+                    _host_np(dirichlet, np.uint8, "dirichlet", P) if dirichlet is not None else None,
+                    _host_np(b, np.float64, "b", P))
+            ptrs = [a.ctypes.data if a is not None else None for a in arrs]
+            hold = arrs
+        r = Request(0, 0, 0, N, 0.0, (ctypes.c_double * 3)(0.0, 0.0, 0.0), ptrs[4], int(precision),
+                    float(rel_tol), int(max_iter), int(E), ptrs[0], ptrs[1], ptrs[2], ptrs[3],
+                    NEK_MEM_DEVICE if on_dev else NEK_MEM_HOST)
+        rid = ctypes.c_uint64()
+        _check(_lib.nek_server_submit(self._h, ctypes.byref(r), ctypes.byref(rid)), "nek_server_submit")
+        self._sizes[rid.value] = P
+        self._rhs[rid.value] = hold
         return rid.value
 
     def step(self, iters: int = 1):

@@ -262,18 +262,30 @@ int nek_convert_g(int64_t E, int N, const double *g, int g_dtype, void *g_lo, vo
 }
 
 // ---------------------------------------------------------------- measurement
-int nek_bw_probe(int64_t n, int nread, const double *src, double *dst, int grid_cap, int streaming,
-                 void *stream) {
+int nek_bw_probe(int64_t n, int nread, const double *src, int64_t src_stride, double *dst, int grid_cap,
+                 int flags, void *stream) {
     clear_error();
-    if (n < 1) return fail(NEK_ERR_ARG, "nek_bw_probe: n must be >= 1");
+    if (n < 2) return fail(NEK_ERR_ARG, "nek_bw_probe: n must be >= 2");
     if (nread < 1 || nread > 8) return fail(NEK_ERR_ARG, "nek_bw_probe: nread must be in 1..8");
+    if (flags & ~(NEK_PROBE_NT | NEK_PROBE_READ_ONLY)) return fail(NEK_ERR_ARG, "nek_bw_probe: unknown flag");
+    if (src_stride < n || (src_stride & 1)) return fail(NEK_ERR_ARG, "nek_bw_probe: src_stride must be even and >= n");
+    if (grid_cap < 0) return fail(NEK_ERR_ARG, "nek_bw_probe: grid_cap must be >= 0");
     if (!src || !dst || ((uintptr_t)src & 15u) || ((uintptr_t)dst & 15u))
         return fail(NEK_ERR_ARG, "nek_bw_probe: null or misaligned pointer");
+    const bool ro = (flags & NEK_PROBE_READ_ONLY) != 0;
+    const int64_t ndst = ro ? probe_blocks(n, grid_cap) : n;
     const uintptr_t sb = (uintptr_t)src, db = (uintptr_t)dst;
-    if (db < sb + (uintptr_t)(nread * n) * 8 && sb < db + (uintptr_t)n * 8)
+    const uintptr_t src_end = sb + (uintptr_t)((nread - 1) * src_stride + n) * 8;
+    if (db < src_end && sb < db + (uintptr_t)ndst * 8)
         return fail(NEK_ERR_ARG, "nek_bw_probe: src and dst overlap");
-    NEK_HIP(launch_probe(n, nread, src, dst, grid_cap, streaming != 0, (hipStream_t)stream));
+    NEK_HIP(launch_probe(n, nread, src, src_stride, dst, grid_cap, (flags & NEK_PROBE_NT) != 0, ro,
+                         (hipStream_t)stream));
     return NEK_OK;
+}
+
+int64_t nek_bw_probe_groups(int64_t n, int grid_cap) {
+    if (n < 2 || grid_cap < 0) return 0;
+    return probe_blocks(n, grid_cap);
 }
 
 // ---------------------------------------------------------------- gather-scatter
@@ -610,79 +622,62 @@ struct HostSnap {
     }
 };
 thread_local HostSnap g_snap;
-}  // namespace
 
-int nek_cg_solve(int64_t E, int N, const double *D, const double *g, const nek_gs *gs,
-                 const double *b, double *x, const nek_cg_opts *opts_in, nek_cg_stats *st,
-                 void *stream_v) {
-    clear_error();
-    nek_cg_opts opts;
-    if (opts_in) opts = *opts_in;
-    else nek_cg_default_opts(&opts);
-    if (st) {
-        st->iters = 0;
-        st->status = NEK_OK;
-        st->rel_res = -1.0;
-        st->rel_res_true = -1.0;
-        st->n_replacements = 0;
-    }
-    if (E < 1) return fail(NEK_ERR_ARG, "nek_cg_solve: E must be >= 1");
-    if (N < 1 || N > NEK_MAX_DEGREE) return fail(NEK_ERR_UNSUPPORTED, "nek_cg_solve: degree must be in 1..15");
-    if (!D || !g || !gs || !b || !x) return fail(NEK_ERR_ARG, "nek_cg_solve: null argument");
+// What nek_cg_solve needs once its arguments have been checked.
+struct CgPlan {
+    bool mixed = false;
+    int g_dtype = 0;
+    double drop = 0.0;
+    int check_every = 0;
+    bool poll = false;
+    int extra = 1;        // vectors kept in the CG layout beside r, p, w: b, and M^-1
+    size_t need = 0;      // workspace bytes
+};
+
+int cg_check(const char *who, int64_t E, int N, const double *D, const double *g, const nek_gs *gs,
+             const double *b, const double *x, const nek_cg_opts &opts, CgPlan &pl) {
+    const std::string w(who);
+    if (E < 1) return fail(NEK_ERR_ARG, w + ": E must be >= 1");
+    if (N < 1 || N > NEK_MAX_DEGREE) return fail(NEK_ERR_UNSUPPORTED, w + ": degree must be in 1..15");
+    if (!D || !g || !gs || !b || !x) return fail(NEK_ERR_ARG, w + ": null argument");
     if (!aligned8(D) || !aligned8(g) || !aligned16(b) || !aligned16(x))
-        return fail(NEK_ERR_ARG, "nek_cg_solve: misaligned pointer (b and x need 16 bytes)");
-    if (gs->d.E != E || gs->d.N != N) return fail(NEK_ERR_ARG, "nek_cg_solve: gather-scatter built for another mesh");
-    if (b == x) return fail(NEK_ERR_ARG, "nek_cg_solve: b and x must differ");
-    if (opts.max_iter < 0) return fail(NEK_ERR_ARG, "nek_cg_solve: max_iter must be >= 0");
-    const bool mixed = opts.precision == NEK_PREC_F32G32 || opts.precision == NEK_PREC_F32GBF16;
-    if (!mixed && opts.precision != NEK_PREC_F64)
-        return fail(NEK_ERR_UNSUPPORTED, "nek_cg_solve: unknown precision");
-    if (mixed && (!opts.D32 || !opts.g_lo))
-        return fail(NEK_ERR_ARG, "nek_cg_solve: mixed precision needs D32 and g_lo");
-    if (mixed && (((uintptr_t)opts.g_lo & (opts.precision == NEK_PREC_F32G32 ? 7u : 3u)) ||
-                  ((uintptr_t)opts.D32 & 3u)))
-        return fail(NEK_ERR_ARG, "nek_cg_solve: misaligned g_lo or D32");
-    if (opts.dinv && mixed)
-        return fail(NEK_ERR_UNSUPPORTED, "nek_cg_solve: the Jacobi preconditioner is FP64 only");
-    if (opts.dinv && !aligned16(opts.dinv)) return fail(NEK_ERR_ARG, "nek_cg_solve: misaligned dinv");
-    const int g_dtype = opts.precision == NEK_PREC_F32G32 ? NEK_G_F32 : NEK_G_BF16;
-    const double drop = mixed ? (opts.reliable_drop > 0.0 ? opts.reliable_drop : RELIABLE_DROP_DEFAULT) : 0.0;
-    if (mixed && !(drop < 1.0)) return fail(NEK_ERR_ARG, "nek_cg_solve: reliable_drop must be < 1");
-    int check_every = opts.check_every > 0 ? opts.check_every : (mixed ? 4 : 25);
-    const bool poll = mixed || opts.rel_tol > 0.0;
-    if (!poll) check_every = opts.max_iter > 0 ? opts.max_iter : 1;
+        return fail(NEK_ERR_ARG, w + ": misaligned pointer (b and x need 16 bytes)");
+    if (gs->d.E != E || gs->d.N != N) return fail(NEK_ERR_ARG, w + ": gather-scatter built for another mesh");
+    if (b == x) return fail(NEK_ERR_ARG, w + ": b and x must differ");
+    if (opts.max_iter < 0) return fail(NEK_ERR_ARG, w + ": max_iter must be >= 0");
+    pl.mixed = opts.precision == NEK_PREC_F32G32 || opts.precision == NEK_PREC_F32GBF16;
+    if (!pl.mixed && opts.precision != NEK_PREC_F64) return fail(NEK_ERR_UNSUPPORTED, w + ": unknown precision");
+    if (pl.mixed && (!opts.D32 || !opts.g_lo)) return fail(NEK_ERR_ARG, w + ": mixed precision needs D32 and g_lo");
+    if (pl.mixed && (((uintptr_t)opts.g_lo & (opts.precision == NEK_PREC_F32G32 ? 7u : 3u)) ||
+                     ((uintptr_t)opts.D32 & 3u)))
+        return fail(NEK_ERR_ARG, w + ": misaligned g_lo or D32");
+    if (opts.dinv && pl.mixed) return fail(NEK_ERR_UNSUPPORTED, w + ": the Jacobi preconditioner is FP64 only");
+    if (opts.dinv && !aligned16(opts.dinv)) return fail(NEK_ERR_ARG, w + ": misaligned dinv");
+    pl.g_dtype = opts.precision == NEK_PREC_F32G32 ? NEK_G_F32 : NEK_G_BF16;
+    pl.drop = pl.mixed ? (opts.reliable_drop > 0.0 ? opts.reliable_drop : RELIABLE_DROP_DEFAULT) : 0.0;
+    if (pl.mixed && !(pl.drop < 1.0)) return fail(NEK_ERR_ARG, w + ": reliable_drop must be < 1");
+    pl.check_every = opts.check_every > 0 ? opts.check_every : (pl.mixed ? 4 : 25);
+    pl.poll = pl.mixed || opts.rel_tol > 0.0;
+    if (!pl.poll) pl.check_every = opts.max_iter > 0 ? opts.max_iter : 1;
+    pl.extra = opts.dinv ? 2 : 1;
+    pl.need = cg_layout(E, N, pl.extra).total;
+    return NEK_OK;
+}
 
-    hipStream_t s = (hipStream_t)stream_v;
+// The CG driver behind both solve entry points.  ws: the workspace (pl.need
+// bytes, 256-byte aligned).  snap: four host CgScalars the device scalars are
+// copied into.  With events, the host reads the snapshot of a chunk while the
+// next chunk already runs (pinned snap); without them it waits for the stream
+// at every poll.
+int cg_run(int64_t E, int N, const double *D, const double *g, const nek_gs *gs, const double *b, double *x,
+           const nek_cg_opts &opts, const CgPlan &pl, char *ws, CgScalars *snap, bool with_events,
+           hipStream_t s, CgScalars &S, double &true_rel) {
+    const bool mixed = pl.mixed;
     const int64_t P = E * n3_of(N);
-    // b and (with a preconditioner) M^-1 get a copy in the CG layout
-    const int extra = opts.dinv ? 2 : 1;
-    const size_t need = cg_layout(E, N, extra).total;
-    char *ws = (char *)opts.workspace;
-    bool own_ws = false;
-    if (ws) {
-        if (opts.workspace_bytes < need) return fail(NEK_ERR_ARG, "nek_cg_solve: workspace too small");
-        if ((uintptr_t)ws & 255u) return fail(NEK_ERR_ARG, "nek_cg_solve: workspace must be 256-byte aligned");
-    } else {
-        hipError_t e = hipMallocAsync((void **)&ws, need, s);
-        if (e != hipSuccess)
-            return fail(e == hipErrorOutOfMemory ? NEK_ERR_NOMEM : NEK_ERR_DEVICE,
-                        std::string("nek_cg_solve: workspace allocation: ") + hipGetErrorString(e));
-        own_ws = true;
-    }
-    const CgWs W = cg_ws(ws, E, N, extra);
+    const CgWs W = cg_ws(ws, E, N, pl.extra);
     double *r = W.r, *p = W.p, *w = W.w, *scratch1 = W.scratch;
-    unsigned int *tickets = W.tickets;
     CgScalars *sc = W.sc;
-    auto site = [&](int k, const double *extra, long nextra) { return W.site(k, extra, nextra); };
-
-    if (!g_snap.buf) {
-        hipError_t e = hipHostMalloc((void **)&g_snap.buf, 4 * sizeof(CgScalars), hipHostMallocDefault);
-        if (e != hipSuccess) {
-            if (own_ws) (void)hipFreeAsync(ws, s);
-            return check_hip(e, "nek_cg_solve: hipHostMalloc");
-        }
-    }
-    CgScalars *snap = g_snap.buf;
+    auto site = [&](int k) { return W.site(k, nullptr, 0); };
     const uint32_t *own = gs->cg.own_bits;
     const double *bc = W.b;        // b in the CG layout
     const float *dinvc = W.dinv;   // M^-1 in the CG layout, rounded to FP32
@@ -690,7 +685,7 @@ int nek_cg_solve(int64_t E, int N, const double *D, const double *g, const nek_g
     // one CG iteration; `first` uses p = b as set by the init kernel.  Small
     // FP64 meshes take the one-thread-per-node operator, which leaves one
     // partial of (p, A_L p) per element
-    const RedSite red_upd = site(SITE_UPDATE, nullptr, 0);
+    const RedSite red_upd = site(SITE_UPDATE);
     const bool node_op = !mixed && ax_node_fused_fits(E, N);
     auto iterate = [&](bool first) -> hipError_t {
         AxFuse fz;
@@ -702,7 +697,7 @@ int nek_cg_solve(int64_t E, int N, const double *D, const double *g, const nek_g
             fz.x = x;
             fz.dinv = dinvc;
         }
-        hipError_t e = mixed ? launch_ax_f32(E, N, opts.D32, opts.g_lo, g_dtype, p, w, fz, s)
+        hipError_t e = mixed ? launch_ax_f32(E, N, opts.D32, opts.g_lo, pl.g_dtype, p, w, fz, s)
                              : (node_op ? launch_ax_node_fused(E, N, D, g, p, w, fz, s)
                                         : launch_ax_f64(E, N, D, g, p, w, fz, s));
         if (e != hipSuccess) return e;
@@ -722,8 +717,7 @@ int nek_cg_solve(int64_t E, int N, const double *D, const double *g, const nek_g
 
     int rc = NEK_OK;
     hipError_t he = hipSuccess;
-    double true_rel = -1.0;
-    CgScalars S;
+    true_rel = -1.0;
     memset(&S, 0, sizeof(S));
 #define CG_TRY(call)                                                     \
     do {                                                                 \
@@ -732,41 +726,50 @@ int nek_cg_solve(int64_t E, int N, const double *D, const double *g, const nek_g
     } while (0)
     hipEvent_t ev[2] = {nullptr, nullptr};
     {
-        CG_TRY(launch_cg_reset(sc, tickets, N_SITES * RED_TICKETS, opts.max_iter, opts.rel_tol, drop, s));
+        CG_TRY(launch_cg_reset(sc, W.tickets, N_SITES * RED_TICKETS, opts.max_iter, opts.rel_tol, pl.drop, s));
         CG_TRY(launch_permute(E, N, b, W.b, true, s));
         if (opts.dinv) CG_TRY(launch_permute_to_cg_f32(E, N, opts.dinv, W.dinv, s));
-        CG_TRY(launch_cg_init(P, bc, x, r, p, own, dinvc, site(SITE_INIT, nullptr, 0), sc, s));
-        if (poll) {
+        CG_TRY(launch_cg_init(P, bc, x, r, p, own, dinvc, site(SITE_INIT), sc, s));
+        if (pl.poll && with_events) {
             CG_TRY(hipEventCreateWithFlags(&ev[0], hipEventDisableTiming));
             CG_TRY(hipEventCreateWithFlags(&ev[1], hipEventDisableTiming));
         }
         // The host polls a snapshot of the device scalars after every chunk of
-        // check_every iterations, one chunk behind: chunk c+1 is already queued
-        // while the host waits for the snapshot of chunk c, so the device never
-        // idles on the poll.  Kernels queued after the solve has finished exit
-        // at once.
+        // check_every iterations, one chunk behind when it has events: chunk
+        // c+1 is already queued while the host waits for the snapshot of chunk
+        // c, so the device never idles on the poll.  Kernels queued after the
+        // solve has finished exit at once.
         int enq = 0, chunks = 0, prev = -1, replacements = 0;
         bool first = true;
         while (enq < opts.max_iter) {
-            const int chunk = std::min(check_every, opts.max_iter - enq);
+            const int chunk = std::min(pl.check_every, opts.max_iter - enq);
             for (int q = 0; q < chunk; ++q) {
                 CG_TRY(iterate(first));
                 first = false;
             }
             enq += chunk;
-            if (!poll) continue;
+            if (!pl.poll) continue;
             const int slot = chunks++ & 1;
             CG_TRY(hipMemcpyAsync(&snap[slot], sc, sizeof(CgScalars), hipMemcpyDeviceToHost, s));
-            CG_TRY(hipEventRecord(ev[slot], s));
-            if (prev >= 0) {
-                CG_TRY(hipEventSynchronize(ev[prev]));
-                const CgScalars &v = snap[prev];
+            int look = -1;
+            if (with_events) {
+                CG_TRY(hipEventRecord(ev[slot], s));
+                if (prev >= 0) {
+                    CG_TRY(hipEventSynchronize(ev[prev]));
+                    look = prev;
+                }
+            } else {
+                CG_TRY(hipStreamSynchronize(s));
+                look = slot;
+            }
+            if (look >= 0) {
+                const CgScalars &v = snap[look];
                 if (v.done) break;
                 // reliable update: r <- b - mask(dssum(A64 x)) in FP64, at most one
                 // per snapshot that asked for it
                 if (mixed && v.need_replace && v.n_replace >= replacements) {
                     CG_TRY(true_ax());
-                    CG_TRY(launch_cg_replace(P, bc, w, r, own, site(SITE_REPLACE, nullptr, 0), sc, s));
+                    CG_TRY(launch_cg_replace(P, bc, w, r, own, site(SITE_REPLACE), sc, s));
                     ++replacements;
                 }
             }
@@ -780,7 +783,7 @@ int nek_cg_solve(int64_t E, int N, const double *D, const double *g, const nek_g
             // lag flag says so, so evaluate A x directly)
             CG_TRY(launch_ax_f64(E, N, D, g, x, w, plain_cg, s));
             CG_TRY(launch_gs(gs->cg, w, s));
-            CG_TRY(launch_gdiff2(P, bc, w, own, site(SITE_RESID, nullptr, 0), scratch1, s));
+            CG_TRY(launch_gdiff2(P, bc, w, own, site(SITE_RESID), scratch1, s));
             CG_TRY(hipMemcpyAsync(&snap[3].bb, scratch1, sizeof(double), hipMemcpyDeviceToHost, s));
         }
         // x back to the layout of Listing 1 (through w, which is free now)
@@ -794,6 +797,74 @@ out:
 #undef CG_TRY
     for (hipEvent_t e : ev)
         if (e) (void)hipEventDestroy(e);
+    return rc;
+}
+
+// Status and statistics of a finished solve.
+int cg_report(const char *who, const nek_cg_opts &opts, const CgPlan &pl, const CgScalars &S, double true_rel,
+              nek_cg_stats *st) {
+    int status = S.status;
+    const double rel = S.bb > 0.0 ? sqrt(S.rr / S.bb) : 0.0;
+    if (status == NEK_OK && opts.rel_tol > 0.0) {
+        const double judged = pl.mixed ? true_rel : rel;
+        if (!(judged <= opts.rel_tol)) status = NEK_ERR_NOCONV;
+    }
+    if (st) {
+        st->iters = S.it;
+        st->status = status;
+        st->rel_res = rel;
+        st->rel_res_true = true_rel;
+        st->n_replacements = S.n_replace;
+    }
+    if (status == NEK_ERR_BREAKDOWN) return fail(status, std::string(who) + ": breakdown ((p,Ap) <= 0 or non-finite)");
+    if (status == NEK_ERR_NOCONV) return fail(status, std::string(who) + ": tolerance not reached");
+    return NEK_OK;
+}
+
+void cg_stats_init(nek_cg_stats *st) {
+    if (!st) return;
+    st->iters = 0;
+    st->status = NEK_OK;
+    st->rel_res = -1.0;
+    st->rel_res_true = -1.0;
+    st->n_replacements = 0;
+}
+}  // namespace
+
+int nek_cg_solve(int64_t E, int N, const double *D, const double *g, const nek_gs *gs,
+                 const double *b, double *x, const nek_cg_opts *opts_in, nek_cg_stats *st,
+                 void *stream_v) {
+    clear_error();
+    nek_cg_opts opts;
+    if (opts_in) opts = *opts_in;
+    else nek_cg_default_opts(&opts);
+    cg_stats_init(st);
+    CgPlan pl;
+    int rc = cg_check("nek_cg_solve", E, N, D, g, gs, b, x, opts, pl);
+    if (rc != NEK_OK) return rc;
+    hipStream_t s = (hipStream_t)stream_v;
+    char *ws = (char *)opts.workspace;
+    bool own_ws = false;
+    if (ws) {
+        if (opts.workspace_bytes < pl.need) return fail(NEK_ERR_ARG, "nek_cg_solve: workspace too small");
+        if ((uintptr_t)ws & 255u) return fail(NEK_ERR_ARG, "nek_cg_solve: workspace must be 256-byte aligned");
+    } else {
+        hipError_t e = hipMallocAsync((void **)&ws, pl.need, s);
+        if (e != hipSuccess)
+            return fail(e == hipErrorOutOfMemory ? NEK_ERR_NOMEM : NEK_ERR_DEVICE,
+                        std::string("nek_cg_solve: workspace allocation: ") + hipGetErrorString(e));
+        own_ws = true;
+    }
+    if (!g_snap.buf) {
+        hipError_t e = hipHostMalloc((void **)&g_snap.buf, 4 * sizeof(CgScalars), hipHostMallocDefault);
+        if (e != hipSuccess) {
+            if (own_ws) (void)hipFreeAsync(ws, s);
+            return check_hip(e, "nek_cg_solve: hipHostMalloc");
+        }
+    }
+    CgScalars S;
+    double true_rel = -1.0;
+    rc = cg_run(E, N, D, g, gs, b, x, opts, pl, ws, g_snap.buf, true, s, S, true_rel);
     if (own_ws) {
         if (rc != NEK_OK) (void)hipStreamSynchronize(s);
         (void)hipFreeAsync(ws, s);
@@ -802,24 +873,7 @@ out:
         if (st) st->status = rc;
         return rc;
     }
-    {
-        int status = S.status;
-        const double rel = S.bb > 0.0 ? sqrt(S.rr / S.bb) : 0.0;
-        if (status == NEK_OK && opts.rel_tol > 0.0) {
-            const double judged = mixed ? true_rel : rel;
-            if (!(judged <= opts.rel_tol)) status = NEK_ERR_NOCONV;
-        }
-        if (st) {
-            st->iters = S.it;
-            st->status = status;
-            st->rel_res = rel;
-            st->rel_res_true = true_rel;
-            st->n_replacements = S.n_replace;
-        }
-        if (status == NEK_ERR_BREAKDOWN) return fail(status, "nek_cg_solve: breakdown ((p,Ap) <= 0 or non-finite)");
-        if (status == NEK_ERR_NOCONV) return fail(status, "nek_cg_solve: tolerance not reached");
-    }
-    return NEK_OK;
+    return cg_report("nek_cg_solve", opts, pl, S, true_rel, st);
 }
 
 }  // extern "C"

@@ -34,11 +34,14 @@ constexpr int round64(int x) { return (x + 63) / 64 * 64; }
 // up to whole wavefronts).  LDS rows are padded to an odd number of words so
 // that lanes walking pencils with stride RS hit distinct banks.  WIDE: two
 // elements per workgroup at n = 10 (see AxShapeFor).
+#ifndef NEK_AX_WIDE_EPB
+#define NEK_AX_WIDE_EPB 2
+#endif
 template <int NX, typename T, bool WIDE = false>
 struct AxShape {
     static constexpr int NN = NX * NX;
     static constexpr int N3 = NN * NX;
-    static constexpr int EPB = WIDE ? 2 : (NN >= 64 ? 1 : 256 / NN);
+    static constexpr int EPB = WIDE ? NEK_AX_WIDE_EPB : (NN >= 64 ? 1 : 256 / NN);
     static constexpr int THREADS = round64(EPB * NN);
     static constexpr int RS = NX | 1;                                  // row stride (elements)
     static constexpr int LS = NX * RS;                                 // layer stride
@@ -47,7 +50,7 @@ struct AxShape {
     // waves per SIMD the register budget is held to: as many as the LDS of
     // the workgroups that fit a 160 KB CU provides, capped so that the FP64
     // form of every degree compiles without register spills
-    static constexpr int WPS = (163840 / LDS_BYTES) * (THREADS / 64) / 4;
+    static constexpr int WPS = ((163840 / LDS_BYTES) * (THREADS / 64) + 3) / 4;
     static constexpr int REG_CAP = sizeof(T) == 8 ? ((NX <= 8 || NX == 10) ? 4 : (NX <= 14 ? 3 : 2)) : 4;
     static constexpr int MINW = WPS < 1 ? 1 : (WPS > REG_CAP ? REG_CAP : WPS);
     // the CG-fused form also carries the FP64 p column through the element

@@ -376,8 +376,9 @@ hipError_t launch_box_geometry(int Ex, int Ey, int Ez, int N, double amp, double
                                double a2, const GllTable &tab, double *g, double *bm, double *X,
                                hipStream_t s);
 
-hipError_t launch_probe(int64_t n, int nread, const double *src, double *dst, int grid, bool streaming,
-                        hipStream_t s);
+hipError_t launch_probe(int64_t n, int nread, const double *src, int64_t stride, double *dst, int grid_cap,
+                        bool streaming, bool read_only, hipStream_t s);
+int64_t probe_blocks(int64_t n, int grid_cap);   // workgroups of a probe launch
 // diagonal of the element operator at every local point, and the reciprocal
 // of a continuous vector in place (0 stays 0)
 hipError_t launch_ax_diag(int64_t E, int N, const double *D, const double *g, double *d, hipStream_t s);

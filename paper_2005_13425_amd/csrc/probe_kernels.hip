@@ -2,13 +2,21 @@
 //
 // Sec. V measures the bandwidth a CG iteration could reach by replacing its
 // computation with device copies of every load and store.  The probes here do
-// the same with one streaming kernel: dst[i] = sum over k < nread of
-// src[k*n + i], i.e. nread coalesced read streams and one write stream of n
-// doubles each.  nread = 1 is a copy; nread = 7 has the 7:1 read:write byte
-// mix of the FP64 local operator (u and six geometric factors in, w out).
+// the same with one streaming kernel over R read streams of n doubles, stream
+// k starting at src + k * stride:
+//   * write form: dst[i] = sum over k < R of stream_k[i] (R reads, one write
+//     stream; R = 1 is a copy, R = 7 the 7:1 read:write byte mix of the FP64
+//     local operator: u and six geometric factors in, w out);
+//   * read-only form: every workgroup writes one partial sum, so only the
+//     read streams touch HBM.
 // With NT the loads and stores carry the non-temporal (streaming) hint, as the
-// plain FP64 operator's do.
+// plain FP64 operator's do.  The stride lets the caller stagger the streams:
+// when they sit a large power of two apart, the lanes' R loads of one
+// iteration share their low address bits and can fall on the same HBM
+// channels, which a layout like the operator's (six factor planes of one
+// element 8 n^3 bytes apart) does not do.
 #include "nek_internal.h"
+#include "reduce.h"
 
 namespace nek {
 namespace {
@@ -18,18 +26,19 @@ constexpr int PROBE_PAIRS = 4;
 
 typedef double dvec2 __attribute__((ext_vector_type(2)));
 
-template <int R, bool NT>
+template <int R, bool NT, bool RO>
 __global__ void __launch_bounds__(PROBE_THREADS)
-probe_kernel(int64_t n, const double *__restrict__ src, double *__restrict__ dst) {
+probe_kernel(int64_t n, const double *__restrict__ src, int64_t stride, double *__restrict__ dst) {
     const int64_t npairs = n >> 1;
     const int64_t chunk = (int64_t)PROBE_THREADS * PROBE_PAIRS;
+    dvec2 tot = dvec2{0.0, 0.0};
     for (int64_t base = blockIdx.x * chunk; base < npairs; base += (int64_t)gridDim.x * chunk) {
         dvec2 acc[PROBE_PAIRS];
 #pragma unroll
         for (int m = 0; m < PROBE_PAIRS; ++m) acc[m] = dvec2{0.0, 0.0};
 #pragma unroll
         for (int k = 0; k < R; ++k) {
-            const dvec2 *s2 = (const dvec2 *)(src + (int64_t)k * n);
+            const dvec2 *s2 = (const dvec2 *)(src + (int64_t)k * stride);
 #pragma unroll
             for (int m = 0; m < PROBE_PAIRS; ++m) {
                 const int64_t q = base + threadIdx.x + (int64_t)m * PROBE_THREADS;
@@ -39,35 +48,53 @@ probe_kernel(int64_t n, const double *__restrict__ src, double *__restrict__ dst
 #pragma unroll
         for (int m = 0; m < PROBE_PAIRS; ++m) {
             const int64_t q = base + threadIdx.x + (int64_t)m * PROBE_THREADS;
-            if (q < npairs) {
+            if constexpr (RO) {
+                tot += acc[m];
+            } else if (q < npairs) {
                 if (NT) __builtin_nontemporal_store(acc[m], &((dvec2 *)dst)[q]);
                 else ((dvec2 *)dst)[q] = acc[m];
             }
         }
     }
-    if ((n & 1) && blockIdx.x == 0 && threadIdx.x == 0) {
+    if constexpr (RO) {
+        __shared__ double red[PROBE_THREADS / 64];
+        const double s = block_sum<PROBE_THREADS>(tot.x + tot.y, red);
+        if (threadIdx.x == 0) dst[blockIdx.x] = s;
+    } else if ((n & 1) && blockIdx.x == 0 && threadIdx.x == 0) {
         double a = 0.0;
-        for (int k = 0; k < R; ++k) a += src[(int64_t)k * n + n - 1];
+        for (int k = 0; k < R; ++k) a += src[(int64_t)k * stride + n - 1];
         dst[n - 1] = a;
+    }
+}
+
+template <int R>
+void launch_r(int64_t blocks, int64_t n, const double *src, int64_t stride, double *dst, bool nt, bool ro,
+              hipStream_t s) {
+    const dim3 grid((unsigned)blocks), block(PROBE_THREADS);
+    if (ro) {
+        if (nt) hipLaunchKernelGGL((probe_kernel<R, true, true>), grid, block, 0, s, n, src, stride, dst);
+        else hipLaunchKernelGGL((probe_kernel<R, false, true>), grid, block, 0, s, n, src, stride, dst);
+    } else {
+        if (nt) hipLaunchKernelGGL((probe_kernel<R, true, false>), grid, block, 0, s, n, src, stride, dst);
+        else hipLaunchKernelGGL((probe_kernel<R, false, false>), grid, block, 0, s, n, src, stride, dst);
     }
 }
 
 }  // namespace
 
-hipError_t launch_probe(int64_t n, int nread, const double *src, double *dst, int grid, bool streaming,
-                        hipStream_t s) {
+int64_t probe_blocks(int64_t n, int grid_cap) {
     const int64_t per = (int64_t)PROBE_THREADS * PROBE_PAIRS * 2;
     int64_t blocks = (n + per - 1) / per;
-    if (grid > 0 && blocks > grid) blocks = grid;
-    if (blocks < 1) blocks = 1;
+    if (grid_cap > 0 && blocks > grid_cap) blocks = grid_cap;
+    return blocks < 1 ? 1 : blocks;
+}
+
+hipError_t launch_probe(int64_t n, int nread, const double *src, int64_t stride, double *dst, int grid_cap,
+                        bool streaming, bool read_only, hipStream_t s) {
+    const int64_t blocks = probe_blocks(n, grid_cap);
     switch (nread) {
-#define NEK_PROBE(R)                                                                                   \
-    case R:                                                                                            \
-        if (streaming)                                                                                 \
-            hipLaunchKernelGGL((probe_kernel<R, true>), dim3((unsigned)blocks), dim3(PROBE_THREADS), 0, s, n, src, dst); \
-        else                                                                                           \
-            hipLaunchKernelGGL((probe_kernel<R, false>), dim3((unsigned)blocks), dim3(PROBE_THREADS), 0, s, n, src, dst); \
-        break;
+#define NEK_PROBE(R) \
+    case R: launch_r<R>(blocks, n, src, stride, dst, streaming, read_only, s); break;
         NEK_PROBE(1) NEK_PROBE(2) NEK_PROBE(3) NEK_PROBE(4) NEK_PROBE(5) NEK_PROBE(6) NEK_PROBE(7)
         NEK_PROBE(8)
 #undef NEK_PROBE

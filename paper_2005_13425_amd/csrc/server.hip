@@ -61,6 +61,8 @@ Footprint footprint_of(int64_t E, int N, int prec) {
 struct Request {
     uint64_t id = 0;
     nek_request spec{};
+    bool mesh = false;            // the caller's own D, g, glo, dirichlet (else a box)
+    bool on_device = false;       // the caller's arrays are device memory
     int64_t E = 0, P = 0;
     Footprint fp{};
     double t_submit = 0.0;
@@ -69,9 +71,10 @@ struct Request {
     int prep_status = NEK_OK;
     std::string prep_msg;
     GsHost gs;                    // group metadata; index arrays dropped once staged
-    void *staging = nullptr;      // pinned: b | gs idx | own bits | D | D32
+    // pinned: b (host b) | gs idx | own bits | rowed bits | D | D32 | g (host g of a mesh)
+    void *staging = nullptr;
     size_t staging_bytes = 0;
-    size_t off_idx = 0, off_own = 0, off_rowed = 0, off_D = 0, off_D32 = 0;
+    size_t off_b = 0, off_idx = 0, off_own = 0, off_rowed = 0, off_D = 0, off_D32 = 0, off_g = 0;
 };
 
 // Pinned host buffers, reused once their upload has completed.
@@ -209,6 +212,7 @@ using namespace nek;
 struct nek_server {
     size_t budget = 0;
     size_t used = 0;
+    int device = 0;                                   // the device the server runs on
     hipStream_t stream = nullptr;
     hipStream_t copy_stream = nullptr;
     std::chrono::steady_clock::time_point t0;
@@ -249,53 +253,106 @@ struct nek_server {
     }
 
     // ------------------------------------------------------------ preparation
-    void prepare(Request *R) {
+    // Numbering and gather-scatter tables on the host, then everything the
+    // admission uploads into pinned staging.  A mesh of the caller's own in
+    // device memory comes to the host on this thread's stream (glo,
+    // dirichlet, D); its b and g are copied device to device at admission.
+    void prepare(Request *R, hipStream_t ps) {
         const nek_request &q = R->spec;
         const int64_t P = R->P;
-        std::vector<int64_t> glo((size_t)P);
-        std::vector<uint8_t> dr((size_t)P);
-        nek_box_numbering(q.Ex, q.Ey, q.Ez, q.N, glo.data(), dr.data());
-        R->prep_status = gs_build_host(R->E, q.N, glo.data(), dr.data(), true, R->gs, R->prep_msg);
+        const int n = q.N + 1;
+        std::vector<int64_t> glo;
+        std::vector<uint8_t> dr;
+        double D[(NEK_MAX_DEGREE + 1) * (NEK_MAX_DEGREE + 1)];
+        const int64_t *glo_p = q.glo;
+        const uint8_t *dir_p = q.dirichlet;
+        R->prep_status = NEK_OK;
+        if (!R->mesh) {
+            glo.resize((size_t)P);
+            dr.resize((size_t)P);
+            nek_box_numbering(q.Ex, q.Ey, q.Ez, q.N, glo.data(), dr.data());
+            glo_p = glo.data();
+            dir_p = dr.data();
+            gll_host(q.N, nullptr, nullptr, D);
+        } else if (R->on_device) {
+            glo.resize((size_t)P);
+            hipError_t e = hipMemcpyAsync(glo.data(), q.glo, (size_t)P * sizeof(int64_t), hipMemcpyDeviceToHost, ps);
+            if (e == hipSuccess && q.dirichlet) {
+                dr.resize((size_t)P);
+                e = hipMemcpyAsync(dr.data(), q.dirichlet, (size_t)P, hipMemcpyDeviceToHost, ps);
+            }
+            if (e == hipSuccess) e = hipMemcpyAsync(D, q.D, (size_t)n * n * sizeof(double), hipMemcpyDeviceToHost, ps);
+            if (e == hipSuccess) e = hipStreamSynchronize(ps);
+            if (e != hipSuccess) {
+                R->prep_status = NEK_ERR_DEVICE;
+                R->prep_msg = std::string("copying the request's numbering and D to the host: ") + hipGetErrorString(e);
+            }
+            glo_p = glo.data();
+            dir_p = q.dirichlet ? dr.data() : nullptr;
+        } else {
+            memcpy(D, q.D, (size_t)n * n * sizeof(double));
+        }
+        if (R->prep_status == NEK_OK)
+            R->prep_status = gs_build_host(R->E, q.N, glo_p, dir_p, true, R->gs, R->prep_msg);
         if (R->prep_status == NEK_OK) {
-            const int n = q.N + 1;
-            R->off_idx = align256(P * sizeof(double));
-            R->off_own = R->off_idx + align256(R->gs.idx.size() * sizeof(int32_t) + 4);
-            R->off_rowed = R->off_own + align256(R->gs.own.size() * sizeof(uint32_t));
-            R->off_D = R->off_rowed + align256(R->gs.rowed.size() * sizeof(uint32_t));
-            R->off_D32 = R->off_D + align256((size_t)n * n * sizeof(double));
-            R->staging_bytes = R->off_D32 + align256((size_t)n * n * sizeof(float));
+            const bool host_b = !R->on_device, host_g = R->mesh && !R->on_device;
+            size_t at = 0;
+            R->off_b = at;
+            if (host_b) at += align256((size_t)P * sizeof(double));
+            R->off_idx = at;
+            at += align256(R->gs.idx.size() * sizeof(int32_t) + 4);
+            R->off_own = at;
+            at += align256(R->gs.own.size() * sizeof(uint32_t));
+            R->off_rowed = at;
+            at += align256(R->gs.rowed.size() * sizeof(uint32_t));
+            R->off_D = at;
+            at += align256((size_t)n * n * sizeof(double));
+            R->off_D32 = at;
+            at += align256((size_t)n * n * sizeof(float));
+            R->off_g = at;
+            if (host_g) at += align256((size_t)6 * P * sizeof(double));
+            R->staging_bytes = at;
             R->staging = pinned.get(R->staging_bytes);
             if (!R->staging) {
                 R->prep_status = NEK_ERR_NOMEM;
                 R->prep_msg = "pinned staging allocation failed";
             } else {
                 char *st = (char *)R->staging;
-                memcpy(st, q.b, (size_t)P * sizeof(double));   // the caller's b, read once
+                if (host_b) memcpy(st + R->off_b, q.b, (size_t)P * sizeof(double));   // the caller's b, read once
                 if (!R->gs.idx.empty()) memcpy(st + R->off_idx, R->gs.idx.data(), R->gs.idx.size() * sizeof(int32_t));
                 memcpy(st + R->off_own, R->gs.own.data(), R->gs.own.size() * sizeof(uint32_t));
                 memcpy(st + R->off_rowed, R->gs.rowed.data(), R->gs.rowed.size() * sizeof(uint32_t));
-                double D[(NEK_MAX_DEGREE + 1) * (NEK_MAX_DEGREE + 1)];
-                gll_host(q.N, nullptr, nullptr, D);
                 memcpy(st + R->off_D, D, (size_t)n * n * sizeof(double));
                 float *D32 = (float *)(st + R->off_D32);
                 for (int t = 0; t < n * n; ++t) D32[t] = (float)D[t];
+                if (host_g) memcpy(st + R->off_g, q.g, (size_t)6 * P * sizeof(double));
             }
         }
         R->prepared.store(true, std::memory_order_release);
     }
 
     void worker_loop() {
+        (void)hipSetDevice(device);
+        hipStream_t ps = nullptr;
+        const bool have_stream = hipStreamCreateWithFlags(&ps, hipStreamNonBlocking) == hipSuccess;
         for (;;) {
             Request *R = nullptr;
             {
                 std::unique_lock<std::mutex> lk(mu);
                 cv.wait(lk, [&] { return stop || !prep_queue.empty(); });
-                if (stop) return;
+                if (stop) break;
                 R = prep_queue.front();
                 prep_queue.pop_front();
             }
-            prepare(R);
+            if (!have_stream && R->mesh && R->on_device) {
+                R->prep_status = NEK_ERR_DEVICE;
+                R->prep_msg = "no stream for the preparation thread";
+                R->prepared.store(true, std::memory_order_release);
+                continue;
+            }
+            prepare(R, ps);
         }
+        if (have_stream) (void)hipStreamDestroy(ps);
     }
 
     // ------------------------------------------------------------ admission
@@ -345,10 +402,15 @@ struct nek_server {
         S->glo = f.glo ? (void *)a : nullptr;
         a += f.glo;
         S->W = cg_ws(a, R->E, q.N, 0);
-        // uploads (pinned staging) and device setup, all on the server stream
+        // uploads (pinned staging, or the caller's device arrays) and device
+        // setup, all on the server stream
         const char *st = (const char *)R->staging;
         // b arrives in the layout of Listing 1 (through w) and is kept in the CG layout
-        NEK_HIP(hipMemcpyAsync(S->W.w, st, (size_t)R->P * sizeof(double), hipMemcpyHostToDevice, stream));
+        if (R->on_device)
+            NEK_HIP(hipMemcpyAsync(S->W.w, q.b, (size_t)R->P * sizeof(double), hipMemcpyDeviceToDevice, stream));
+        else
+            NEK_HIP(hipMemcpyAsync(S->W.w, st + R->off_b, (size_t)R->P * sizeof(double), hipMemcpyHostToDevice,
+                                   stream));
         NEK_HIP(launch_permute(R->E, q.N, S->W.w, S->b, true, stream));
         const size_t own_off = R->gs.idx_bytes();   // == off_own - off_idx
         NEK_HIP(hipMemcpyAsync(gs_arena, st + R->off_idx, own_off, hipMemcpyHostToDevice, stream));
@@ -356,19 +418,26 @@ struct nek_server {
                                R->gs.rowed.size() * sizeof(uint32_t), hipMemcpyHostToDevice, stream));
         NEK_HIP(hipMemcpyAsync(gs_arena + own_off, st + R->off_own, R->gs.own.size() * sizeof(uint32_t),
                                hipMemcpyHostToDevice, stream));
-        NEK_HIP(hipMemcpyAsync(S->D, st + R->off_D, R->off_D32 - R->off_D, hipMemcpyHostToDevice, stream));
-        NEK_HIP(hipMemcpyAsync(S->D32, st + R->off_D32, R->staging_bytes - R->off_D32, hipMemcpyHostToDevice, stream));
+        const size_t n2 = (size_t)(q.N + 1) * (q.N + 1);
+        NEK_HIP(hipMemcpyAsync(S->D, st + R->off_D, n2 * sizeof(double), hipMemcpyHostToDevice, stream));
+        NEK_HIP(hipMemcpyAsync(S->D32, st + R->off_D32, n2 * sizeof(float), hipMemcpyHostToDevice, stream));
+        if (R->mesh)
+            NEK_HIP(hipMemcpyAsync(S->g, R->on_device ? (const void *)q.g : (const void *)(st + R->off_g),
+                                   (size_t)6 * R->P * sizeof(double),
+                                   R->on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, stream));
         NEK_HIP(hipEventCreateWithFlags(&S->ev_upload, hipEventDisableTiming));
         NEK_HIP(hipEventRecord(S->ev_upload, stream));
         gs_attach(R->gs, gs_arena, S->gsd);
         std::vector<int32_t>().swap(R->gs.idx);
         std::vector<uint32_t>().swap(R->gs.own);
         std::vector<uint32_t>().swap(R->gs.rowed);
-        GllTable tab;
-        memset(&tab, 0, sizeof(tab));
-        gll_host(q.N, tab.z, tab.w, tab.D);
-        NEK_HIP(launch_box_geometry(q.Ex, q.Ey, q.Ez, q.N, q.amp, q.a[0], q.a[1], q.a[2], tab, S->g,
-                                    nullptr, nullptr, stream));
+        if (!R->mesh) {
+            GllTable tab;
+            memset(&tab, 0, sizeof(tab));
+            gll_host(q.N, tab.z, tab.w, tab.D);
+            NEK_HIP(launch_box_geometry(q.Ex, q.Ey, q.Ez, q.N, q.amp, q.a[0], q.a[1], q.a[2], tab, S->g,
+                                        nullptr, nullptr, stream));
+        }
         if (is_mixed(q.precision))
             NEK_HIP(launch_convert_g(R->E, q.N, S->g,
                                      q.precision == NEK_PREC_F32G32 ? NEK_G_F32 : NEK_G_BF16, S->glo, stream));
@@ -644,6 +713,11 @@ size_t nek_server_footprint(int Ex, int Ey, int Ez, int N, int precision) {
     return footprint_of((int64_t)Ex * Ey * Ez, N, precision).total;
 }
 
+size_t nek_server_footprint_mesh(int64_t E, int N, int precision) {
+    if (E < 1 || N < 1 || N > NEK_MAX_DEGREE) return 0;
+    return footprint_of(E, N, precision).total;
+}
+
 int nek_server_create(size_t hbm_budget, nek_server **out) {
     clear_error();
     if (!out) return fail(NEK_ERR_ARG, "nek_server_create: out is null");
@@ -652,6 +726,7 @@ int nek_server_create(size_t hbm_budget, nek_server **out) {
     std::unique_ptr<nek_server> S(new nek_server());
     S->budget = hbm_budget;
     S->t0 = std::chrono::steady_clock::now();
+    NEK_HIP(hipGetDevice(&S->device));
     NEK_HIP(hipStreamCreate(&S->stream));
     NEK_HIP(hipStreamCreateWithFlags(&S->copy_stream, hipStreamNonBlocking));
     for (int k = 0; k < 2; ++k) {
@@ -673,17 +748,33 @@ int nek_server_create(size_t hbm_budget, nek_server **out) {
 int nek_server_submit(nek_server *srv, const nek_request *req, uint64_t *id) {
     clear_error();
     if (!srv || !req || !req->b) return fail(NEK_ERR_ARG, "nek_server_submit: null argument");
-    if (req->Ex < 1 || req->Ey < 1 || req->Ez < 1) return fail(NEK_ERR_ARG, "nek_server_submit: box sizes must be >= 1");
     if (req->N < 1 || req->N > NEK_MAX_DEGREE) return fail(NEK_ERR_UNSUPPORTED, "nek_server_submit: degree must be in 1..15");
     if (req->precision != NEK_PREC_F64 && !is_mixed(req->precision))
         return fail(NEK_ERR_UNSUPPORTED, "nek_server_submit: unknown precision");
     if (req->max_iter < 0) return fail(NEK_ERR_ARG, "nek_server_submit: max_iter must be >= 0");
-    const int64_t E = (int64_t)req->Ex * req->Ey * req->Ez;
+    if (req->mem != NEK_MEM_HOST && req->mem != NEK_MEM_DEVICE)
+        return fail(NEK_ERR_ARG, "nek_server_submit: mem must be NEK_MEM_HOST or NEK_MEM_DEVICE");
+    const bool mesh = req->g != nullptr;
+    const bool on_device = req->mem == NEK_MEM_DEVICE;
+    int64_t E;
+    if (mesh) {
+        if (req->E < 1) return fail(NEK_ERR_ARG, "nek_server_submit: a mesh of the caller's needs E >= 1");
+        if (!req->D || !req->glo) return fail(NEK_ERR_ARG, "nek_server_submit: a mesh of the caller's needs D, g and glo");
+        E = req->E;
+    } else {
+        if (req->Ex < 1 || req->Ey < 1 || req->Ez < 1) return fail(NEK_ERR_ARG, "nek_server_submit: box sizes must be >= 1");
+        E = (int64_t)req->Ex * req->Ey * req->Ez;
+    }
+    if (on_device && (!aligned8(req->b) || (mesh && (!aligned8(req->g) || !aligned8(req->D) || !aligned8(req->glo)))))
+        return fail(NEK_ERR_ARG, "nek_server_submit: device arrays must be 8-byte aligned");
+    if (E > ((int64_t)1 << 31)) return fail(NEK_ERR_ARG, "nek_server_submit: E*(N+1)^3 must be < 2^31");
     const int64_t P = E * n3_of(req->N);
     if (P >= ((int64_t)1 << 31)) return fail(NEK_ERR_ARG, "nek_server_submit: E*(N+1)^3 must be < 2^31");
     auto R = std::make_unique<Request>();
     R->id = srv->next_id++;
-    R->spec = *req;   // b is read by a preparation thread, not copied here
+    R->spec = *req;   // the arrays are read later, not copied here
+    R->mesh = mesh;
+    R->on_device = on_device;
     R->E = E;
     R->P = P;
     R->fp = footprint_of(E, req->N, req->precision);

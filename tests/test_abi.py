@@ -92,11 +92,18 @@ def test_argument_errors_before_device_work(nek):
     assert "2^31" in lib.nek_last_error().decode()
     # bandwidth probe
     big = ctypes.c_void_p(0x100000)
-    assert lib.nek_bw_probe(0, 7, fake, big, 0, 0, None) == nek.NEK_ERR_ARG
-    assert lib.nek_bw_probe(16, 9, fake, big, 0, 0, None) == nek.NEK_ERR_ARG
-    assert lib.nek_bw_probe(16, 0, fake, big, 0, 1, None) == nek.NEK_ERR_ARG
-    assert lib.nek_bw_probe(16, 1, ctypes.c_void_p(0x1008), big, 0, 0, None) == nek.NEK_ERR_ARG
-    assert lib.nek_bw_probe(16, 2, fake, ctypes.c_void_p(0x1010), 0, 0, None) == nek.NEK_ERR_ARG   # overlap
+    assert lib.nek_bw_probe(0, 7, fake, 0, big, 0, 0, None) == nek.NEK_ERR_ARG
+    assert lib.nek_bw_probe(16, 9, fake, 16, big, 0, 0, None) == nek.NEK_ERR_ARG
+    assert lib.nek_bw_probe(16, 0, fake, 16, big, 0, 1, None) == nek.NEK_ERR_ARG
+    assert lib.nek_bw_probe(16, 1, ctypes.c_void_p(0x1008), 16, big, 0, 0, None) == nek.NEK_ERR_ARG
+    assert lib.nek_bw_probe(16, 2, fake, 16, ctypes.c_void_p(0x1010), 0, 0, None) == nek.NEK_ERR_ARG   # overlap
+    assert lib.nek_bw_probe(16, 2, fake, 15, big, 0, 0, None) == nek.NEK_ERR_ARG    # stride < n
+    assert lib.nek_bw_probe(16, 2, fake, 17, big, 0, 0, None) == nek.NEK_ERR_ARG    # odd stride
+    assert lib.nek_bw_probe(16, 2, fake, 16, big, 0, 4, None) == nek.NEK_ERR_ARG    # unknown flag
+    assert lib.nek_bw_probe(16, 2, fake, 16, big, -1, 0, None) == nek.NEK_ERR_ARG   # negative cap
+    assert lib.nek_bw_probe_groups(10 ** 6, 0) == (10 ** 6 + 2047) // 2048
+    assert lib.nek_bw_probe_groups(10 ** 6, 100) == 100
+    assert lib.nek_bw_probe_groups(1, 0) == 0
     # Jacobi setup
     assert lib.nek_jacobi_inverse(0, 9, fake, fake, fake, fake, None) == nek.NEK_ERR_ARG
     assert lib.nek_jacobi_inverse(4, 16, fake, fake, fake, fake, None) == nek.NEK_ERR_UNSUPPORTED

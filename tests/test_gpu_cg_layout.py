@@ -81,7 +81,7 @@ def test_cg_every_degree(nek, N):
     err = _rel(x, ref.x)
     print(f"CG N={N} box={box}: iters {res.iters}/{ref.iters} rel-L2 {err:.2e}", flush=True)
     assert res.status == 0 and res.iters == ref.iters
-    assert err <= 1e-11
+    assert err <= 1e-12
     assert abs(res.rel_res - ref.res_hist[-1]) <= 1e-9 * ref.res_hist[-1] + 1e-14
 
 

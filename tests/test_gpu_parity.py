@@ -280,15 +280,15 @@ def test_cg_odd_point_count_and_interior_mask(nek):
 
 @pytest.mark.parametrize("streaming", [False, True])
 def test_bw_probe_sums_its_streams(nek, streaming):
-    # dst[i] = sum over k of src[k*n + i], summed in k order; odd n for the tail
+    # dst[i] = sum over k of stream_k[i], summed in k order; odd n for the tail
     rng = np.random.default_rng(9)
-    for nread, n in ((1, 1001), (7, 40001), (8, 12345)):
-        src = rng.uniform(-1, 1, nread * n)
+    for nread, n, stride in ((1, 1001, 1002), (7, 40001, 40001 + 31 * 32 + 1), (8, 12345, 12346)):
+        src = rng.uniform(-1, 1, (nread - 1) * stride + n)
         dst = torch.empty(n, dtype=torch.float64, device="cuda")
-        nek.bw_probe(_dev(src), dst, nread, streaming=streaming)
+        nek.bw_probe(_dev(src), dst, nread, stride=stride, streaming=streaming)
         ref = np.zeros(n)
         for k in range(nread):
-            ref = ref + src[k * n:(k + 1) * n]
+            ref = ref + src[k * stride:k * stride + n]
         np.testing.assert_array_equal(dst.cpu().numpy(), ref)
     # a capped grid walks the rest with a stride
     src = rng.uniform(-1, 1, 3 * 300001)
@@ -296,6 +296,24 @@ def test_bw_probe_sums_its_streams(nek, streaming):
     nek.bw_probe(_dev(src), dst, 3, grid_cap=7, streaming=streaming)
     ref = src[:300001] + src[300001:600002] + src[600002:]
     np.testing.assert_array_equal(dst.cpu().numpy(), ref)
+
+
+@pytest.mark.parametrize("streaming", [False, True])
+def test_bw_probe_read_only_partials(nek, streaming):
+    # one partial per workgroup; together they hold the sum of every stream
+    # (the last value left out for odd n)
+    rng = np.random.default_rng(10)
+    for nread, n, cap in ((7, 40000, 0), (7, 300001, 13), (2, 5000, 1)):
+        stride = n + 33
+        src = rng.uniform(-1, 1, (nread - 1) * stride + n)
+        groups = nek.bw_probe_groups(n, cap)
+        dst = torch.empty(groups, dtype=torch.float64, device="cuda")
+        nek.bw_probe(_dev(src), dst, nread, n=n, stride=stride, grid_cap=cap, streaming=streaming,
+                     read_only=True)
+        m = n - (n & 1)
+        ref = sum(src[k * stride:k * stride + m].sum() for k in range(nread))
+        got = dst.cpu().numpy().sum()
+        assert abs(got - ref) <= 1e-12 * np.abs(src).sum(), (nread, n, cap)
 
 
 def test_gs_dot_odd_and_unaligned_rejected(nek):

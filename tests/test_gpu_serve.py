@@ -219,3 +219,88 @@ def test_server_errors(nek):
         srv.fetch(12345) if 12345 in srv._sizes else nek._check(
             nek._lib.nek_server_fetch(srv._h, nek.ctypes.c_uint64(12345), b.ctypes.data), "fetch")
     srv.close()
+
+
+def _oracle_residual(m, b, x):
+    """||b - mask(dssum(A_L x))|| / ||b|| over unique nodes, by the oracle."""
+    r = b - oracle.masked_ax(m, x)
+    return np.sqrt(oracle.gdot(m.glo, r, r, m.U) / oracle.gdot(m.glo, b, b, m.U))
+
+
+def test_served_caller_mesh_host_and_device(nek):
+    """The oracle's own arrays of a perturbed mesh, submitted once from host
+    memory and once from device memory, beside a box request of another
+    degree: both solutions are bitwise the same as the host request served
+    alone, and the oracle's converged solution to 1e-8."""
+    box, N = (4, 3, 3), 7
+    m = oracle.box_mesh(*box, N, synth.AMP, synth.geom_coeffs(seed=31))
+    b = oracle.lattice_to_local(m, synth.lattice_uniform(*box, N, seed=17))
+    assert nek.server_footprint_mesh(m.E, N) == nek.server_footprint(*box, N)
+
+    def run(with_device, with_box):
+        srv = nek.Server(8 * GB)
+        ids = {srv.submit_mesh(m.E, N, m.D, m.g, m.glo, m.dirichlet, b): "host"}
+        if with_device:
+            dev = [torch.from_numpy(np.ascontiguousarray(a)).cuda() for a in (m.D, m.g, m.glo, m.dirichlet, b)]
+            ids[srv.submit_mesh(m.E, N, *dev)] = "device"
+        if with_box:
+            ids[srv.submit(3, 3, 3, 5, _rhs(nek, (3, 3, 3), 5, 2), amp=synth.AMP, a=synth.geom_coeffs())] = "box"
+        got = srv.run_until_done(list(ids))
+        xs = {ids[k]: srv.fetch(k) for k in got}
+        res = {ids[k]: v for k, v in got.items()}
+        srv.close()
+        return xs, res
+
+    xa, ra = run(False, False)
+    xm, rm = run(True, True)
+    for k in rm:
+        assert rm[k]["status"] == 0 and rm[k]["rel_res"] <= 1e-10, (k, rm[k])
+    assert rm["host"]["E"] == m.E and rm["host"]["N"] == N
+    np.testing.assert_array_equal(xm["host"], xa["host"])
+    np.testing.assert_array_equal(xm["device"], xa["host"])
+    assert rm["device"]["iters"] == rm["host"]["iters"] == ra["host"]["iters"]
+    ref = oracle.cg(m, b, max_iter=5000, rel_tol=1e-13)
+    assert np.linalg.norm(xa["host"] - ref.x) / np.linalg.norm(ref.x) <= 1e-8
+    assert _oracle_residual(m, b, xa["host"]) <= 1.01e-10
+
+
+def test_served_paper_shape_fp64_and_large_mixed(nek):
+    """One mix of the benchmark's shape in FP64 (E = 4096, N = 9) and the
+    largest request of the served workload in the mixed form (E = 8192 as
+    32x16x16, N = 11, FP32 operator with FP32 g), both from the oracle's own
+    arrays: the FP64 solution is bitwise that of nek_cg_solve on the same
+    arrays; the oracle evaluates b - A x of the mixed solution itself."""
+    print("serve: building E=4096 N=9 and E=8192 N=11 meshes", flush=True)
+    m9 = oracle.box_mesh(16, 16, 16, 9, synth.AMP, synth.geom_coeffs(seed=41))
+    b9 = oracle.lattice_to_local(m9, synth.lattice_uniform(16, 16, 16, 9, seed=42))
+    m11 = oracle.box_mesh(32, 16, 16, 11, synth.AMP, synth.geom_coeffs(seed=43))
+    b11 = oracle.lattice_to_local(m11, synth.lattice_uniform(32, 16, 16, 11, seed=44))
+    srv = nek.Server(16 * GB)
+    ids = {srv.submit_mesh(m9.E, 9, m9.D, m9.g, m9.glo, m9.dirichlet, b9, rel_tol=1e-10): "fp64",
+           srv.submit_mesh(m11.E, 11, m11.D, m11.g, m11.glo, m11.dirichlet, b11,
+                           precision=nek.NEK_PREC_F32G32, rel_tol=1e-10, max_iter=20000): "mixed"}
+    print("serve: running the mix", flush=True)
+    got = srv.run_until_done(list(ids), iters=4)
+    xs = {ids[k]: srv.fetch(k) for k in got}
+    res = {ids[k]: v for k, v in got.items()}
+    srv.close()
+    print(f"serve: fp64 {res['fp64']['iters']} iterations, mixed {res['mixed']['iters']} "
+          f"({res['mixed']['n_replacements']} replacements)", flush=True)
+    for k in res:
+        assert res[k]["status"] == 0, (k, res[k])
+    # FP64: the same arrays through nek_cg_solve
+    gs = nek.GatherScatter(m9.E, 9, m9.glo, m9.dirichlet)
+    xs9, rs9 = nek.cg_solve(torch.from_numpy(m9.D).cuda(), torch.from_numpy(m9.g).cuda(), gs,
+                            torch.from_numpy(b9).cuda(), max_iter=10000, rel_tol=1e-10, true_residual=True)
+    torch.cuda.synchronize()
+    gs.close()
+    assert rs9.iters == res["fp64"]["iters"]
+    np.testing.assert_array_equal(xs["fp64"], xs9.cpu().numpy())
+    assert res["fp64"]["rel_res"] == rs9.rel_res
+    # mixed: the oracle's own FP64 residual of the served solution
+    print("serve: oracle residual of the mixed solution", flush=True)
+    t = _oracle_residual(m11, b11, xs["mixed"])
+    lib = res["mixed"]["rel_res_true"]
+    print(f"serve: mixed true residual oracle {t:.4e} library {lib:.4e}", flush=True)
+    assert t <= 1.01e-10
+    assert abs(t - lib) <= 1e-3 * t
