@@ -182,7 +182,8 @@ def main():
     # x and g in; p, x and w out), the assemble-update 24 B per single-copy
     # point, 20 B per copy of a shared node plus 8 B per node (r in) and one
     # bit per point
-    n_unique, n_rows, n_entries, n_masked = gs.info()
+    info = gs.info()
+    n_rows, n_entries = info["n_rows"], info["n_entries"]
     n_zero = int(dirichlet.sum())
     asm_bytes = 24 * (P - n_entries - n_zero) + 20 * n_entries + 8 * n_rows + P // 8
     cg_bytes_iter = 96 * P + asm_bytes

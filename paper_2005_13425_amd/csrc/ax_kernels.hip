@@ -160,9 +160,17 @@ __device__ __forceinline__ void cgl_point(int c, int &i, int &j) {
 // In the CG layout thread (a, b) loads and stores the vector entries at
 // offset c = a + n b of each layer, which belong to another column; they pass
 // through LDS, with one more barrier before w is stored.
+//
+// A part of a workgroup runs the body: `tid` is the thread's index within the
+// part (THREADS or more for threads of the workgroup that belong to no part:
+// they only take part in the barriers), `lds` the part's EPB * 2 * BUF values
+// and `rbase` the first thread of the part, for the sum of its partial (`red`
+// holds one double per wave of the workgroup).  A plain launch is one part
+// per workgroup (tid = threadIdx.x, rbase = 0).
 template <int NX, typename T, typename GT, bool FUSE, bool CGL>
 __device__ __forceinline__ void ax_body(int64_t blk, int64_t E, kptr<T> D, gptr<const GT> g,
-                                        gptr<double> p, gptr<double> w, const AxFuse &fz)
+                                        gptr<double> p, gptr<double> w, const AxFuse &fz,
+                                        int tid, T *lds, double *red, int rbase)
 {
     using S = AxShapeFor<NX, T, FUSE, CGL>;
     // The plain FP64 operator streams g and w with the non-temporal hint from
@@ -187,9 +195,6 @@ __device__ __forceinline__ void ax_body(int64_t blk, int64_t E, kptr<T> D, gptr<
     const gptr<const float> fdinv = (gptr<const float>)fz.dinv;
     if (FUSE && sc->done) return;   // uniform: CG already finished
 
-    __shared__ T lds[EPB * 2 * BUF];
-
-    const int tid = threadIdx.x;
     const int eb = tid / NN;
     const int c = tid - eb * NN;
     const int a = c % NX;
@@ -416,9 +421,8 @@ __device__ __forceinline__ void ax_body(int64_t blk, int64_t E, kptr<T> D, gptr<
     // nodes, so the assembly needs no product of its own.
     if constexpr (FUSE) {
         if (fz.partials != nullptr) {
-            __shared__ double red[S::THREADS / 64];
-            const double bs = block_sum<S::THREADS>(pw, red);
-            if (threadIdx.x == 0) ((gptr<double>)fz.partials)[blk] = bs;
+            const double bs = seg_sum<S::THREADS>(pw, red, rbase);
+            if ((int)threadIdx.x == rbase && blk * EPB < E) ((gptr<double>)fz.partials)[blk] = bs;
         }
     }
 }
@@ -430,30 +434,113 @@ __global__ void __launch_bounds__((AxShapeFor<NX, T, FUSE, CGL>::THREADS),
 ax_kernel(int64_t E, const T *__restrict__ D, const GT *__restrict__ g, double *__restrict__ p,
           double *__restrict__ w, AxFuse fz)
 {
+    using S = AxShapeFor<NX, T, FUSE, CGL>;
+    __shared__ T lds[S::EPB * 2 * S::BUF];
+    __shared__ double red[S::THREADS / 64];
     ax_body<NX, T, GT, FUSE, CGL>(blockIdx.x, E, (kptr<T>)D, (gptr<const GT>)g, (gptr<double>)p,
-                             (gptr<double>)w, fz);
+                             (gptr<double>)w, fz, threadIdx.x, lds, red, 0);
 }
 
-// Several CG solves of the same degree and precision in one launch: slot s
-// owns workgroups [slots[s].block0, slots[s+1].block0) and runs exactly the
-// workgroups its own launch would, so its arithmetic does not depend on
-// which other solves share the launch.
+// The served form: the CG-fused operator of every admitted solve of any
+// degree and precision in one launch of 256-thread workgroups.  Solve s owns
+// workgroups [block0, next block0); a workgroup holds 256 / THREADS parts of
+// the solve's own shape (two pencil workgroups of 128 threads at n = 10, four
+// of 64 at n = 8), and part q of workgroup b does exactly what workgroup
+// (b - block0) * parts + q of the solve's own launch would do, with the same
+// partial of (p, A_L p) summed in the same order: a solve's arithmetic does
+// not depend on which others share the launch, or on sharing it at all.  The
+// LDS is given at launch, sized for the largest shape in it.
 template <int NX, typename T, typename GT>
-__global__ void __launch_bounds__((AxShape<NX, T>::THREADS), (AxShape<NX, T>::MINW_FUSED))
-ax_batch_kernel(const AxSlot *__restrict__ slots, int nslots)
+struct ServeShape {
+    using S = AxShapeFor<NX, T, true, true>;
+    static constexpr int PARTS = SERVE_THREADS / S::THREADS;
+    static constexpr int PART_LDS = S::EPB * 2 * S::BUF;   // values of T
+    static constexpr size_t LDS_BYTES = (size_t)PARTS * PART_LDS * sizeof(T);
+};
+
+template <int NX, typename T, typename GT>
+__device__ __forceinline__ void serve_part(const ServeAxSlot &S, int64_t wg, char *lds_raw, double *red) {
+    using H = ServeShape<NX, T, GT>;
+    constexpr int TH = H::S::THREADS;
+    const int q = (int)threadIdx.x / TH;                  // H::PARTS: no part
+    const int qc = q < H::PARTS ? q : H::PARTS - 1;
+    const int tid = q < H::PARTS ? (int)threadIdx.x - q * TH : TH;
+    const int64_t blk = (wg - S.block0) * H::PARTS + qc;
+    ax_body<NX, T, GT, true, true>(blk, S.E, (kptr<T>)S.D, (gptr<const GT>)S.g, (gptr<double>)S.p,
+                                   (gptr<double>)S.w, S.fz, tid, (T *)lds_raw + (size_t)qc * H::PART_LDS, red,
+                                   qc * TH);
+}
+
+// The two merged kernels split the shapes by register need: B takes the FP64
+// shapes whose own kernel holds fewer than four waves per SIMD (odd n from 9,
+// and n >= 13), A everything else (at most 128 VGPRs, four waves per SIMD:
+// the LDS of two n = 10 pencil workgroups, 35 KB, allows four workgroups per
+// CU).  The served workload's degrees 5, 7, 9, 11 all run in A.
+template <int NX, typename T>
+constexpr bool serve_in_b() { return sizeof(T) == 8 && (NX >= 13 || NX == 9 || NX == 11); }
+
+template <bool B, typename T, typename GT>
+__device__ __forceinline__ void serve_dispatch(const ServeAxSlot &S, int64_t wg, char *lds, double *red) {
+    switch (S.nx) {
+#define NEK_SCASE(NX) \
+    case NX:                                                        \
+        if constexpr (serve_in_b<NX, T>() == B) serve_part<NX, T, GT>(S, wg, lds, red); \
+        break;
+        NEK_SCASE(2) NEK_SCASE(3) NEK_SCASE(4) NEK_SCASE(5) NEK_SCASE(6) NEK_SCASE(7) NEK_SCASE(8)
+        NEK_SCASE(9) NEK_SCASE(10) NEK_SCASE(11) NEK_SCASE(12) NEK_SCASE(13) NEK_SCASE(14)
+        NEK_SCASE(15) NEK_SCASE(16)
+#undef NEK_SCASE
+    default: break;
+    }
+}
+
+template <bool B>
+__device__ __forceinline__ void serve_body(const ServeAxSlot *__restrict__ slots, int nslots, char *lds,
+                                           double *red)
 {
-    const AxSlot S = slots[batch_slot(slots, nslots, (int64_t)blockIdx.x)];
-    ax_body<NX, T, GT, true, true>((int64_t)blockIdx.x - S.block0, S.E, (kptr<T>)S.D, (gptr<const GT>)S.g,
-                             (gptr<double>)S.p, (gptr<double>)S.w, S.fz);
+    const ServeAxSlot &S = slots[batch_slot(slots, nslots, (int64_t)blockIdx.x)];
+    if (S.precision == NEK_PREC_F64) serve_dispatch<B, double, double>(S, blockIdx.x, lds, red);
+    else if (S.precision == NEK_PREC_F32G32) serve_dispatch<B, float, float>(S, blockIdx.x, lds, red);
+    else serve_dispatch<B, float, uint16_t>(S, blockIdx.x, lds, red);
+}
+
+__global__ void __launch_bounds__(SERVE_THREADS, 4)
+ax_serve_kernel(const ServeAxSlot *__restrict__ slots, int nslots)
+{
+    extern __shared__ __align__(16) char serve_lds[];
+    __shared__ double red[SERVE_THREADS / 64];
+    serve_body<false>(slots, nslots, serve_lds, red);
+}
+
+__global__ void __launch_bounds__(SERVE_THREADS, 2)
+ax_serve_hi_kernel(const ServeAxSlot *__restrict__ slots, int nslots)
+{
+    extern __shared__ __align__(16) char serve_lds[];
+    __shared__ double red[SERVE_THREADS / 64];
+    serve_body<true>(slots, nslots, serve_lds, red);
 }
 
 template <int NX, typename T, typename GT>
-hipError_t launch_batch(const AxSlot *slots, int nslots, int64_t blocks, hipStream_t s)
-{
-    using S = AxShape<NX, T>;
-    hipLaunchKernelGGL((ax_batch_kernel<NX, T, GT>), dim3((unsigned)blocks), dim3(S::THREADS), 0, s,
-                       slots, nslots);
-    return hipGetLastError();
+void serve_shape_of(int64_t E, ServeAxShape &o) {
+    using H = ServeShape<NX, T, GT>;
+    const int64_t parts = (E + H::S::EPB - 1) / H::S::EPB;
+    o.nparts = parts;
+    o.blocks = (parts + H::PARTS - 1) / H::PARTS;
+    o.lds_bytes = H::LDS_BYTES;
+    o.hi = serve_in_b<NX, T>();
+}
+
+template <typename T, typename GT>
+bool serve_shape_prec(int N, int64_t E, ServeAxShape &o) {
+    switch (N + 1) {
+#define NEK_HCASE(NX) \
+    case NX: serve_shape_of<NX, T, GT>(E, o); return true;
+        NEK_HCASE(2) NEK_HCASE(3) NEK_HCASE(4) NEK_HCASE(5) NEK_HCASE(6) NEK_HCASE(7) NEK_HCASE(8)
+        NEK_HCASE(9) NEK_HCASE(10) NEK_HCASE(11) NEK_HCASE(12) NEK_HCASE(13) NEK_HCASE(14)
+        NEK_HCASE(15) NEK_HCASE(16)
+#undef NEK_HCASE
+    default: return false;
+    }
 }
 
 template <int NX, typename T, typename GT>
@@ -535,23 +622,30 @@ __global__ void convert_g_kernel(int64_t E, int64_t n3, const double *__restrict
 
 }  // namespace
 
-hipError_t launch_ax_batch(int N, int precision, const AxSlot *slots, int nslots, int64_t blocks,
+bool serve_ax_shape(int N, int precision, int64_t E, ServeAxShape &out) {
+    if (precision == NEK_PREC_F64) return serve_shape_prec<double, double>(N, E, out);
+    if (precision == NEK_PREC_F32G32) return serve_shape_prec<float, float>(N, E, out);
+    if (precision == NEK_PREC_F32GBF16) return serve_shape_prec<float, uint16_t>(N, E, out);
+    return false;
+}
+
+hipError_t launch_ax_serve(const ServeAxSlot *slots, int nslots, int64_t blocks, size_t lds_bytes, bool hi,
                            hipStream_t s)
 {
-    if (nslots < 1 || nslots > BATCH_MAX_SLOTS || blocks < 1 || blocks > 0x7fffffff)
-        return hipErrorInvalidValue;
-    switch (N + 1) {
-#define NEK_BCASE(NX)                                                                          \
-    case NX:                                                                                   \
-        if (precision == NEK_PREC_F64) return launch_batch<NX, double, double>(slots, nslots, blocks, s); \
-        if (precision == NEK_PREC_F32G32) return launch_batch<NX, float, float>(slots, nslots, blocks, s); \
-        return launch_batch<NX, float, uint16_t>(slots, nslots, blocks, s);
-        NEK_BCASE(2) NEK_BCASE(3) NEK_BCASE(4) NEK_BCASE(5) NEK_BCASE(6) NEK_BCASE(7) NEK_BCASE(8)
-        NEK_BCASE(9) NEK_BCASE(10) NEK_BCASE(11) NEK_BCASE(12) NEK_BCASE(13) NEK_BCASE(14)
-        NEK_BCASE(15) NEK_BCASE(16)
-#undef NEK_BCASE
-    default: return hipErrorInvalidValue;
+    if (nslots < 1 || nslots > BATCH_MAX_SLOTS || blocks < 1 || blocks > 0x7fffffff) return hipErrorInvalidValue;
+    if (lds_bytes > 65536) {
+        // n = 16 in FP64 takes 70 KB of the 160 KB of a CU: allowed once
+        static const hipError_t attr = hipFuncSetAttribute((const void *)ax_serve_hi_kernel,
+                                                           hipFuncAttributeMaxDynamicSharedMemorySize, 163840);
+        if (attr != hipSuccess) return attr;
     }
+    if (hi)
+        hipLaunchKernelGGL(ax_serve_hi_kernel, dim3((unsigned)blocks), dim3(SERVE_THREADS), lds_bytes, s, slots,
+                           nslots);
+    else
+        hipLaunchKernelGGL(ax_serve_kernel, dim3((unsigned)blocks), dim3(SERVE_THREADS), lds_bytes, s, slots,
+                           nslots);
+    return hipGetLastError();
 }
 
 hipError_t launch_ax_f64(int64_t E, int N, const double *D, const double *g, double *p, double *w,

@@ -19,27 +19,29 @@ namespace {
 
 constexpr int node_threads(int nx) { return (nx * nx * nx + 63) / 64 * 64; }
 
+// The operator on element e by the threads of one part of a workgroup: `t`
+// the node of this thread (N3 or more: no node; such threads only take part
+// in the barriers), `L` the part's LDS (4 n^3 + n^2 doubles), `rbase` its
+// first thread for the sum of the partial (`red`: one double per wave of the
+// workgroup).  A plain launch is one part per workgroup.
 template <int NX>
-__global__ void __launch_bounds__(node_threads(NX))
-ax_node_fused_kernel(const double *__restrict__ D_, const double *__restrict__ g_, double *__restrict__ p_,
-                     double *__restrict__ w_, AxFuse fz) {
+__device__ __forceinline__ void node_body(int64_t e, bool real, int t, const AxFuse &fz, const double *D_,
+                                          const double *g_, double *p_, double *w_, double *L, double *red,
+                                          int rbase) {
     constexpr int NN = NX * NX, N3 = NN * NX, NT = node_threads(NX);
     // the CG scalars are written only by other launches
     const kptr<CgScalars> sc = (kptr<CgScalars>)fz.sc;
     // uniform: the CG has finished (tested once the loads are in flight,
     // before the first store)
     const int done = sc->done;
-    __shared__ double su[N3], sr[N3], ss[N3], st[N3], sD[NN];
-    __shared__ double red[NT / 64];
+    double *su = L, *sr = L + N3, *ss = L + 2 * N3, *st = L + 3 * N3, *sD = L + 4 * N3;
     const gptr<const double> D = (gptr<const double>)D_;
     const gptr<double> p = (gptr<double>)p_, w = (gptr<double>)w_;
     const gptr<const double> fr = (gptr<const double>)fz.r;
     const gptr<double> fx = (gptr<double>)fz.x;
     const gptr<const float> fdinv = (gptr<const float>)fz.dinv;
 
-    const int64_t e = blockIdx.x;
-    const int t = threadIdx.x;   // node (i, j, k) in the order of Listing 1
-    const bool on = t < N3;
+    const bool on = real && t < N3;   // node (i, j, k) in the order of Listing 1
     const int i = t % NX, j = (t / NX) % NX, k = t / NN;
     const int64_t at = e * N3 + (int64_t)k * NN + cgl_col(i, j, NX);   // its entry of the CG vectors
 
@@ -103,9 +105,70 @@ ax_node_fused_kernel(const double *__restrict__ D_, const double *__restrict__ g
     }
     // this element's share of sum p (A_L p), as the pencil kernel leaves it
     if (fz.partials != nullptr) {
-        const double bs = block_sum<NT>(pw, red);
-        if (t == 0) ((gptr<double>)fz.partials)[blockIdx.x] = bs;
+        const double bs = seg_sum<NT>(pw, red, rbase);
+        if ((int)threadIdx.x == rbase && real) ((gptr<double>)fz.partials)[e] = bs;
     }
+}
+
+template <int NX>
+constexpr int node_lds() { return 4 * NX * NX * NX + NX * NX; }
+
+template <int NX>
+__global__ void __launch_bounds__(node_threads(NX))
+ax_node_fused_kernel(const double *__restrict__ D, const double *__restrict__ g, double *__restrict__ p,
+                     double *__restrict__ w, AxFuse fz) {
+    __shared__ double L[node_lds<NX>()];
+    __shared__ double red[node_threads(NX) / 64];
+    node_body<NX>(blockIdx.x, true, threadIdx.x, fz, D, g, p, w, L, red, 0);
+}
+
+// The served form's launch (see ServeNodeSlot): several elements per
+// 1024-thread workgroup at n < 10.
+template <int NX>
+__device__ __forceinline__ void node_serve_part(const ServeNodeSlot &S, int64_t wg, double *lds, double *red) {
+    constexpr int NT = node_threads(NX), PARTS = SERVE_NODE_THREADS / NT;
+    const int q = (int)threadIdx.x / NT;
+    const int qc = q < PARTS ? q : PARTS - 1;
+    const int t = q < PARTS ? (int)threadIdx.x - q * NT : NT;
+    const int64_t e = (wg - S.block0) * PARTS + qc;
+    const bool real = e < S.E;
+    node_body<NX>(real ? e : 0, real, t, S.fz, S.D, S.g, S.p, S.w, lds + (size_t)qc * node_lds<NX>(), red,
+                  qc * NT);
+}
+
+// Two kernels: n = 9 needs more than 64 VGPRs (79 in its own kernel), the
+// others fit 64, which lets two 1024-thread workgroups share a CU.
+template <bool N9>
+__device__ __forceinline__ void node_serve_body(const ServeNodeSlot *__restrict__ slots, int nslots, double *lds,
+                                                double *red) {
+    const ServeNodeSlot &S = slots[batch_slot(slots, nslots, (int64_t)blockIdx.x)];
+    if constexpr (N9) {
+        node_serve_part<9>(S, blockIdx.x, lds, red);
+    } else {
+        switch (S.nx) {
+        case 4: node_serve_part<4>(S, blockIdx.x, lds, red); break;
+        case 5: node_serve_part<5>(S, blockIdx.x, lds, red); break;
+        case 6: node_serve_part<6>(S, blockIdx.x, lds, red); break;
+        case 7: node_serve_part<7>(S, blockIdx.x, lds, red); break;
+        case 8: node_serve_part<8>(S, blockIdx.x, lds, red); break;
+        case 10: node_serve_part<10>(S, blockIdx.x, lds, red); break;
+        default: break;
+        }
+    }
+}
+
+__global__ void __launch_bounds__(SERVE_NODE_THREADS, 8)
+ax_node_serve_kernel(const ServeNodeSlot *__restrict__ slots, int nslots) {
+    extern __shared__ __align__(16) double node_serve_lds[];
+    __shared__ double red[SERVE_NODE_THREADS / 64];
+    node_serve_body<false>(slots, nslots, node_serve_lds, red);
+}
+
+__global__ void __launch_bounds__(SERVE_NODE_THREADS)
+ax_node_serve9_kernel(const ServeNodeSlot *__restrict__ slots, int nslots) {
+    extern __shared__ __align__(16) double node_serve_lds[];
+    __shared__ double red[SERVE_NODE_THREADS / 64];
+    node_serve_body<true>(slots, nslots, node_serve_lds, red);
 }
 
 template <int NX>
@@ -117,6 +180,29 @@ hipError_t launch_node(int64_t E, const double *D, const double *g, double *p, d
 }
 
 }  // namespace
+
+bool serve_node_shape(int N, int64_t E, ServeNodeShape &o) {
+    if (N < AX_NODE_MIN_N || N > 9) return false;
+    const int nx = N + 1;
+    const int nt = (nx * nx * nx + 63) / 64 * 64;
+    const int parts = SERVE_NODE_THREADS / nt;
+    o.blocks = (E + parts - 1) / parts;
+    o.lds_bytes = (size_t)parts * (4 * nx * nx * nx + nx * nx) * sizeof(double);
+    o.n9 = N == 8;
+    return true;
+}
+
+hipError_t launch_ax_node_serve(const ServeNodeSlot *slots, int nslots, int64_t blocks, size_t lds_bytes, bool n9,
+                                hipStream_t s) {
+    if (nslots < 1 || nslots > BATCH_MAX_SLOTS || blocks < 1 || blocks > 0x7fffffff) return hipErrorInvalidValue;
+    if (n9)
+        hipLaunchKernelGGL(ax_node_serve9_kernel, dim3((unsigned)blocks), dim3(SERVE_NODE_THREADS), lds_bytes, s,
+                           slots, nslots);
+    else
+        hipLaunchKernelGGL(ax_node_serve_kernel, dim3((unsigned)blocks), dim3(SERVE_NODE_THREADS), lds_bytes, s,
+                           slots, nslots);
+    return hipGetLastError();
+}
 
 bool ax_node_fused_fits(int64_t E, int N) {
     return N >= AX_NODE_MIN_N && N <= 9 && E >= 1 && E <= AX_NODE_MAX_POINTS / n3_of(N);

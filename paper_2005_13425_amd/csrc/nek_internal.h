@@ -142,18 +142,59 @@ __device__ __forceinline__ int batch_slot(const Slot *__restrict__ slots, int ns
     return __popcll(__ballot(before)) - 1;
 }
 
-// One solve inside a launch that serves several (same degree and precision).
-struct AxSlot {
+// One solve in a merged operator launch of the served form (any degree and
+// precision; see ax_serve_kernel).
+constexpr int SERVE_THREADS = 256;
+struct ServeAxSlot {
     int64_t block0;      // first workgroup of this solve in the launch
     int64_t E;
+    int nx;              // N + 1
+    int precision;       // NEK_PREC_*
     const void *D;       // double or float, by precision
     const void *g;       // FP64 g, or the paired FP32 / BF16 copy
     double *p;
     double *w;
     AxFuse fz;
 };
-hipError_t launch_ax_batch(int N, int precision, const AxSlot *slots, int nslots, int64_t blocks,
+// A solve's share of a merged operator launch: its workgroups, the partials
+// it leaves (those of its own launch, ax_blocks), the LDS its workgroups use
+// and which of the two merged kernels runs it (hi: the FP64 shapes that need
+// more registers than four waves per SIMD allow; see ax_serve_kernel).
+struct ServeAxShape {
+    int64_t blocks = 0;
+    int64_t nparts = 0;
+    size_t lds_bytes = 0;
+    bool hi = false;
+};
+bool serve_ax_shape(int N, int precision, int64_t E, ServeAxShape &out);
+hipError_t launch_ax_serve(const ServeAxSlot *slots, int nslots, int64_t blocks, size_t lds_bytes, bool hi,
                            hipStream_t s);
+
+// The one-thread-per-node operator of the served form: every small FP64
+// solve (ax_node_fused_fits) in one launch of 1024-thread workgroups, each
+// holding 1024 / node_threads parts (elements); part q of workgroup b is
+// element (b - block0) * parts + q of the solve, with the partial of the
+// solve's own launch.
+constexpr int SERVE_NODE_THREADS = 1024;
+struct ServeNodeSlot {
+    int64_t block0;
+    int64_t E;
+    int nx;
+    int pad_;
+    const double *D;
+    const double *g;
+    double *p;
+    double *w;
+    AxFuse fz;
+};
+struct ServeNodeShape {
+    int64_t blocks = 0;
+    size_t lds_bytes = 0;
+    bool n9 = false;     // n = 9 runs in a kernel of its own (more registers)
+};
+bool serve_node_shape(int N, int64_t E, ServeNodeShape &out);
+hipError_t launch_ax_node_serve(const ServeNodeSlot *slots, int nslots, int64_t blocks, size_t lds_bytes, bool n9,
+                                hipStream_t s);
 
 hipError_t launch_convert_g(int64_t E, int N, const double *g, int g_dtype, void *out, hipStream_t s);
 

@@ -46,6 +46,26 @@ __device__ __forceinline__ double block_sum(double v, double *lds) {
     return s;
 }
 
+// Sum over the NT threads [base, base + NT) of a workgroup that holds several
+// independent parts (NT and base multiples of 64); valid in thread base.  lds
+// must hold one double per wave of the whole workgroup, and every thread of
+// the workgroup calls it (two barriers).  For base = 0 in a workgroup of NT
+// threads it is block_sum<NT>, operation for operation.
+template <int NT>
+__device__ __forceinline__ double seg_sum(double v, double *lds, int base) {
+    v = wave_sum(v);
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    if (lane == 0) lds[wave] = v;
+    __syncthreads();
+    double s = 0.0;
+    if ((int)threadIdx.x == base) {
+#pragma unroll
+        for (int q = 0; q < NT / 64; ++q) s += lds[base / 64 + q];
+    }
+    __syncthreads();
+    return s;
+}
+
 __device__ __forceinline__ double load_coherent(gptr<const double> p) {
     unsigned long long bits =
         __hip_atomic_load((gptr<const unsigned long long>)p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);

@@ -1,10 +1,12 @@
 // server.hip -- served Poisson solves: requests arrive over time, are admitted
 // when their whole device footprint fits the budget, keep their CG state
-// resident, and advance together: every step runs CG iterations of all
-// admitted solves with one operator and one assemble-update launch per
-// (degree, precision, size) group.  A solve's workgroups do exactly what its own
-// launch would do (per-solve reductions and tickets), so its result does not
-// depend on which other solves share the launches.
+// resident, and advance together: a CG iteration of every admitted solve, of
+// any degree and precision, is one merged operator launch (plus one for the
+// small FP64 solves that take the one-thread-per-node operator, and one for
+// degrees above 11) and one assemble-update launch.  A solve's workgroups do
+// exactly what its own launch would do (per-solve partials, reductions and
+// tickets), so its result does not depend on which other solves share the
+// launches.
 #include <math.h>
 #include <string.h>
 
@@ -147,62 +149,56 @@ struct TableSet {       // slot tables of one step, host (pinned) and device
     bool used = false;
 };
 
-struct Group {
-    int N, precision, size_class;
-    int first, count;            // range in the slot tables
-    int64_t ax_blocks, asm_blocks;
-    int64_t points;              // local points of its solves
-    int extra = 0;               // iterations per step beyond the common count
-};
-
-// Solves of similar size share a group: a class spans a factor of 4 in local
-// points.
-int size_class(int64_t P) {
-    int c = 0;
-    while (P >= 4) {
-        P >>= 2;
-        ++c;
-    }
-    return c;
-}
-
-// Extra iterations per step for cheap groups.  A group costs about its local
-// points plus the launch overhead of its three kernels (worth about 0.5 M
-// points); every group runs `iters` iterations, then a budget of half the
-// heaviest group's step goes, cheapest group first, to up to 7 * iters more.
-// Small solves no longer move at the pace of the largest ones, and the step
-// grows by at most half.
+// Iterations per server iteration: a solve of weight w takes part in the
+// first w of up to MAX_ITER_WEIGHT rounds of launches, so small solves do not
+// move at the pace of the largest ones.  A solve's iteration costs about its
+// local points; a round of launches about LAUNCH_POINTS more (its fixed
+// launch and reduction latency).  A solve gets weight min(8, cmax / (2 P))
+// (cmax the costliest solve), and the top levels are dropped until the extra
+// rounds cost at most half of the first one.
 constexpr int64_t LAUNCH_POINTS = 500000;
 constexpr int MAX_ITER_WEIGHT = 8;
 
-void assign_extra(std::vector<Group> &groups, int iters) {
-    if (groups.size() < 2) {
-        for (Group &G : groups) G.extra = 0;
-        return;
+int assign_weights(const std::vector<int64_t> &points, std::vector<int> &wt) {
+    const size_t n = points.size();
+    wt.assign(n, 1);
+    if (n < 2) return 1;
+    int64_t cmax = 0, total = 0;
+    for (int64_t p : points) {
+        cmax = std::max(cmax, p);
+        total += p;
     }
-    std::vector<int> order(groups.size());
-    int64_t cmax = 0;
-    for (size_t g = 0; g < groups.size(); ++g) {
-        order[g] = (int)g;
-        groups[g].extra = 0;
-        cmax = std::max(cmax, groups[g].points + LAUNCH_POINTS);
+    int wmax = 1;
+    for (size_t i = 0; i < n; ++i) {
+        const int64_t w = cmax / (2 * std::max<int64_t>(points[i], 1));
+        wt[i] = (int)std::min<int64_t>(MAX_ITER_WEIGHT, std::max<int64_t>(1, w));
+        wmax = std::max(wmax, wt[i]);
     }
-    std::stable_sort(order.begin(), order.end(),
-                     [&](int a, int b) { return groups[a].points < groups[b].points; });
-    int64_t budget = (int64_t)iters * cmax / 2;
-    for (int g : order) {
-        const int64_t c = groups[g].points + LAUNCH_POINTS;
-        if (c >= cmax) continue;
-        const int64_t want = (int64_t)(MAX_ITER_WEIGHT - 1) * iters;
-        const int64_t can = budget / c;
-        const int64_t e = want < can ? want : can;
-        groups[g].extra = (int)e;
-        budget -= e * c;
+    const int64_t budget = (total + LAUNCH_POINTS) / 2;
+    for (; wmax > 1; --wmax) {
+        int64_t extra = 0;
+        for (int j = 1; j < wmax; ++j) {
+            extra += LAUNCH_POINTS;
+            for (size_t i = 0; i < n; ++i)
+                if (std::min(wt[i], wmax) > j) extra += points[i];
+        }
+        if (extra <= budget) break;
     }
+    for (int &w : wt) w = std::min(w, wmax);
+    return wmax;
 }
 
+// One of the launches of a round: its table (slots in weight order, so the
+// solves of round j are a prefix of it) and, per round, the prefix's slot
+// count, workgroups and LDS.
+struct LaunchPlan {
+    int count[MAX_ITER_WEIGHT] = {};
+    int64_t blocks[MAX_ITER_WEIGHT] = {};
+    size_t lds[MAX_ITER_WEIGHT] = {};
+};
+
 constexpr size_t TABLE_BYTES =
-    MAX_SLOTS * (sizeof(AxSlot) + sizeof(AsmSlot) + sizeof(CgScalars *));
+    MAX_SLOTS * (2 * sizeof(ServeAxSlot) + 2 * sizeof(ServeNodeSlot) + sizeof(AsmSlot) + sizeof(CgScalars *));
 
 }  // namespace
 }  // namespace nek
@@ -237,7 +233,11 @@ struct nek_server {
     TableSet tables[2];
     int cur_table = 0;
     bool dirty = true;
-    std::vector<Group> groups;
+    // the launches of a round: the two merged pencil operators, the two
+    // node operators (n = 9 apart), the assemble-update
+    enum { L_PEN, L_PEN_HI, L_NODE, L_NODE9, L_ASM, N_LAUNCH };
+    LaunchPlan plan[N_LAUNCH];
+    int wmax = 1;
     std::vector<Slot *> table_slots;                  // slots of the current tables, in order
     // status snapshots, one step behind
     CgScalars *status_dev[2] = {nullptr, nullptr};
@@ -493,41 +493,89 @@ struct nek_server {
         std::vector<Slot *> act;
         for (auto &s : slots)
             if (s->state == ACTIVE) act.push_back(s.get());
-        std::stable_sort(act.begin(), act.end(), [](const Slot *a, const Slot *b) {
-            if (a->req->spec.N != b->req->spec.N) return a->req->spec.N < b->req->spec.N;
-            if (a->req->spec.precision != b->req->spec.precision)
-                return a->req->spec.precision < b->req->spec.precision;
-            return size_class(a->req->P) < size_class(b->req->P);
-        });
-        AxSlot *ax = (AxSlot *)T.host;
-        AsmSlot *asl = (AsmSlot *)(T.host + MAX_SLOTS * sizeof(AxSlot));
-        CgScalars **scp = (CgScalars **)(T.host + MAX_SLOTS * (sizeof(AxSlot) + sizeof(AsmSlot)));
-        groups.clear();
-        for (size_t i = 0; i < act.size(); ++i) {
+        std::vector<int64_t> pts;
+        for (Slot *S : act) pts.push_back(S->req->P);
+        std::vector<int> wt;
+        wmax = assign_weights(pts, wt);
+        // heaviest weight first: the solves of round j are those of weight > j
+        std::vector<size_t> order(act.size());
+        for (size_t i = 0; i < order.size(); ++i) order[i] = i;
+        std::stable_sort(order.begin(), order.end(), [&](size_t a, size_t b) { return wt[a] > wt[b]; });
+        ServeAxSlot *pen = (ServeAxSlot *)T.host;
+        ServeAxSlot *pen_hi = pen + MAX_SLOTS;
+        ServeNodeSlot *node = (ServeNodeSlot *)(pen_hi + MAX_SLOTS);
+        ServeNodeSlot *node9 = node + MAX_SLOTS;
+        AsmSlot *asl = (AsmSlot *)(node9 + MAX_SLOTS);
+        CgScalars **scp = (CgScalars **)(asl + MAX_SLOTS);
+        int cnt[N_LAUNCH] = {};
+        int64_t blk[N_LAUNCH] = {};
+        size_t lds[N_LAUNCH] = {};
+        for (LaunchPlan &L : plan) L = LaunchPlan{};
+        std::vector<Slot *> ordered;
+        // close round j of every launch: the prefix so far is what it runs
+        auto close_rounds = [&](int from, int to) {
+            for (int j = from; j < to; ++j)
+                for (int l = 0; l < N_LAUNCH; ++l) {
+                    plan[l].count[j] = cnt[l];
+                    plan[l].blocks[j] = blk[l];
+                    plan[l].lds[j] = lds[l];
+                }
+        };
+        int prev_w = MAX_ITER_WEIGHT;
+        for (size_t oi = 0; oi < order.size(); ++oi) {
+            const size_t i = order[oi];
             Slot *S = act[i];
+            // rounds j >= wt[i] hold only the solves before this one
+            if (wt[i] < prev_w) close_rounds(wt[i], prev_w);
+            prev_w = wt[i];
             const nek_request &q = S->req->spec;
-            const int cls = size_class(S->req->P);
-            if (groups.empty() || groups.back().N != q.N || groups.back().precision != q.precision ||
-                groups.back().size_class != cls)
-                groups.push_back({q.N, q.precision, cls, (int)i, 0, 0, 0, 0, 0});
-            Group &G = groups.back();
-            G.points += S->req->P;
+            const int64_t E = S->req->E;
             const bool mixed = is_mixed(q.precision);
-            AxSlot &A = ax[i];
-            A.block0 = G.ax_blocks;
-            A.E = S->req->E;
-            A.D = mixed ? (const void *)S->D32 : (const void *)S->D;
-            A.g = mixed ? (const void *)S->glo : (const void *)S->g;
-            A.p = S->W.p;
-            A.w = S->W.w;
-            A.fz.r = S->W.r;
-            A.fz.x = S->x;
-            A.fz.partials = S->W.axp;
-            A.fz.sc = S->W.sc;
-            A.fz.cg_layout = true;
-            G.ax_blocks += ax_blocks(S->req->E, q.N);
-            AsmSlot &U = asl[i];
-            U.block0 = G.asm_blocks;
+            int64_t nparts;
+            AxFuse fz;
+            fz.r = S->W.r;
+            fz.x = S->x;
+            fz.partials = S->W.axp;
+            fz.sc = S->W.sc;
+            fz.cg_layout = true;
+            // the operator nek_cg_solve would run (bitwise the same solve)
+            if (!mixed && ax_node_fused_fits(E, q.N)) {
+                ServeNodeShape sh;
+                if (!serve_node_shape(q.N, E, sh)) return fail(NEK_ERR_STATE, "server: no node shape");
+                const int l = sh.n9 ? L_NODE9 : L_NODE;
+                ServeNodeSlot &A = (sh.n9 ? node9 : node)[cnt[l]++];
+                A.block0 = blk[l];
+                A.E = E;
+                A.nx = q.N + 1;
+                A.pad_ = 0;
+                A.D = S->D;
+                A.g = S->g;
+                A.p = S->W.p;
+                A.w = S->W.w;
+                A.fz = fz;
+                blk[l] += sh.blocks;
+                lds[l] = std::max(lds[l], sh.lds_bytes);
+                nparts = E;
+            } else {
+                ServeAxShape sh;
+                if (!serve_ax_shape(q.N, q.precision, E, sh)) return fail(NEK_ERR_STATE, "server: no operator shape");
+                const int l = sh.hi ? L_PEN_HI : L_PEN;
+                ServeAxSlot &A = (sh.hi ? pen_hi : pen)[cnt[l]++];
+                A.block0 = blk[l];
+                A.E = E;
+                A.nx = q.N + 1;
+                A.precision = q.precision;
+                A.D = mixed ? (const void *)S->D32 : (const void *)S->D;
+                A.g = mixed ? (const void *)S->glo : (const void *)S->g;
+                A.p = S->W.p;
+                A.w = S->W.w;
+                A.fz = fz;
+                blk[l] += sh.blocks;
+                lds[l] = std::max(lds[l], sh.lds_bytes);
+                nparts = sh.nparts;
+            }
+            AsmSlot &U = asl[cnt[L_ASM]++];
+            U.block0 = blk[L_ASM];
             U.nblocks = asm_blocks(S->gsd);
             U.P = S->req->P;
             U.args = S->gsd.args;
@@ -535,19 +583,20 @@ struct nek_server {
             U.r = S->W.r;
             U.w = S->W.w;
             U.axparts = S->W.axp;
-            U.nparts = ax_blocks(S->req->E, q.N);
+            U.nparts = nparts;
             U.red = S->W.site(SITE_UPDATE);
             U.sc = S->W.sc;
-            G.asm_blocks += U.nblocks;
-            scp[i] = S->W.sc;
-            G.count++;
+            blk[L_ASM] += U.nblocks;
+            scp[ordered.size()] = S->W.sc;
+            ordered.push_back(S);
         }
+        close_rounds(0, prev_w);
         NEK_HIP(hipMemcpyAsync(T.dev, T.host, TABLE_BYTES, hipMemcpyHostToDevice, stream));
         // the set in use until now may be rewritten once the work queued so far is done
         if (tables[cur_table].used) NEK_HIP(hipEventRecord(tables[cur_table].ev, stream));
         T.used = true;
         cur_table = k;
-        table_slots = act;
+        table_slots = ordered;
         dirty = false;
         return NEK_OK;
     }
@@ -654,15 +703,24 @@ struct nek_server {
         }
         if (!table_slots.empty()) {
             const TableSet &T = tables[cur_table];
-            const AxSlot *ax = (const AxSlot *)T.dev;
-            const AsmSlot *asl = (const AsmSlot *)(T.dev + MAX_SLOTS * sizeof(AxSlot));
-            CgScalars *const *scp = (CgScalars *const *)(T.dev + MAX_SLOTS * (sizeof(AxSlot) + sizeof(AsmSlot)));
+            const ServeAxSlot *pen = (const ServeAxSlot *)T.dev;
+            const ServeAxSlot *pen_hi = pen + MAX_SLOTS;
+            const ServeNodeSlot *node = (const ServeNodeSlot *)(pen_hi + MAX_SLOTS);
+            const ServeNodeSlot *node9 = node + MAX_SLOTS;
+            const AsmSlot *asl = (const AsmSlot *)(node9 + MAX_SLOTS);
+            CgScalars *const *scp = (CgScalars *const *)(asl + MAX_SLOTS);
             const int base_iters = std::max(1, iters);
-            assign_extra(groups, base_iters);
-            for (const Group &G : groups) {
-                for (int it = 0; it < base_iters + G.extra; ++it) {
-                    NEK_HIP(launch_ax_batch(G.N, G.precision, ax + G.first, G.count, G.ax_blocks, stream));
-                    NEK_HIP(launch_assemble_update_batch(asl + G.first, G.count, G.asm_blocks, stream));
+            for (int it = 0; it < base_iters; ++it) {
+                for (int j = 0; j < wmax; ++j) {
+                    const LaunchPlan &A = plan[L_PEN], &H = plan[L_PEN_HI], &V = plan[L_NODE], &V9 = plan[L_NODE9],
+                                     &U = plan[L_ASM];
+                    if (A.count[j]) NEK_HIP(launch_ax_serve(pen, A.count[j], A.blocks[j], A.lds[j], false, stream));
+                    if (H.count[j]) NEK_HIP(launch_ax_serve(pen_hi, H.count[j], H.blocks[j], H.lds[j], true, stream));
+                    if (V.count[j])
+                        NEK_HIP(launch_ax_node_serve(node, V.count[j], V.blocks[j], V.lds[j], false, stream));
+                    if (V9.count[j])
+                        NEK_HIP(launch_ax_node_serve(node9, V9.count[j], V9.blocks[j], V9.lds[j], true, stream));
+                    if (U.count[j]) NEK_HIP(launch_assemble_update_batch(asl, U.count[j], U.blocks[j], stream));
                 }
             }
             // snapshot of every active solve's scalars into buffer q; the snapshot

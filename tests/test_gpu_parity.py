@@ -290,11 +290,12 @@ def test_bw_probe_sums_its_streams(nek, streaming):
         for k in range(nread):
             ref = ref + src[k * stride:k * stride + n]
         np.testing.assert_array_equal(dst.cpu().numpy(), ref)
-    # a capped grid walks the rest with a stride
-    src = rng.uniform(-1, 1, 3 * 300001)
-    dst = torch.empty(300001, dtype=torch.float64, device="cuda")
-    nek.bw_probe(_dev(src), dst, 3, grid_cap=7, streaming=streaming)
-    ref = src[:300001] + src[300001:600002] + src[600002:]
+    # a capped grid walks the rest with a stride (streams 16-byte aligned: even stride)
+    n, stride = 300001, 300002
+    src = rng.uniform(-1, 1, 2 * stride + n)
+    dst = torch.empty(n, dtype=torch.float64, device="cuda")
+    nek.bw_probe(_dev(src), dst, 3, stride=stride, grid_cap=7, streaming=streaming)
+    ref = src[:n] + src[stride:stride + n] + src[2 * stride:2 * stride + n]
     np.testing.assert_array_equal(dst.cpu().numpy(), ref)
 
 
@@ -304,7 +305,7 @@ def test_bw_probe_read_only_partials(nek, streaming):
     # (the last value left out for odd n)
     rng = np.random.default_rng(10)
     for nread, n, cap in ((7, 40000, 0), (7, 300001, 13), (2, 5000, 1)):
-        stride = n + 33
+        stride = (n + 34) // 2 * 2          # even: the streams stay 16-byte aligned
         src = rng.uniform(-1, 1, (nread - 1) * stride + n)
         groups = nek.bw_probe_groups(n, cap)
         dst = torch.empty(groups, dtype=torch.float64, device="cuda")
