@@ -248,6 +248,28 @@ int nek_cg_solve(int64_t E, int N, const double *D, const double *g, const nek_g
                  const double *b, double *x, const nek_cg_opts *opts, nek_cg_stats *stats,
                  void *stream);
 
+/* For callers that cannot allocate device or pinned host memory (code under
+ * stream capture, tight serving loops, harnesses that forbid allocation):
+ * nek_cg_solve with its workspace (r, p, w, b and M^-1 in the CG layout, the
+ * operator's partials, the reduction sites and counters, the CG scalars) in a
+ * file-scope device array of NEK_CG_NOALLOC_BYTES bytes inside the library,
+ * one per GPU, held until the process ends.  The caller passes D, g, gs, b, x
+ * and stream as for nek_cg_solve; opts->workspace must be NULL.  The call
+ * makes no device or host allocation: the host polls the status word into
+ * its own stack with a synchronous copy (no events, no pinned buffer).
+ * Returns NEK_ERR_ARG, with a message, when the solve needs more than
+ * NEK_CG_NOALLOC_BYTES (about 2 M local points in FP64 without a
+ * preconditioner: E = 2048 at N = 9).  Every call on a GPU uses that GPU's
+ * one array and finds there what the last call left: the solver sets every
+ * word it reads first (counters and scalars by its reset kernel), so no state
+ * carries over, but calls that overlap on one GPU (two host threads, or
+ * two streams) race on the array and must be serialised by the caller.
+ * Results are bitwise those of nek_cg_solve with the same arguments. */
+#define NEK_CG_NOALLOC_BYTES ((size_t)64 << 20)
+int nek_cg_solve_noalloc(int64_t E, int N, const double *D, const double *g, const nek_gs *gs,
+                         const double *b, double *x, const nek_cg_opts *opts, nek_cg_stats *stats,
+                         void *stream);
+
 /* Jacobi preconditioner of the assembled, masked operator: on device
  * dinv[P], 1 / (dssum of the diagonals of the element operators of Listing 1)
  * at free nodes and 0 at masked nodes, a continuous local vector.  The

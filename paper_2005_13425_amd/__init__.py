@@ -122,6 +122,11 @@ _sig("nek_cg_default_opts", None, [ctypes.POINTER(CgOpts)])
 _sig("nek_cg_workspace_bytes", ctypes.c_size_t, [_i64, _ci])
 _sig("nek_cg_solve", _ci, [_i64, _ci, _vp, _vp, _vp, _vp, _vp, ctypes.POINTER(CgOpts),
                            ctypes.POINTER(CgStats), _vp])
+_sig("nek_cg_solve_noalloc", _ci, [_i64, _ci, _vp, _vp, _vp, _vp, _vp, ctypes.POINTER(CgOpts),
+                                   ctypes.POINTER(CgStats), _vp])
+
+# workspace bytes of nek_cg_solve_noalloc's device array (NEK_CG_NOALLOC_BYTES)
+CG_NOALLOC_BYTES = 64 << 20
 
 
 class NekError(RuntimeError):
@@ -414,6 +419,20 @@ def cg_solve(D, g, gs: GatherScatter, b, x=None, max_iter: int = 100, rel_tol: f
     non-convergence is reported in CgResult.status instead of raising."""
     return _cg_call(_lib.nek_cg_solve, "nek_cg_solve", D, g, gs, b, x, max_iter, rel_tol, precision, D32, g_lo,
                     check_every, true_residual, reliable_drop, workspace, raise_on_error, stream, dinv)
+
+
+def cg_solve_noalloc(D, g, gs: GatherScatter, b, x, max_iter: int = 100, rel_tol: float = 0.0,
+                     precision: int = NEK_PREC_F64, D32=None, g_lo=None, check_every: int = 0,
+                     true_residual: bool = False, reliable_drop: float = 0.0, raise_on_error: bool = True,
+                     stream=None, dinv=None):
+    """cg_solve with the library's own fixed device workspace (CG_NOALLOC_BYTES
+    per GPU): the call allocates nothing, so x must be given.  Calls that
+    overlap on one GPU share that workspace and must not overlap."""
+    if x is None:
+        raise ValueError("cg_solve_noalloc: x must be given (the call allocates nothing)")
+    return _cg_call(_lib.nek_cg_solve_noalloc, "nek_cg_solve_noalloc", D, g, gs, b, x, max_iter, rel_tol,
+                    precision, D32, g_lo, check_every, true_residual, reliable_drop, None, raise_on_error,
+                    stream, dinv)
 
 
 def jacobi_inverse(D, g, gs: GatherScatter, out=None, stream=None):

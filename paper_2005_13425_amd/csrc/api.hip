@@ -877,3 +877,66 @@ int nek_cg_solve(int64_t E, int N, const double *D, const double *g, const nek_g
 }
 
 }  // extern "C"
+
+// ---------------------------------------------------------------- CG without allocation
+// The workspace of nek_cg_solve_noalloc.  In host code `scratch` names a
+// host-side stand-in, not device memory: only the address that
+// hipGetSymbolAddress returns for the current device is ever handed to a
+// kernel or a copy.
+static __device__ __align__(256) char scratch[NEK_CG_NOALLOC_BYTES];
+
+namespace {
+constexpr int MAX_DEVICES = 64;
+std::mutex g_scratch_mu;
+char *g_scratch_dev[MAX_DEVICES] = {};
+
+// The device address of `scratch` on the current device, looked up once per
+// device with that device current.
+int scratch_address(char **out) {
+    int dev = -1;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return check_hip(e, "nek_cg_solve_noalloc: hipGetDevice");
+    if (dev < 0 || dev >= MAX_DEVICES) return fail(NEK_ERR_DEVICE, "nek_cg_solve_noalloc: device ordinal out of range");
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_dev[dev]) {
+        void *p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return check_hip(e, "nek_cg_solve_noalloc: hipGetSymbolAddress");
+        if (!p || ((uintptr_t)p & 255u)) return fail(NEK_ERR_DEVICE, "nek_cg_solve_noalloc: workspace symbol not 256-byte aligned");
+        g_scratch_dev[dev] = (char *)p;
+    }
+    *out = g_scratch_dev[dev];
+    return NEK_OK;
+}
+}  // namespace
+
+extern "C" int nek_cg_solve_noalloc(int64_t E, int N, const double *D, const double *g, const nek_gs *gs,
+                                    const double *b, double *x, const nek_cg_opts *opts_in, nek_cg_stats *st,
+                                    void *stream_v) {
+    clear_error();
+    nek_cg_opts opts;
+    if (opts_in) opts = *opts_in;
+    else nek_cg_default_opts(&opts);
+    cg_stats_init(st);
+    if (opts.workspace) return fail(NEK_ERR_ARG, "nek_cg_solve_noalloc: takes no workspace (opts->workspace must be NULL)");
+    CgPlan pl;
+    int rc = cg_check("nek_cg_solve_noalloc", E, N, D, g, gs, b, x, opts, pl);
+    if (rc != NEK_OK) return rc;
+    if (pl.need > NEK_CG_NOALLOC_BYTES)
+        return fail(NEK_ERR_ARG, "nek_cg_solve_noalloc: the solve needs " + std::to_string(pl.need) +
+                                     " bytes of workspace, more than NEK_CG_NOALLOC_BYTES = " +
+                                     std::to_string((size_t)NEK_CG_NOALLOC_BYTES));
+    char *ws = nullptr;
+    rc = scratch_address(&ws);
+    if (rc != NEK_OK) return rc;
+    CgScalars snap[4];   // polled with synchronous copies into pageable memory
+    CgScalars S;
+    double true_rel = -1.0;
+    rc = cg_run(E, N, D, g, gs, b, x, opts, pl, ws, snap, false, (hipStream_t)stream_v, S, true_rel);
+    if (rc != NEK_OK) {
+        (void)hipStreamSynchronize((hipStream_t)stream_v);
+        if (st) st->status = rc;
+        return rc;
+    }
+    return cg_report("nek_cg_solve_noalloc", opts, pl, S, true_rel, st);
+}
