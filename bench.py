@@ -449,13 +449,16 @@ def staggered_stride(n):
     return s
 
 
-def probe_rate(nek, torch, dev, stream, n, nread, stride, grid, streaming, read_only, reps=40):
+def probe_rate(nek, torch, dev, stream, n, nread, stride, grid, streaming, read_only, reps=40, blocked=False):
     """HBM rate of one probe shape: two buffer sets rotating (cold), `reps`
-    launches between HIP events on the launch stream; bytes read + written."""
+    launches between HIP events on the launch stream; bytes read + written.
+    blocked: the read streams interleaved in blocks of one workgroup pass."""
     import ctypes
     sp = ctypes.c_void_p(stream.cuda_stream)
-    flags = (nek.NEK_PROBE_NT if streaming else 0) | (nek.NEK_PROBE_READ_ONLY if read_only else 0)
-    srcs = [torch.empty((nread - 1) * stride + n, dtype=torch.float64, device=dev).uniform_() for _ in range(2)]
+    flags = ((nek.NEK_PROBE_NT if streaming else 0) | (nek.NEK_PROBE_READ_ONLY if read_only else 0) |
+             (nek.NEK_PROBE_BLOCKED if blocked else 0))
+    nsrc = nek.bw_probe_src_doubles(n, nread, stride, blocked)
+    srcs = [torch.empty(nsrc, dtype=torch.float64, device=dev).uniform_() for _ in range(2)]
     dsts = [torch.empty(n, dtype=torch.float64, device=dev) for _ in range(2)]
     ptrs = [(ctypes.c_void_p(srcs[q].data_ptr()), ctypes.c_void_p(dsts[q].data_ptr())) for q in range(2)]
     pr = nek._lib.nek_bw_probe
@@ -477,20 +480,22 @@ def probe_rate(nek, torch, dev, stream, n, nread, stride, grid, streaming, read_
 def probe_sweep(nek, torch, dev, stream, n, grids=(0, 1024, 2048, 4096, 8192)):
     """The probes at one footprint: 7 read streams + 1 write stream (the
     operator's mix), 7 read streams alone, and a copy; plain and non-temporal;
-    streams a power of two apart (aliased) and staggered; one pass or a
-    capped grid striding over the data.  Every rate and the best of each kind."""
+    streams a power of two apart (aliased), staggered, or interleaved in
+    blocks of one workgroup pass (blocked, as the operator reads an element's
+    u and factor planes); one pass or a capped grid striding over the data.
+    Every rate and the best of each kind."""
     st = staggered_stride(n)
     rows = []
     for nread, ro in ((7, False), (7, True), (1, False)):
         for streaming in (False, True):
-            for stride, sname in ((n, "aliased"), (st, "staggered")):
-                if nread == 1 and sname == "staggered":
+            for stride, sname in ((n, "aliased"), (st, "staggered"), (n, "blocked")):
+                if nread == 1 and sname != "aliased":
                     continue
                 for grid in grids:
                     rows.append({"reads": nread, "write": not ro, "nontemporal": streaming, "streams": sname,
                                  "grid": grid or "one pass",
                                  "gbs": round(probe_rate(nek, torch, dev, stream, n, nread, stride, grid,
-                                                         streaming, ro), 1)})
+                                                         streaming, ro, blocked=sname == "blocked"), 1)})
     torch.cuda.empty_cache()
     best = lambda f: max((r for r in rows if f(r)), key=lambda r: r["gbs"])
     b7 = best(lambda r: r["reads"] == 7 and r["write"])
@@ -533,8 +538,10 @@ def sweep_leg(nek, torch, dev, stream, reps=20):
         torch.cuda.synchronize()
         per = np.array([1e3 * evs[r].elapsed_time(evs[r + 1]) for r in range(reps)])
         del g, u, w
-        probe_gbs = max(probe_rate(nek, torch, dev, stream, P, 7, stride, 0, streaming, False, reps)
-                        for streaming in (False, True) for stride in (P, staggered_stride(P)))
+        probe_gbs = max(probe_rate(nek, torch, dev, stream, P, 7, stride, 0, streaming, False, reps,
+                                   blocked=blocked)
+                        for streaming in (False, True)
+                        for stride, blocked in ((P, False), (staggered_stride(P), False), (P, True)))
         torch.cuda.empty_cache()
         t = float(per.mean()) * 1e-6
         gbs = 64 * P / t / 1e9

@@ -192,10 +192,12 @@ typedef struct {
     int precision;         /* NEK_PREC_* */
     const float *D32;      /* FP32 copy of D (device), required for NEK_PREC_F32G* */
     const void *g_lo;      /* g as FP32 / BF16 (device), required for NEK_PREC_F32G* */
-    int check_every;       /* host polls convergence every this many iterations (0: 25) */
+    int check_every;       /* host polls convergence every this many iterations (0: 25;
+                              4 in the mixed precisions) */
     int true_residual;     /* 1: report ||b - A x|| / ||b|| computed in FP64 at the end */
     double reliable_drop;  /* NEK_PREC_F32G*: replace r by b - A64 x whenever ||r|| fell
-                              by this factor since the last replacement (0: 0.3) */
+                              by this factor since the last replacement (0: 0.1 with
+                              FP32 g, 0.3 with BF16 g) */
     void *workspace;       /* device scratch of nek_cg_workspace_bytes() bytes, or NULL
                               to let the call allocate and free its own */
     size_t workspace_bytes;
@@ -288,9 +290,12 @@ int nek_jacobi_inverse(int64_t E, int N, const double *D, const double *g, const
  * server builds, or the caller's own arrays) arrive over time; each is
  * admitted when its whole device footprint fits in the HBM budget, its CG
  * state then stays resident, and every server step advances all admitted
- * solves by CG iterations in shared launches (one operator and one
- * assemble-update launch per (degree, precision, size) group).  Each solve's
- * arithmetic is the same as when it runs alone.  The method is the one of
+ * solves by CG iterations in shared launches: a CG iteration of every solve,
+ * whatever its degree and precision, is one merged operator launch (two when
+ * FP64 solves of the register-hungry degrees are present, one more for small
+ * FP64 solves, which take the one-thread-per-node operator) and one
+ * assemble-update launch.  Each solve's arithmetic is the same as when it
+ * runs alone, and an FP64 solve's is that of nek_cg_solve.  The method is the one of
  * nek_cg_solve (Sec. III, Sec. V); the service around it is not in the
  * paper. */
 
@@ -369,9 +374,9 @@ size_t nek_server_footprint_mesh(int64_t E, int N, int precision);
 /* One step: admit prepared requests in arrival order while they fit (a
  * request still being prepared does not hold back prepared ones behind it; a
  * prepared one that does not fit holds back all later ones), run at least
- * `iters` CG iterations of every admitted solve (solves are grouped by degree,
- * precision and size; groups much cheaper than the heaviest get up to 8 times
- * as many, within half the heaviest group's time), and retire solves whose
+ * `iters` CG iterations of every admitted solve (a solve much cheaper than
+ * the heaviest takes part in up to 8 rounds of launches per iteration, within
+ * half the first round's cost), and retire solves whose
  * completion the step observed.  active / queued (may be NULL) receive the
  * number of admitted and waiting requests after the step.  Returns after
  * queueing the device work (it waits only for the device work of the step
@@ -406,6 +411,12 @@ int nek_server_destroy(nek_server *srv);
  *     leaves out the last value when n is odd).
  *   NEK_PROBE_NT: the loads and stores carry the non-temporal hint (as the
  *     plain FP64 operator's do from N = 7 up).
+ *   NEK_PROBE_BLOCKED: the streams are interleaved in blocks of
+ *     NEK_PROBE_BLOCK doubles: block b of stream k sits at
+ *     src + (b * nread + k) * NEK_PROBE_BLOCK, so a workgroup reads one
+ *     contiguous run of nread blocks, as the operator reads one element's u
+ *     and six factor planes; src_stride is ignored and src holds
+ *     nread * NEK_PROBE_BLOCK * ceil(n / NEK_PROBE_BLOCK) doubles.
  * src_stride (doubles, even, >= n) lets the caller stagger the streams so
  * that they do not sit a large power of two apart.  grid_cap > 0 caps the
  * number of workgroups, which then stride over the streams (0: one pass).
@@ -414,6 +425,8 @@ int nek_server_destroy(nek_server *srv);
  * Asynchronous. */
 #define NEK_PROBE_NT        1
 #define NEK_PROBE_READ_ONLY 2
+#define NEK_PROBE_BLOCKED   4
+#define NEK_PROBE_BLOCK     2048
 int nek_bw_probe(int64_t n, int nread, const double *src, int64_t src_stride, double *dst, int grid_cap,
                  int flags, void *stream);
 

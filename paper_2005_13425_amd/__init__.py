@@ -280,24 +280,35 @@ def ax_f32(u, D32, g_lo, g_dtype: int, N: int, out=None, stream=None):
 
 NEK_PROBE_NT = 1
 NEK_PROBE_READ_ONLY = 2
+NEK_PROBE_BLOCKED = 4
+NEK_PROBE_BLOCK = 2048
+
+
+def bw_probe_src_doubles(n: int, nread: int, stride: int | None = None, blocked: bool = False) -> int:
+    """Doubles the probe's src must hold for these streams."""
+    if blocked:
+        return nread * NEK_PROBE_BLOCK * ((n + NEK_PROBE_BLOCK - 1) // NEK_PROBE_BLOCK)
+    return (nread - 1) * (n if stride is None else int(stride)) + n
 
 
 def bw_probe(src, dst, nread: int, n: int | None = None, stride: int | None = None, grid_cap: int = 0,
-             streaming: bool = False, read_only: bool = False, stream=None):
-    """nread read streams of n doubles, stream k at src[k*stride:]; without
-    read_only dst[i] = sum_k stream_k[i] (n doubles), with read_only dst gets
-    one partial per workgroup (bw_probe_groups(n, grid_cap) doubles).
+             streaming: bool = False, read_only: bool = False, blocked: bool = False, stream=None):
+    """nread read streams of n doubles, stream k at src[k*stride:] (blocked:
+    interleaved in blocks of NEK_PROBE_BLOCK doubles); without read_only
+    dst[i] = sum_k stream_k[i] (n doubles), with read_only dst gets one
+    partial per workgroup (bw_probe_groups(n, grid_cap) doubles).
     streaming: non-temporal loads and stores."""
     torch = _torch()
     if n is None:
         n = dst.numel()
     stride = n if stride is None else int(stride)
     ndst = bw_probe_groups(n, grid_cap) if read_only else n
-    if src.numel() < (nread - 1) * stride + n:
+    if src.numel() < bw_probe_src_doubles(n, nread, stride, blocked):
         raise ValueError("src is shorter than its streams")
     if dst.numel() < ndst:
         raise ValueError(f"dst must hold {ndst} doubles")
-    flags = (NEK_PROBE_NT if streaming else 0) | (NEK_PROBE_READ_ONLY if read_only else 0)
+    flags = ((NEK_PROBE_NT if streaming else 0) | (NEK_PROBE_READ_ONLY if read_only else 0) |
+             (NEK_PROBE_BLOCKED if blocked else 0))
     _check(_lib.nek_bw_probe(int(n), int(nread), _dev(src, torch.float64, "src"), stride,
                              _dev(dst, torch.float64, "dst"), int(grid_cap), flags, _stream_ptr(stream)),
            "nek_bw_probe")

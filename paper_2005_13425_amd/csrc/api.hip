@@ -267,18 +267,22 @@ int nek_bw_probe(int64_t n, int nread, const double *src, int64_t src_stride, do
     clear_error();
     if (n < 2) return fail(NEK_ERR_ARG, "nek_bw_probe: n must be >= 2");
     if (nread < 1 || nread > 8) return fail(NEK_ERR_ARG, "nek_bw_probe: nread must be in 1..8");
-    if (flags & ~(NEK_PROBE_NT | NEK_PROBE_READ_ONLY)) return fail(NEK_ERR_ARG, "nek_bw_probe: unknown flag");
-    if (src_stride < n || (src_stride & 1)) return fail(NEK_ERR_ARG, "nek_bw_probe: src_stride must be even and >= n");
+    if (flags & ~(NEK_PROBE_NT | NEK_PROBE_READ_ONLY | NEK_PROBE_BLOCKED))
+        return fail(NEK_ERR_ARG, "nek_bw_probe: unknown flag");
+    const bool blk = (flags & NEK_PROBE_BLOCKED) != 0;
+    if (!blk && (src_stride < n || (src_stride & 1)))
+        return fail(NEK_ERR_ARG, "nek_bw_probe: src_stride must be even and >= n");
     if (grid_cap < 0) return fail(NEK_ERR_ARG, "nek_bw_probe: grid_cap must be >= 0");
     if (!src || !dst || ((uintptr_t)src & 15u) || ((uintptr_t)dst & 15u))
         return fail(NEK_ERR_ARG, "nek_bw_probe: null or misaligned pointer");
     const bool ro = (flags & NEK_PROBE_READ_ONLY) != 0;
     const int64_t ndst = ro ? probe_blocks(n, grid_cap) : n;
     const uintptr_t sb = (uintptr_t)src, db = (uintptr_t)dst;
-    const uintptr_t src_end = sb + (uintptr_t)((nread - 1) * src_stride + n) * 8;
+    const int64_t nblk = (n + NEK_PROBE_BLOCK - 1) / NEK_PROBE_BLOCK;
+    const uintptr_t src_end = sb + (uintptr_t)(blk ? nread * NEK_PROBE_BLOCK * nblk : (nread - 1) * src_stride + n) * 8;
     if (db < src_end && sb < db + (uintptr_t)ndst * 8)
         return fail(NEK_ERR_ARG, "nek_bw_probe: src and dst overlap");
-    NEK_HIP(launch_probe(n, nread, src, src_stride, dst, grid_cap, (flags & NEK_PROBE_NT) != 0, ro,
+    NEK_HIP(launch_probe(n, nread, src, src_stride, dst, grid_cap, (flags & NEK_PROBE_NT) != 0, ro, blk,
                          (hipStream_t)stream));
     return NEK_OK;
 }
@@ -654,7 +658,7 @@ int cg_check(const char *who, int64_t E, int N, const double *D, const double *g
     if (opts.dinv && pl.mixed) return fail(NEK_ERR_UNSUPPORTED, w + ": the Jacobi preconditioner is FP64 only");
     if (opts.dinv && !aligned16(opts.dinv)) return fail(NEK_ERR_ARG, w + ": misaligned dinv");
     pl.g_dtype = opts.precision == NEK_PREC_F32G32 ? NEK_G_F32 : NEK_G_BF16;
-    pl.drop = pl.mixed ? (opts.reliable_drop > 0.0 ? opts.reliable_drop : RELIABLE_DROP_DEFAULT) : 0.0;
+    pl.drop = pl.mixed ? (opts.reliable_drop > 0.0 ? opts.reliable_drop : reliable_drop_default(opts.precision)) : 0.0;
     if (pl.mixed && !(pl.drop < 1.0)) return fail(NEK_ERR_ARG, w + ": reliable_drop must be < 1");
     pl.check_every = opts.check_every > 0 ? opts.check_every : (pl.mixed ? 4 : 25);
     pl.poll = pl.mixed || opts.rel_tol > 0.0;
@@ -701,7 +705,7 @@ int cg_run(int64_t E, int N, const double *D, const double *g, const nek_gs *gs,
                              : (node_op ? launch_ax_node_fused(E, N, D, g, p, w, fz, s)
                                         : launch_ax_f64(E, N, D, g, p, w, fz, s));
         if (e != hipSuccess) return e;
-        return launch_cg_assemble_update(gs->cg, r, w, dinvc, W.axp, node_op ? E : ax_blocks(E, N), red_upd,
+        return launch_cg_assemble_update(gs->cg, r, w, mixed, dinvc, W.axp, node_op ? E : ax_blocks(E, N), red_upd,
                                          sc, s);
     };
     AxFuse plain_cg;   // A x alone, on CG-layout vectors

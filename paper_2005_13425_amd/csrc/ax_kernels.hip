@@ -22,6 +22,8 @@
 //     ahead of use;
 //   * in the CG the updates x += alpha p and p <- r + beta p are fused into
 //     the load of u, and the (p, A_L p) partial comes out of the same pass.
+#include <type_traits>
+
 #include "nek_internal.h"
 #include "reduce.h"
 
@@ -400,13 +402,16 @@ __device__ __forceinline__ void ax_body(int64_t blk, int64_t E, kptr<T> D, gptr<
     }
     double pw = 0.0;
     if constexpr (CGL) {
-        // ---- 6b. w leaves LDS at the thread's CG-layout entries
+        // ---- 6b. w leaves LDS at the thread's CG-layout entries; the CG-fused
+        // FP32 operator stores its FP32 result as it is (the assemble-update
+        // widens it), 4 bytes per point less to write and to read back
+        using WT = std::conditional_t<FUSE && sizeof(T) == 4, float, double>;
         __syncthreads();
         if (active) {
 #pragma unroll
             for (int k = 0; k < NX; ++k) {
                 const T wv = B0[k * LS + colv];
-                w[base + k * NN] = (double)wv;
+                ((gptr<WT>)w)[base + k * NN] = (WT)wv;
                 if constexpr (FUSE) pw += p[base + k * NN] * (double)wv;   // written by this thread
             }
         }

@@ -213,16 +213,16 @@ cg_init_kernel(int64_t P, const double *__restrict__ b, double *__restrict__ x,
 // of its copies (ascending local index), and r - alpha * sum goes to every
 // copy of r (r is continuous, so its first copy stands for all).  The node's
 // contribution to (r, r) and (r, M^-1 r) is taken once.
-template <int C, bool PRE>
+template <int C, bool PRE, typename WT>
 __device__ __forceinline__ void asm_row(gptr<const int32_t> idx, int32_t rows, int32_t row,
-                                        gptr<const double> w, gptr<double> r, gptr<const float> dinv,
+                                        gptr<const WT> w, gptr<double> r, gptr<const float> dinv,
                                         double alpha, double *acc) {
     int32_t id[C];
 #pragma unroll
     for (int m = 0; m < C; ++m) id[m] = idx[(int64_t)m * rows + row];
     double v[C];
 #pragma unroll
-    for (int m = 0; m < C; ++m) v[m] = w[id[m]];
+    for (int m = 0; m < C; ++m) v[m] = (double)w[id[m]];
     const double rv = r[id[0]];
     double dv = 0.0;
     if constexpr (PRE) dv = dinv[id[0]];
@@ -236,8 +236,8 @@ __device__ __forceinline__ void asm_row(gptr<const int32_t> idx, int32_t rows, i
     if constexpr (PRE) acc[1] += nr * (dv * nr);
 }
 
-template <bool PRE>
-__device__ __forceinline__ void asm_vblock(const GsArgs &a, int vb, gptr<const double> w, gptr<double> r,
+template <bool PRE, typename WT>
+__device__ __forceinline__ void asm_vblock(const GsArgs &a, int vb, gptr<const WT> w, gptr<double> r,
                                            gptr<const float> dinv, double alpha, double *acc) {
     int g = 0;
     while (g + 1 < a.ngroups && vb >= a.grp[g + 1].block0) ++g;
@@ -247,18 +247,18 @@ __device__ __forceinline__ void asm_vblock(const GsArgs &a, int vb, gptr<const d
     const gptr<const int32_t> idx = (gptr<const int32_t>)G.idx;
     switch (G.kind) {
     case 0: break;   // copies of masked nodes: r stays 0
-    case 2: asm_row<2, PRE>(idx, G.rows, row, w, r, dinv, alpha, acc); break;
-    case 3: asm_row<3, PRE>(idx, G.rows, row, w, r, dinv, alpha, acc); break;
-    case 4: asm_row<4, PRE>(idx, G.rows, row, w, r, dinv, alpha, acc); break;
-    case 5: asm_row<5, PRE>(idx, G.rows, row, w, r, dinv, alpha, acc); break;
-    case 6: asm_row<6, PRE>(idx, G.rows, row, w, r, dinv, alpha, acc); break;
-    case 7: asm_row<7, PRE>(idx, G.rows, row, w, r, dinv, alpha, acc); break;
-    case 8: asm_row<8, PRE>(idx, G.rows, row, w, r, dinv, alpha, acc); break;
+    case 2: asm_row<2, PRE, WT>(idx, G.rows, row, w, r, dinv, alpha, acc); break;
+    case 3: asm_row<3, PRE, WT>(idx, G.rows, row, w, r, dinv, alpha, acc); break;
+    case 4: asm_row<4, PRE, WT>(idx, G.rows, row, w, r, dinv, alpha, acc); break;
+    case 5: asm_row<5, PRE, WT>(idx, G.rows, row, w, r, dinv, alpha, acc); break;
+    case 6: asm_row<6, PRE, WT>(idx, G.rows, row, w, r, dinv, alpha, acc); break;
+    case 7: asm_row<7, PRE, WT>(idx, G.rows, row, w, r, dinv, alpha, acc); break;
+    case 8: asm_row<8, PRE, WT>(idx, G.rows, row, w, r, dinv, alpha, acc); break;
     default: {   // CSR rows with many copies
         const gptr<const int32_t> off = (gptr<const int32_t>)G.off;
         const int32_t o0 = off[row], o1 = off[row + 1];
         double s = 0.0;
-        for (int32_t o = o0; o < o1; ++o) s += w[idx[o]];
+        for (int32_t o = o0; o < o1; ++o) s += (double)w[idx[o]];
         const int32_t first = idx[o0];
         const double nr = r[first] - alpha * s;
         for (int32_t o = o0; o < o1; ++o) r[idx[o]] = nr;
@@ -292,13 +292,13 @@ __device__ __forceinline__ void row_setup(const GsArgs &a, int vb, RowJob &J) {
         if (m < J.C) J.id[m] = idx[(int64_t)m * G.rows + row];
 }
 
-template <bool PRE>
-__device__ __forceinline__ void row_load(RowJob &J, gptr<const double> w, gptr<const double> r,
+template <bool PRE, typename WT>
+__device__ __forceinline__ void row_load(RowJob &J, gptr<const WT> w, gptr<const double> r,
                                          gptr<const float> dinv) {
     if (J.C == 0) return;
 #pragma unroll
     for (int m = 0; m < 4; ++m)
-        if (m < J.C) J.v[m] = w[J.id[m]];
+        if (m < J.C) J.v[m] = (double)w[J.id[m]];
     J.rv = r[J.id[0]];
     if constexpr (PRE) J.dv = dinv[J.id[0]];
 }
@@ -335,15 +335,20 @@ __device__ __forceinline__ void chunk_bits(int64_t base, int64_t npairs, gptr<co
     }
 }
 
-template <bool PRE>
-__device__ __forceinline__ void chunk_load(int64_t base, gptr<const double> r, gptr<const double> w,
+template <bool PRE, typename WT>
+__device__ __forceinline__ void chunk_load(int64_t base, gptr<const double> r, gptr<const WT> w,
                                            gptr<const float> dinv, PairChunk<PRE> &Q) {
 #pragma unroll
     for (int m = 0; m < VEC_PAIRS; ++m) {
         const int64_t q = base + threadIdx.x + (int64_t)m * VEC_THREADS;
         if (Q.rb[m] != 3u) {
             Q.rv[m] = ((gptr<const double2>)r)[q];
-            Q.wv[m] = ((gptr<const double2>)w)[q];
+            if constexpr (sizeof(WT) == 8) {
+                Q.wv[m] = ((gptr<const double2>)w)[q];
+            } else {
+                const float2 wf = ((gptr<const float2>)w)[q];
+                Q.wv[m] = make_double2(wf.x, wf.y);
+            }
             if constexpr (PRE) {
                 const float2 df = ((gptr<const float2>)dinv)[q];
                 Q.dv[m] = make_double2(df.x, df.y);
@@ -402,11 +407,13 @@ __device__ __forceinline__ void chunk_finish(int64_t base, gptr<double> r, doubl
 // then the values those select; only then does it wait for alpha.  Further
 // row blocks and chunks (large meshes), rows of rare kinds, then the
 // reduction: rr = (r, r), rho' = (r, z), beta = rho' / rho, convergence on rr
-// and the iteration cap.  lb / nb as in the gather-scatter.
-template <bool PRE>
+// and the iteration cap.  lb / nb as in the gather-scatter.  WT: the type the
+// operator stored w in (FP32 for the FP32 operator, which computes it in FP32:
+// widening on the way in gives the same values as storing FP64).
+template <bool PRE, typename WT>
 __device__ __forceinline__ void assemble_update_body(int lb, int nb, int64_t P, const GsArgs &a,
                                                      gptr<const uint32_t> rowed, gptr<double> r,
-                                                     gptr<const double> w, gptr<const float> dinv,
+                                                     gptr<const WT> w, gptr<const float> dinv,
                                                      gptr<const double> axparts, int64_t nparts,
                                                      const RedSite &red, gptr<CgScalars> sc) {
     constexpr int K = PRE ? 2 : 1;
@@ -461,9 +468,9 @@ __device__ __forceinline__ void assemble_update_body(int lb, int nb, int64_t P, 
     if (done_s) return;
 
     // ---- 2. loads selected by the indices and bits
-    row_load<PRE>(J0, w, r, dinv);
-    row_load<PRE>(J1, w, r, dinv);
-    chunk_load<PRE>(base0, r, w, dinv, Q);
+    row_load<PRE, WT>(J0, w, r, dinv);
+    row_load<PRE, WT>(J1, w, r, dinv);
+    chunk_load<PRE, WT>(base0, r, w, dinv, Q);
 
     // ---- 3. alpha = rho / (p, A p): every workgroup sums the partials in the
     // same order, so all of them hold the same alpha; workgroup 0 records it
@@ -521,10 +528,10 @@ __device__ __forceinline__ void assemble_update_body(int lb, int nb, int64_t P, 
                     if (seen++ < 2) continue;
                     RowJob J;
                     row_setup(a, vb, J);
-                    row_load<PRE>(J, w, r, dinv);
+                    row_load<PRE, WT>(J, w, r, dinv);
                     row_finish<PRE>(J, r, alpha, acc);
                 } else {   // rare kinds: corners of 8 elements, many-copy CSR rows
-                    asm_vblock<PRE>(a, vb, w, r, dinv, alpha, acc);
+                    asm_vblock<PRE, WT>(a, vb, w, r, dinv, alpha, acc);
                 }
             }
         }
@@ -533,13 +540,13 @@ __device__ __forceinline__ void assemble_update_body(int lb, int nb, int64_t P, 
         const int64_t base = c * VEC_CHUNK;
         PairChunk<PRE> Qn;
         chunk_bits<PRE>(base, npairs, rowed, Qn);
-        chunk_load<PRE>(base, r, w, dinv, Qn);
+        chunk_load<PRE, WT>(base, r, w, dinv, Qn);
         chunk_finish<PRE>(base, r, alpha, Qn, acc);
     }
     if ((P & 1) && lb == nb - 1 && threadIdx.x == VEC_THREADS - 1) {
         const int64_t t = P - 1;
         if (!own_bit(rowed, t)) {
-            const double nr = r[t] - alpha * w[t];
+            const double nr = r[t] - alpha * (double)w[t];
             r[t] = nr;
             acc[0] += nr * nr;
             if constexpr (PRE) acc[K - 1] += nr * (dinv[t] * nr);
@@ -569,13 +576,13 @@ __device__ __forceinline__ void assemble_update_body(int lb, int nb, int64_t P, 
     }
 }
 
-template <bool PRE>
+template <bool PRE, typename WT>
 __global__ void __launch_bounds__(VEC_THREADS)
 assemble_update_kernel(int64_t P, GsArgs a, const uint32_t *__restrict__ rowed, double *__restrict__ r,
-                       const double *__restrict__ w, const float *__restrict__ dinv,
+                       const WT *__restrict__ w, const float *__restrict__ dinv,
                        const double *__restrict__ axparts, int64_t nparts, RedSite red, CgScalars *sc) {
-    assemble_update_body<PRE>(blockIdx.x, gridDim.x, P, a, (gptr<const uint32_t>)rowed, (gptr<double>)r,
-                              (gptr<const double>)w, (gptr<const float>)dinv,
+    assemble_update_body<PRE, WT>(blockIdx.x, gridDim.x, P, a, (gptr<const uint32_t>)rowed, (gptr<double>)r,
+                              (gptr<const WT>)w, (gptr<const float>)dinv,
                               (gptr<const double>)axparts, nparts, red, (gptr<CgScalars>)sc);
 }
 
@@ -584,9 +591,14 @@ assemble_update_batch_kernel(const AsmSlot *__restrict__ slots, int nslots) {
     const AsmSlot &S = slots[batch_slot(slots, nslots, (int64_t)blockIdx.x)];
     const int lb = (int)((int64_t)blockIdx.x - S.block0);
     if (lb >= S.nblocks) return;
-    assemble_update_body<false>(lb, (int)S.nblocks, S.P, S.args, (gptr<const uint32_t>)S.rowed,
-                                (gptr<double>)S.r, (gptr<const double>)S.w, nullptr,
-                                (gptr<const double>)S.axparts, S.nparts, S.red, (gptr<CgScalars>)S.sc);
+    if (S.w_f32)
+        assemble_update_body<false, float>(lb, (int)S.nblocks, S.P, S.args, (gptr<const uint32_t>)S.rowed,
+                                           (gptr<double>)S.r, (gptr<const float>)S.w, nullptr,
+                                           (gptr<const double>)S.axparts, S.nparts, S.red, (gptr<CgScalars>)S.sc);
+    else
+        assemble_update_body<false, double>(lb, (int)S.nblocks, S.P, S.args, (gptr<const uint32_t>)S.rowed,
+                                            (gptr<double>)S.r, (gptr<const double>)S.w, nullptr,
+                                            (gptr<const double>)S.axparts, S.nparts, S.red, (gptr<CgScalars>)S.sc);
 }
 
 __global__ void gather_scalars_kernel(CgScalars *const *src, int n, CgScalars *dst) {
@@ -770,15 +782,19 @@ int64_t asm_blocks(const GsDevice &gs) {
     return g > RED_MAX_BLOCKS ? RED_MAX_BLOCKS : g;
 }
 
-hipError_t launch_cg_assemble_update(const GsDevice &gs, double *r, const double *w, const float *dinv,
+hipError_t launch_cg_assemble_update(const GsDevice &gs, double *r, const double *w, bool w_f32, const float *dinv,
                                      const double *axparts, int64_t nparts, const RedSite &red,
                                      CgScalars *sc, hipStream_t s) {
     const dim3 grid((unsigned)asm_blocks(gs));
+    if (w_f32 && dinv != nullptr) return hipErrorInvalidValue;   // the preconditioned CG is FP64 only
     if (dinv != nullptr)
-        hipLaunchKernelGGL(assemble_update_kernel<true>, grid, dim3(VEC_THREADS), 0, s, gs.P, gs.args,
+        hipLaunchKernelGGL((assemble_update_kernel<true, double>), grid, dim3(VEC_THREADS), 0, s, gs.P, gs.args,
                            gs.rowed_bits, r, w, dinv, axparts, nparts, red, sc);
+    else if (w_f32)
+        hipLaunchKernelGGL((assemble_update_kernel<false, float>), grid, dim3(VEC_THREADS), 0, s, gs.P, gs.args,
+                           gs.rowed_bits, r, (const float *)w, dinv, axparts, nparts, red, sc);
     else
-        hipLaunchKernelGGL(assemble_update_kernel<false>, grid, dim3(VEC_THREADS), 0, s, gs.P, gs.args,
+        hipLaunchKernelGGL((assemble_update_kernel<false, double>), grid, dim3(VEC_THREADS), 0, s, gs.P, gs.args,
                            gs.rowed_bits, r, w, dinv, axparts, nparts, red, sc);
     return hipGetLastError();
 }

@@ -68,10 +68,11 @@ struct CgScalars {
 };
 
 // Mixed precision: r is replaced by the FP64 true residual once ||r|| has
-// fallen by this factor since the last replacement (measured at E = 4096,
-// N = 9: 0.3 takes 6% fewer iterations than 0.1 with BF16 g, the same with
-// FP32 g).
-constexpr double RELIABLE_DROP_DEFAULT = 0.3;
+// fallen by this factor since the last replacement.  Measured at E = 4096,
+// N = 9 (manufactured solution, to 1e-10): with BF16 g, 0.3 takes 1324
+// iterations and 0.1 1412; with FP32 g both take 1148, and 0.1 needs 11
+// replacements instead of 19 (0.8% less time).
+inline double reliable_drop_default(int precision) { return precision == NEK_PREC_F32G32 ? 0.1 : 0.3; }
 
 // ---------------------------------------------------------------- ax_e
 // Optional CG fusion of the local-operator launch (all device pointers):
@@ -299,7 +300,9 @@ hipError_t launch_cg_init(int64_t P, const double *b, double *x, double *r, doub
 // assembled w itself is never stored.  alpha = rho / (p, A p), from the nparts
 // per-workgroup partials of (p, A_L p) left by the ax launch, summed in index
 // order by every workgroup (workgroup 0 records it, or flags a breakdown).
-hipError_t launch_cg_assemble_update(const GsDevice &gs, double *r, const double *w,
+// w_f32: w holds FP32 values (the FP32 operator of the mixed form stores its
+// FP32 result as it is; FP64 only without a preconditioner).
+hipError_t launch_cg_assemble_update(const GsDevice &gs, double *r, const double *w, bool w_f32,
                                      const float *dinv, const double *axparts, int64_t nparts,
                                      const RedSite &red, CgScalars *sc, hipStream_t s);
 int64_t asm_blocks(const GsDevice &gs);   // its grid: a multiple of 8, <= RED_MAX_BLOCKS
@@ -311,11 +314,12 @@ struct AsmSlot {
     GsArgs args;
     const uint32_t *rowed;
     double *r;
-    const double *w;
+    const double *w;     // FP32 values when w_f32 (the FP32 operator's output)
     const double *axparts;
     int64_t nparts;
     RedSite red;
     CgScalars *sc;
+    int w_f32;
 };
 hipError_t launch_assemble_update_batch(const AsmSlot *slots, int nslots, int64_t blocks, hipStream_t s);
 
@@ -418,7 +422,7 @@ hipError_t launch_box_geometry(int Ex, int Ey, int Ez, int N, double amp, double
                                hipStream_t s);
 
 hipError_t launch_probe(int64_t n, int nread, const double *src, int64_t stride, double *dst, int grid_cap,
-                        bool streaming, bool read_only, hipStream_t s);
+                        bool streaming, bool read_only, bool blocked, hipStream_t s);
 int64_t probe_blocks(int64_t n, int grid_cap);   // workgroups of a probe launch
 // diagonal of the element operator at every local point, and the reciprocal
 // of a continuous vector in place (0 stays 0)

@@ -10,7 +10,10 @@
 //   * read-only form: every workgroup writes one partial sum, so only the
 //     read streams touch HBM.
 // With NT the loads and stores carry the non-temporal (streaming) hint, as the
-// plain FP64 operator's do.  The stride lets the caller stagger the streams:
+// plain FP64 operator's do.  BLK interleaves the streams in blocks of one
+// workgroup's pass (NEK_PROBE_BLOCK doubles), so that a workgroup reads one
+// contiguous run, as the operator reads an element's u and factor planes.
+// The stride lets the caller stagger the streams:
 // when they sit a large power of two apart, the lanes' R loads of one
 // iteration share their low address bits and can fall on the same HBM
 // channels, which a layout like the operator's (six factor planes of one
@@ -26,11 +29,14 @@ constexpr int PROBE_PAIRS = 4;
 
 typedef double dvec2 __attribute__((ext_vector_type(2)));
 
-template <int R, bool NT, bool RO>
+constexpr int64_t PROBE_CHUNK = (int64_t)PROBE_THREADS * PROBE_PAIRS;   // pairs per workgroup pass
+static_assert(2 * PROBE_CHUNK == NEK_PROBE_BLOCK, "a probe block is one workgroup pass");
+
+template <int R, bool NT, bool RO, bool BLK>
 __global__ void __launch_bounds__(PROBE_THREADS)
 probe_kernel(int64_t n, const double *__restrict__ src, int64_t stride, double *__restrict__ dst) {
     const int64_t npairs = n >> 1;
-    const int64_t chunk = (int64_t)PROBE_THREADS * PROBE_PAIRS;
+    const int64_t chunk = PROBE_CHUNK;
     dvec2 tot = dvec2{0.0, 0.0};
     for (int64_t base = blockIdx.x * chunk; base < npairs; base += (int64_t)gridDim.x * chunk) {
         dvec2 acc[PROBE_PAIRS];
@@ -38,11 +44,14 @@ probe_kernel(int64_t n, const double *__restrict__ src, int64_t stride, double *
         for (int m = 0; m < PROBE_PAIRS; ++m) acc[m] = dvec2{0.0, 0.0};
 #pragma unroll
         for (int k = 0; k < R; ++k) {
-            const dvec2 *s2 = (const dvec2 *)(src + (int64_t)k * stride);
+            // pair q of stream k: at q in a stream of its own, or at q - base
+            // in block base / chunk of the interleaved layout
+            const dvec2 *s2 = BLK ? (const dvec2 *)src + ((base / chunk) * R + k) * chunk
+                                  : (const dvec2 *)(src + (int64_t)k * stride) + base;
 #pragma unroll
             for (int m = 0; m < PROBE_PAIRS; ++m) {
-                const int64_t q = base + threadIdx.x + (int64_t)m * PROBE_THREADS;
-                if (q < npairs) acc[m] += NT ? __builtin_nontemporal_load(&s2[q]) : s2[q];
+                const int64_t o = threadIdx.x + (int64_t)m * PROBE_THREADS;
+                if (base + o < npairs) acc[m] += NT ? __builtin_nontemporal_load(&s2[o]) : s2[o];
             }
         }
 #pragma unroll
@@ -61,23 +70,33 @@ probe_kernel(int64_t n, const double *__restrict__ src, int64_t stride, double *
         const double s = block_sum<PROBE_THREADS>(tot.x + tot.y, red);
         if (threadIdx.x == 0) dst[blockIdx.x] = s;
     } else if ((n & 1) && blockIdx.x == 0 && threadIdx.x == 0) {
+        // the odd last value: block npairs / chunk, position 2 * (npairs % chunk)
         double a = 0.0;
-        for (int k = 0; k < R; ++k) a += src[(int64_t)k * stride + n - 1];
+        for (int k = 0; k < R; ++k)
+            a += BLK ? src[(((npairs / chunk) * R + k) * chunk + npairs % chunk) * 2]
+                     : src[(int64_t)k * stride + n - 1];
         dst[n - 1] = a;
+    }
+}
+
+template <int R, bool BLK>
+void launch_rb(int64_t blocks, int64_t n, const double *src, int64_t stride, double *dst, bool nt, bool ro,
+               hipStream_t s) {
+    const dim3 grid((unsigned)blocks), block(PROBE_THREADS);
+    if (ro) {
+        if (nt) hipLaunchKernelGGL((probe_kernel<R, true, true, BLK>), grid, block, 0, s, n, src, stride, dst);
+        else hipLaunchKernelGGL((probe_kernel<R, false, true, BLK>), grid, block, 0, s, n, src, stride, dst);
+    } else {
+        if (nt) hipLaunchKernelGGL((probe_kernel<R, true, false, BLK>), grid, block, 0, s, n, src, stride, dst);
+        else hipLaunchKernelGGL((probe_kernel<R, false, false, BLK>), grid, block, 0, s, n, src, stride, dst);
     }
 }
 
 template <int R>
 void launch_r(int64_t blocks, int64_t n, const double *src, int64_t stride, double *dst, bool nt, bool ro,
-              hipStream_t s) {
-    const dim3 grid((unsigned)blocks), block(PROBE_THREADS);
-    if (ro) {
-        if (nt) hipLaunchKernelGGL((probe_kernel<R, true, true>), grid, block, 0, s, n, src, stride, dst);
-        else hipLaunchKernelGGL((probe_kernel<R, false, true>), grid, block, 0, s, n, src, stride, dst);
-    } else {
-        if (nt) hipLaunchKernelGGL((probe_kernel<R, true, false>), grid, block, 0, s, n, src, stride, dst);
-        else hipLaunchKernelGGL((probe_kernel<R, false, false>), grid, block, 0, s, n, src, stride, dst);
-    }
+              bool blk, hipStream_t s) {
+    if (blk) launch_rb<R, true>(blocks, n, src, stride, dst, nt, ro, s);
+    else launch_rb<R, false>(blocks, n, src, stride, dst, nt, ro, s);
 }
 
 }  // namespace
@@ -90,11 +109,11 @@ int64_t probe_blocks(int64_t n, int grid_cap) {
 }
 
 hipError_t launch_probe(int64_t n, int nread, const double *src, int64_t stride, double *dst, int grid_cap,
-                        bool streaming, bool read_only, hipStream_t s) {
+                        bool streaming, bool read_only, bool blocked, hipStream_t s) {
     const int64_t blocks = probe_blocks(n, grid_cap);
     switch (nread) {
 #define NEK_PROBE(R) \
-    case R: launch_r<R>(blocks, n, src, stride, dst, streaming, read_only, s); break;
+    case R: launch_r<R>(blocks, n, src, stride, dst, streaming, read_only, blocked, s); break;
         NEK_PROBE(1) NEK_PROBE(2) NEK_PROBE(3) NEK_PROBE(4) NEK_PROBE(5) NEK_PROBE(6) NEK_PROBE(7)
         NEK_PROBE(8)
 #undef NEK_PROBE

@@ -441,7 +441,7 @@ struct nek_server {
         if (is_mixed(q.precision))
             NEK_HIP(launch_convert_g(R->E, q.N, S->g,
                                      q.precision == NEK_PREC_F32G32 ? NEK_G_F32 : NEK_G_BF16, S->glo, stream));
-        const double drop = is_mixed(q.precision) ? RELIABLE_DROP_DEFAULT : 0.0;
+        const double drop = is_mixed(q.precision) ? reliable_drop_default(q.precision) : 0.0;
         NEK_HIP(launch_cg_reset(S->W.sc, S->W.tickets, N_SITES * RED_TICKETS, q.max_iter, q.rel_tol, drop,
                                 stream));
         NEK_HIP(launch_cg_init(R->P, S->b, S->x, S->W.r, S->W.p, S->gsd.own_bits, nullptr, S->W.site(SITE_INIT),
@@ -586,6 +586,7 @@ struct nek_server {
             U.nparts = nparts;
             U.red = S->W.site(SITE_UPDATE);
             U.sc = S->W.sc;
+            U.w_f32 = mixed ? 1 : 0;   // the FP32 operator leaves w in FP32
             blk[L_ASM] += U.nblocks;
             scp[ordered.size()] = S->W.sc;
             ordered.push_back(S);

@@ -99,7 +99,12 @@ def test_argument_errors_before_device_work(nek):
     assert lib.nek_bw_probe(16, 2, fake, 16, ctypes.c_void_p(0x1010), 0, 0, None) == nek.NEK_ERR_ARG   # overlap
     assert lib.nek_bw_probe(16, 2, fake, 15, big, 0, 0, None) == nek.NEK_ERR_ARG    # stride < n
     assert lib.nek_bw_probe(16, 2, fake, 17, big, 0, 0, None) == nek.NEK_ERR_ARG    # odd stride
-    assert lib.nek_bw_probe(16, 2, fake, 16, big, 0, 4, None) == nek.NEK_ERR_ARG    # unknown flag
+    assert lib.nek_bw_probe(16, 2, fake, 16, big, 0, 8, None) == nek.NEK_ERR_ARG    # unknown flag
+    # blocked streams: src holds nread whole blocks per block of n, whatever the stride
+    blk = nek.NEK_PROBE_BLOCKED
+    dst_in = ctypes.c_void_p(0x1000 + 8 * (2 * nek.NEK_PROBE_BLOCK - 16))
+    assert lib.nek_bw_probe(16, 2, fake, 0, dst_in, 0, blk, None) == nek.NEK_ERR_ARG   # overlap
+    assert "overlap" in lib.nek_last_error().decode()
     assert lib.nek_bw_probe(16, 2, fake, 16, big, -1, 0, None) == nek.NEK_ERR_ARG   # negative cap
     assert lib.nek_bw_probe_groups(10 ** 6, 0) == (10 ** 6 + 2047) // 2048
     assert lib.nek_bw_probe_groups(10 ** 6, 100) == 100

@@ -300,6 +300,29 @@ def test_bw_probe_sums_its_streams(nek, streaming):
 
 
 @pytest.mark.parametrize("streaming", [False, True])
+def test_bw_probe_blocked_layout(nek, streaming):
+    # streams interleaved in blocks of NEK_PROBE_BLOCK doubles: block b of
+    # stream k at (b * nread + k) * BLOCK; odd n and a ragged last block
+    rng = np.random.default_rng(11)
+    B = nek.NEK_PROBE_BLOCK
+    for nread, n, cap in ((7, 40001, 0), (7, 3 * B, 2), (1, 12345, 0), (3, 300001, 13)):
+        nb = (n + B - 1) // B
+        src = rng.uniform(-1, 1, nek.bw_probe_src_doubles(n, nread, blocked=True))
+        streams = src.reshape(nb, nread, B).transpose(1, 0, 2).reshape(nread, nb * B)[:, :n]
+        dst = torch.empty(n, dtype=torch.float64, device="cuda")
+        nek.bw_probe(_dev(src), dst, nread, grid_cap=cap, streaming=streaming, blocked=True)
+        ref = np.zeros(n)
+        for k in range(nread):
+            ref = ref + streams[k]
+        np.testing.assert_array_equal(dst.cpu().numpy(), ref)
+        groups = nek.bw_probe_groups(n, cap)
+        part = torch.empty(groups, dtype=torch.float64, device="cuda")
+        nek.bw_probe(_dev(src), part, nread, n=n, grid_cap=cap, streaming=streaming, read_only=True, blocked=True)
+        tot = streams[:, :n - (n & 1)].sum()
+        assert abs(part.sum().item() - tot) <= 1e-9 * np.abs(streams).sum()
+
+
+@pytest.mark.parametrize("streaming", [False, True])
 def test_bw_probe_read_only_partials(nek, streaming):
     # one partial per workgroup; together they hold the sum of every stream
     # (the last value left out for odd n)
