@@ -258,7 +258,8 @@ def main():
 def mixed_leg(nek, torch, dev, Ex, Ey, Ez, N, D, g, gs, ws, tol=1e-10):
     """Time to a true relative residual of 1e-10 on the manufactured solution
     sin(pi x) sin(pi y) sin(pi z): FP64 CG against the FP32 operator with g in
-    FP32 and in BF16 inside FP64 reliable-update CG, on the same mesh."""
+    FP32 and in BF16, and the FP64 operator reading g in FP32 and in BF16,
+    each inside FP64 reliable-update CG, on the same mesh."""
     import numpy as np
     E = Ex * Ey * Ez
     g2, bm, X = nek.box_geometry(Ex, Ey, Ez, N, synth_amp(), synth_coeffs(), want_mass=True,
@@ -274,7 +275,9 @@ def mixed_leg(nek, torch, dev, Ex, Ey, Ez, N, D, g, gs, ws, tol=1e-10):
     x64 = None
     for name, prec, code in (("fp64", nek.NEK_PREC_F64, None),
                              ("f32_g32", nek.NEK_PREC_F32G32, nek.NEK_G_F32),
-                             ("f32_gbf16", nek.NEK_PREC_F32GBF16, nek.NEK_G_BF16)):
+                             ("f32_gbf16", nek.NEK_PREC_F32GBF16, nek.NEK_G_BF16),
+                             ("f64_g32", nek.NEK_PREC_F64G32, nek.NEK_G_F32),
+                             ("f64_gbf16", nek.NEK_PREC_F64GBF16, nek.NEK_G_BF16)):
         glo = nek.convert_g(g, N, code) if code else None
         x = torch.empty_like(b)
         nek.cg_solve(D, g, gs, b, x, max_iter=5000, rel_tol=tol, precision=prec, D32=D32, g_lo=glo,
@@ -292,7 +295,7 @@ def mixed_leg(nek, torch, dev, Ex, Ey, Ez, N, D, g, gs, ws, tol=1e-10):
                      "rel_err_vs_fp64_solve": float(torch.linalg.norm(x - x64) / torch.linalg.norm(x64)),
                      "rel_err_vs_exact_u": float(torch.linalg.norm(x - ustar) / torch.linalg.norm(ustar))}
         del glo
-    for name in ("f32_g32", "f32_gbf16"):
+    for name in ("f32_g32", "f32_gbf16", "f64_g32", "f64_gbf16"):
         res[name]["speedup_vs_fp64"] = round(res["fp64"]["ms"] / res[name]["ms"], 3)
     res["workload"] = (f"manufactured sin solution, E={E} ({Ex}x{Ey}x{Ez}) N={N}, stop at true "
                        f"||b-Ax||/||b|| <= {tol}; FP64 residual/dots/axpy, reliable updates")
@@ -577,7 +580,8 @@ def serve_leg(nek, torch, n_req, budget_gb, iters_per_step, tol=1e-10, max_iter=
        capacity with that budget: latency from submission to the step that saw
        the solve finish (p50 / p99; with a few dozen requests p99 is close to
        the maximum).
-    2-4 run in FP64 and in the mixed form (FP32 operator, FP32 g)."""
+    2-4 run in FP64 and in two mixed forms (FP32 operator with FP32 g; FP64
+    operator reading FP32 g)."""
     import numpy as np
     import synth
 
@@ -623,7 +627,8 @@ def serve_leg(nek, torch, n_req, budget_gb, iters_per_step, tol=1e-10, max_iter=
     }
     big = 64 << 30
     budget = int(budget_gb * (1 << 30))
-    for name, prec in (("fp64", nek.NEK_PREC_F64), ("f32_g32", nek.NEK_PREC_F32G32)):
+    for name, prec in (("fp64", nek.NEK_PREC_F64), ("f32_g32", nek.NEK_PREC_F32G32),
+                       ("f64_g32", nek.NEK_PREC_F64G32)):
         out[f"footprint_gb_{name}"] = round(sum(nek.server_footprint(*r["box"], r["N"], prec)
                                                 for r in reqs) / (1 << 30), 3)
         sat = _serve_run(nek, reqs, [0.0] * n_req, prec, big, iters_per_step, tol, max_iter)

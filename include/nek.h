@@ -63,6 +63,8 @@ extern "C" {
 #define NEK_PREC_F64      0  /* FP64 operator (Listing 1 in double precision) */
 #define NEK_PREC_F32G32   1  /* FP32 operator, g stored FP32, FP64 reliable updates */
 #define NEK_PREC_F32GBF16 2  /* FP32 operator, g stored BF16, FP64 reliable updates */
+#define NEK_PREC_F64G32   3  /* FP64 operator arithmetic, g stored FP32, FP64 reliable updates */
+#define NEK_PREC_F64GBF16 4  /* FP64 operator arithmetic, g stored BF16, FP64 reliable updates */
 
 /* Text of a status code (static string). */
 const char *nek_strerror(int code);
@@ -113,7 +115,7 @@ int nek_ax(int64_t E, int N, const double *u, const double *D, const double *g,
 /* The same operator computed in FP32: u is read in FP64 and rounded, the
  * contractions and the geometric multiply run in FP32 with D32 (FP32 copy of
  * D, 4-byte aligned) and g_lo (the factors as FP32 or BF16, g_dtype =
- * NEK_G_F32 or NEK_G_BF16, in the paired layout written by nek_convert_g;
+ * NEK_G_F32 or NEK_G_BF16, in the point layout written by nek_convert_g;
  * 8-byte aligned for FP32, 4-byte for BF16), and w is written in FP64.  Used
  * inside the FP64 reliable-update CG (NEK_PREC_F32G*).  Allocates nothing.
  * Asynchronous. */
@@ -142,9 +144,10 @@ int nek_ax_variant(int64_t E, int N, const double *u, const double *D, const dou
 
 /* Round g (6*P FP64 values, device) to FP32 or BF16 (round to nearest even;
  * BF16 through FP32) into g_lo (device, 6*P values of the chosen type).
- * Paired layout of g_lo: per element, three planes q = 0, 1, 2 of n^3 pairs
- * (gxyz(.,2q), gxyz(.,2q+1)) in point order, so that the FP32 operator loads
- * one pair per load.  Asynchronous. */
+ * Point layout of g_lo: the six factors of a point side by side
+ * (gxyz(i,j,k,0..5,e) at [6*(i + n*(j + n*(k + n*e))) + c], 24 bytes a point
+ * in FP32, 12 in BF16), so that the operator loads a point's factors with one
+ * load per lane.  Asynchronous. */
 int nek_convert_g(int64_t E, int N, const double *g, int g_dtype, void *g_lo, void *stream);
 
 /* ---------------------------------------------------- gather-scatter (dssum) */
@@ -191,7 +194,8 @@ typedef struct {
     double rel_tol;        /* stop when ||r||/||b|| <= rel_tol; <= 0: run max_iter */
     int precision;         /* NEK_PREC_* */
     const float *D32;      /* FP32 copy of D (device), required for NEK_PREC_F32G* */
-    const void *g_lo;      /* g as FP32 / BF16 (device), required for NEK_PREC_F32G* */
+    const void *g_lo;      /* g as FP32 / BF16 from nek_convert_g (device), required for
+                              NEK_PREC_F32G* and NEK_PREC_F64G* */
     int check_every;       /* host polls convergence every this many iterations (0: 25;
                               4 in the mixed precisions) */
     int true_residual;     /* 1: report ||b - A x|| / ||b|| computed in FP64 at the end */
@@ -240,6 +244,14 @@ size_t nek_cg_workspace_bytes(int64_t E, int N);
  * workspace in that order, x is written in it while iterating and put back
  * into the layout of Listing 1 before the call returns.  After a failure other than NEK_ERR_NOCONV and
  * NEK_ERR_BREAKDOWN, x is unspecified.
+ *
+ * Mixed precisions (opts->precision): the operator of every iteration reads
+ * g_lo instead of g; the residual, the inner products, the vector updates and
+ * a reliable update of r to the true FP64 residual b - A x (with g) stay in
+ * FP64, and the solve stops on that true residual.  NEK_PREC_F32G*: the
+ * operator computes in FP32 (with D32).  NEK_PREC_F64G*: the operator computes
+ * in FP64 and only g is stored in FP32 or BF16; an FP32 contraction perturbs
+ * the operator more than FP32 storage of g does, and costs iterations.
  *
  * With opts->dinv set: preconditioned CG with M^-1 = dinv (the preconditioning
  * Sec. VII leaves as future work, in its simplest, Jacobi form):

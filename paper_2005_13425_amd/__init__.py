@@ -42,6 +42,8 @@ NEK_G_BF16 = 2
 NEK_PREC_F64 = 0
 NEK_PREC_F32G32 = 1
 NEK_PREC_F32GBF16 = 2
+NEK_PREC_F64G32 = 3
+NEK_PREC_F64GBF16 = 4
 NEK_AX_PENCIL = 0
 NEK_AX_ORIGINAL = 1
 NEK_AX_SHARED3D = 2
@@ -396,8 +398,9 @@ def _cg_call(fn, name, D, g, gs, b, x, max_iter, rel_tol, precision, D32, g_lo, 
     o.rel_tol = float(rel_tol)
     o.precision = int(precision)
     if precision != NEK_PREC_F64:
-        o.D32 = _dev(D32, torch.float32, "D32", (N + 1) ** 2)
-        gdt = torch.float32 if precision == NEK_PREC_F32G32 else torch.int16
+        if precision in (NEK_PREC_F32G32, NEK_PREC_F32GBF16):   # the FP32 operator
+            o.D32 = _dev(D32, torch.float32, "D32", (N + 1) ** 2)
+        gdt = torch.float32 if precision in (NEK_PREC_F32G32, NEK_PREC_F64G32) else torch.int16
         o.g_lo = _dev(g_lo, gdt, "g_lo", 6 * P)
     o.check_every = int(check_every)
     o.true_residual = 1 if true_residual else 0

@@ -629,7 +629,8 @@ thread_local HostSnap g_snap;
 
 // What nek_cg_solve needs once its arguments have been checked.
 struct CgPlan {
-    bool mixed = false;
+    bool mixed = false;   // any mixed precision: reliable updates, stop on the true residual
+    bool f64_op = false;  // NEK_PREC_F64G*: FP64 operator arithmetic on g_lo
     int g_dtype = 0;
     double drop = 0.0;
     int check_every = 0;
@@ -649,15 +650,18 @@ int cg_check(const char *who, int64_t E, int N, const double *D, const double *g
     if (gs->d.E != E || gs->d.N != N) return fail(NEK_ERR_ARG, w + ": gather-scatter built for another mesh");
     if (b == x) return fail(NEK_ERR_ARG, w + ": b and x must differ");
     if (opts.max_iter < 0) return fail(NEK_ERR_ARG, w + ": max_iter must be >= 0");
-    pl.mixed = opts.precision == NEK_PREC_F32G32 || opts.precision == NEK_PREC_F32GBF16;
-    if (!pl.mixed && opts.precision != NEK_PREC_F64) return fail(NEK_ERR_UNSUPPORTED, w + ": unknown precision");
-    if (pl.mixed && (!opts.D32 || !opts.g_lo)) return fail(NEK_ERR_ARG, w + ": mixed precision needs D32 and g_lo");
-    if (pl.mixed && (((uintptr_t)opts.g_lo & (opts.precision == NEK_PREC_F32G32 ? 7u : 3u)) ||
-                     ((uintptr_t)opts.D32 & 3u)))
+    const int pr = opts.precision;
+    pl.f64_op = pr == NEK_PREC_F64G32 || pr == NEK_PREC_F64GBF16;
+    pl.mixed = pr == NEK_PREC_F32G32 || pr == NEK_PREC_F32GBF16 || pl.f64_op;
+    if (!pl.mixed && pr != NEK_PREC_F64) return fail(NEK_ERR_UNSUPPORTED, w + ": unknown precision");
+    if (pl.mixed && !opts.g_lo) return fail(NEK_ERR_ARG, w + ": mixed precision needs g_lo");
+    if (pl.mixed && !pl.f64_op && !opts.D32) return fail(NEK_ERR_ARG, w + ": the FP32 operator needs D32");
+    const bool g32 = pr == NEK_PREC_F32G32 || pr == NEK_PREC_F64G32;
+    if (pl.mixed && (((uintptr_t)opts.g_lo & (g32 ? 7u : 3u)) || (!pl.f64_op && ((uintptr_t)opts.D32 & 3u))))
         return fail(NEK_ERR_ARG, w + ": misaligned g_lo or D32");
     if (opts.dinv && pl.mixed) return fail(NEK_ERR_UNSUPPORTED, w + ": the Jacobi preconditioner is FP64 only");
     if (opts.dinv && !aligned16(opts.dinv)) return fail(NEK_ERR_ARG, w + ": misaligned dinv");
-    pl.g_dtype = opts.precision == NEK_PREC_F32G32 ? NEK_G_F32 : NEK_G_BF16;
+    pl.g_dtype = g32 ? NEK_G_F32 : NEK_G_BF16;
     pl.drop = pl.mixed ? (opts.reliable_drop > 0.0 ? opts.reliable_drop : reliable_drop_default(opts.precision)) : 0.0;
     if (pl.mixed && !(pl.drop < 1.0)) return fail(NEK_ERR_ARG, w + ": reliable_drop must be < 1");
     pl.check_every = opts.check_every > 0 ? opts.check_every : (pl.mixed ? 4 : 25);
@@ -701,11 +705,14 @@ int cg_run(int64_t E, int N, const double *D, const double *g, const nek_gs *gs,
             fz.x = x;
             fz.dinv = dinvc;
         }
-        hipError_t e = mixed ? launch_ax_f32(E, N, opts.D32, opts.g_lo, pl.g_dtype, p, w, fz, s)
+        hipError_t e = pl.f64_op ? launch_ax_f64_glo(E, N, D, opts.g_lo, pl.g_dtype, p, w, fz, s)
+                     : mixed ? launch_ax_f32(E, N, opts.D32, opts.g_lo, pl.g_dtype, p, w, fz, s)
                              : (node_op ? launch_ax_node_fused(E, N, D, g, p, w, fz, s)
                                         : launch_ax_f64(E, N, D, g, p, w, fz, s));
         if (e != hipSuccess) return e;
-        return launch_cg_assemble_update(gs->cg, r, w, mixed, dinvc, W.axp, node_op ? E : ax_blocks(E, N), red_upd,
+        // the FP32 operator leaves w in FP32
+        return launch_cg_assemble_update(gs->cg, r, w, mixed && !pl.f64_op, dinvc, W.axp,
+                                         node_op ? E : ax_blocks(E, N), red_upd,
                                          sc, s);
     };
     AxFuse plain_cg;   // A x alone, on CG-layout vectors

@@ -74,10 +74,7 @@ using AxShapeFor = AxShape<NX, T, !FUSE && !CGL && sizeof(T) == 8 && NX == 10>;
 
 // Loading the six geometric factors of one point of layer k.
 //   FP64 g: the layout of Listing 1, six planes of n^3 per element (six loads).
-//   FP32 / BF16 g (the mixed form's own copy, written by nek_convert_g): per
-//   element three planes q = 0..2 of n^3 pairs (g_2q, g_2q+1), so a point
-//   needs three 8-byte (FP32) or three 4-byte (BF16) loads, coalesced across
-//   the lanes of a layer.
+//   FP32 / BF16 g: see G6f / G6h below.
 template <typename T, typename GT, int N3>
 struct GLoad;
 
@@ -91,17 +88,20 @@ struct GLoad<double, double, N3> {
     }
 };
 
+// FP32 / BF16 g (the mixed forms' own copy, written by nek_convert_g): the six
+// factors of a point side by side, point after point (24 or 12 bytes), so a
+// point is one load per lane, coalesced across the lanes of a layer.  BF16
+// pairs (g_2q, g_2q+1) share a 32-bit word, g_2q in the low half.
+struct G6f { float v[6]; };
+struct G6h { uint32_t v[3]; };
+
 template <int N3>
 struct GLoad<float, float, N3> {
-    template <bool NT>   // the mixed form's loads carry no hint
+    template <bool NT>
     __device__ static __forceinline__ void load(gptr<const float> ge, int off, float *o) {
-        const gptr<const float2> pp = (gptr<const float2>)ge;
+        const G6f x = ((gptr<const G6f>)ge)[off];
 #pragma unroll
-        for (int q = 0; q < 3; ++q) {
-            const float2 v = pp[q * N3 + off];
-            o[2 * q] = v.x;
-            o[2 * q + 1] = v.y;
-        }
+        for (int q = 0; q < 6; ++q) o[q] = x.v[q];
     }
 };
 
@@ -109,12 +109,36 @@ template <int N3>
 struct GLoad<float, uint16_t, N3> {
     template <bool NT>
     __device__ static __forceinline__ void load(gptr<const uint16_t> ge, int off, float *o) {
-        const gptr<const uint32_t> pp = (gptr<const uint32_t>)ge;
+        const G6h x = ((gptr<const G6h>)ge)[off];
 #pragma unroll
         for (int q = 0; q < 3; ++q) {
-            const uint32_t v = pp[q * N3 + off];
-            o[2 * q] = __uint_as_float(v << 16);
-            o[2 * q + 1] = __uint_as_float(v & 0xffff0000u);
+            o[2 * q] = __uint_as_float(x.v[q] << 16);
+            o[2 * q + 1] = __uint_as_float(x.v[q] & 0xffff0000u);
+        }
+    }
+};
+
+// FP64 arithmetic on FP32 / BF16 factors (NEK_PREC_F64G*): the same loads,
+// widened to FP64.
+template <int N3>
+struct GLoad<double, float, N3> {
+    template <bool NT>
+    __device__ static __forceinline__ void load(gptr<const float> ge, int off, double *o) {
+        const G6f x = ((gptr<const G6f>)ge)[off];
+#pragma unroll
+        for (int q = 0; q < 6; ++q) o[q] = (double)x.v[q];
+    }
+};
+
+template <int N3>
+struct GLoad<double, uint16_t, N3> {
+    template <bool NT>
+    __device__ static __forceinline__ void load(gptr<const uint16_t> ge, int off, double *o) {
+        const G6h x = ((gptr<const G6h>)ge)[off];
+#pragma unroll
+        for (int q = 0; q < 3; ++q) {
+            o[2 * q] = (double)__uint_as_float(x.v[q] << 16);
+            o[2 * q + 1] = (double)__uint_as_float(x.v[q] & 0xffff0000u);
         }
     }
 };
@@ -504,9 +528,14 @@ __device__ __forceinline__ void serve_body(const ServeAxSlot *__restrict__ slots
                                            double *red)
 {
     const ServeAxSlot &S = slots[batch_slot(slots, nslots, (int64_t)blockIdx.x)];
-    if (S.precision == NEK_PREC_F64) serve_dispatch<B, double, double>(S, blockIdx.x, lds, red);
-    else if (S.precision == NEK_PREC_F32G32) serve_dispatch<B, float, float>(S, blockIdx.x, lds, red);
-    else serve_dispatch<B, float, uint16_t>(S, blockIdx.x, lds, red);
+    switch (S.precision) {
+    case NEK_PREC_F64: serve_dispatch<B, double, double>(S, blockIdx.x, lds, red); break;
+    case NEK_PREC_F32G32: serve_dispatch<B, float, float>(S, blockIdx.x, lds, red); break;
+    case NEK_PREC_F32GBF16: serve_dispatch<B, float, uint16_t>(S, blockIdx.x, lds, red); break;
+    case NEK_PREC_F64G32: serve_dispatch<B, double, float>(S, blockIdx.x, lds, red); break;
+    case NEK_PREC_F64GBF16: serve_dispatch<B, double, uint16_t>(S, blockIdx.x, lds, red); break;
+    default: break;
+    }
 }
 
 __global__ void __launch_bounds__(SERVE_THREADS, 4)
@@ -605,22 +634,20 @@ __device__ __forceinline__ uint16_t f64_to_bf16(double v) {
     return (uint16_t)(b >> 16);
 }
 
-// g (six planes of n^3 per element) -> three planes of pairs (g_2q, g_2q+1)
+// g (six planes of n^3 per element) -> six values per point, point after point
 __global__ void convert_g_kernel(int64_t E, int64_t n3, const double *__restrict__ g, int dtype,
                                  void *__restrict__ out) {
-    const int64_t npairs = E * 3 * n3;
+    const int64_t npts = E * n3;
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < npairs; t += stride) {
-        const int64_t e = t / (3 * n3);
-        const int64_t rem = t - e * 3 * n3;
-        const int64_t q = rem / n3;
-        const int64_t pt = rem - q * n3;
-        const double lo = g[(e * 6 + 2 * q) * n3 + pt];
-        const double hi = g[(e * 6 + 2 * q + 1) * n3 + pt];
+    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < npts; t += stride) {
+        const int64_t e = t / n3, pt = t - e * n3;
+        double v[6];
+        for (int q = 0; q < 6; ++q) v[q] = g[(e * 6 + q) * n3 + pt];
         if (dtype == NEK_G_F32) {
-            ((float2 *)out)[t] = make_float2((float)lo, (float)hi);
+            for (int q = 0; q < 6; ++q) ((float *)out)[t * 6 + q] = (float)v[q];
         } else {
-            ((uint32_t *)out)[t] = (uint32_t)f64_to_bf16(lo) | ((uint32_t)f64_to_bf16(hi) << 16);
+            for (int q = 0; q < 3; ++q)
+                ((uint32_t *)out)[t * 3 + q] = (uint32_t)f64_to_bf16(v[2 * q]) | ((uint32_t)f64_to_bf16(v[2 * q + 1]) << 16);
         }
     }
 }
@@ -631,6 +658,8 @@ bool serve_ax_shape(int N, int precision, int64_t E, ServeAxShape &out) {
     if (precision == NEK_PREC_F64) return serve_shape_prec<double, double>(N, E, out);
     if (precision == NEK_PREC_F32G32) return serve_shape_prec<float, float>(N, E, out);
     if (precision == NEK_PREC_F32GBF16) return serve_shape_prec<float, uint16_t>(N, E, out);
+    if (precision == NEK_PREC_F64G32) return serve_shape_prec<double, float>(N, E, out);
+    if (precision == NEK_PREC_F64GBF16) return serve_shape_prec<double, uint16_t>(N, E, out);
     return false;
 }
 
@@ -659,6 +688,44 @@ hipError_t launch_ax_f64(int64_t E, int N, const double *D, const double *g, dou
     return dispatch<double, double>(E, N, D, g, p, w, fz, s);
 }
 
+namespace {
+template <int NX, typename GT>
+hipError_t launch_fused_f64_glo(int64_t E, const double *D, const GT *g_lo, double *p, double *w, const AxFuse &fz,
+                                hipStream_t s)
+{
+    using S = AxShapeFor<NX, double, true, true>;
+    const int64_t blocks = (E + S::EPB - 1) / S::EPB;
+    if (blocks > 0x7fffffff) return hipErrorInvalidValue;
+    hipLaunchKernelGGL((ax_kernel<NX, double, GT, true, true>), dim3((unsigned)blocks), dim3(S::THREADS), 0, s, E,
+                       D, g_lo, p, w, fz);
+    return hipGetLastError();
+}
+
+template <typename GT>
+hipError_t dispatch_f64_glo(int64_t E, int N, const double *D, const GT *g_lo, double *p, double *w,
+                            const AxFuse &fz, hipStream_t s)
+{
+    switch (N + 1) {
+#define NEK_GCASE(NX) \
+    case NX: return launch_fused_f64_glo<NX, GT>(E, D, g_lo, p, w, fz, s);
+        NEK_GCASE(2) NEK_GCASE(3) NEK_GCASE(4) NEK_GCASE(5) NEK_GCASE(6) NEK_GCASE(7) NEK_GCASE(8)
+        NEK_GCASE(9) NEK_GCASE(10) NEK_GCASE(11) NEK_GCASE(12) NEK_GCASE(13) NEK_GCASE(14)
+        NEK_GCASE(15) NEK_GCASE(16)
+#undef NEK_GCASE
+    default: return hipErrorInvalidValue;
+    }
+}
+}  // namespace
+
+hipError_t launch_ax_f64_glo(int64_t E, int N, const double *D, const void *g_lo, int g_dtype, double *p,
+                             double *w, const AxFuse &fz, hipStream_t s)
+{
+    if (fz.sc == nullptr || !fz.cg_layout) return hipErrorInvalidValue;   // the CG-fused form only
+    if (g_dtype == NEK_G_F32) return dispatch_f64_glo<float>(E, N, D, (const float *)g_lo, p, w, fz, s);
+    if (g_dtype == NEK_G_BF16) return dispatch_f64_glo<uint16_t>(E, N, D, (const uint16_t *)g_lo, p, w, fz, s);
+    return hipErrorInvalidValue;
+}
+
 hipError_t launch_ax_f32(int64_t E, int N, const float *D32, const void *g_lo, int g_dtype,
                          double *p, double *w, const AxFuse &fz, hipStream_t s)
 {
@@ -679,7 +746,7 @@ int64_t ax_blocks(int64_t E, int N)
 hipError_t launch_convert_g(int64_t E, int N, const double *g, int g_dtype, void *out, hipStream_t s)
 {
     const int64_t n3 = n3_of(N);
-    int64_t blocks = (E * 3 * n3 + 255) / 256;
+    int64_t blocks = (E * n3 + 255) / 256;
     if (blocks > 65536) blocks = 65536;
     if (blocks < 1) blocks = 1;
     hipLaunchKernelGGL(convert_g_kernel, dim3((unsigned)blocks), dim3(256), 0, s, E, n3, g, g_dtype, out);

@@ -32,7 +32,9 @@ constexpr int MAX_SLOTS = 64;
 static_assert(MAX_SLOTS <= BATCH_MAX_SLOTS, "a batched launch holds at most BATCH_MAX_SLOTS solves");
 constexpr int PREP_THREADS = 4;   // host threads preparing submitted requests
 
-bool is_mixed(int prec) { return prec == NEK_PREC_F32G32 || prec == NEK_PREC_F32GBF16; }
+bool f32_operator(int prec) { return prec == NEK_PREC_F32G32 || prec == NEK_PREC_F32GBF16; }
+bool is_mixed(int prec) { return f32_operator(prec) || prec == NEK_PREC_F64G32 || prec == NEK_PREC_F64GBF16; }
+int g_storage(int prec) { return prec == NEK_PREC_F32G32 || prec == NEK_PREC_F64G32 ? NEK_G_F32 : NEK_G_BF16; }
 
 // Device bytes of one admitted request (arena + solution vector).  The
 // gather-scatter part is bounded by one int32 per local point plus two bit
@@ -51,8 +53,8 @@ Footprint footprint_of(int64_t E, int N, int prec) {
     f.gs = align256(P * sizeof(int32_t) + 4) + 2 * align256((P + 31) / 32 * sizeof(uint32_t));
     f.D = align256(n2 * sizeof(double));
     f.D32 = align256(n2 * sizeof(float));
-    f.glo = prec == NEK_PREC_F32G32 ? align256(6 * P * sizeof(float))
-          : prec == NEK_PREC_F32GBF16 ? align256(6 * P * sizeof(uint16_t)) : 0;
+    f.glo = !is_mixed(prec) ? 0
+          : g_storage(prec) == NEK_G_F32 ? align256(6 * P * sizeof(float)) : align256(6 * P * sizeof(uint16_t));
     f.ws = cg_layout(E, N, 0).total;
     f.arena = f.g + f.b + f.gs + f.D + f.D32 + f.glo + f.ws;
     f.x = align256(P * sizeof(double));
@@ -439,8 +441,7 @@ struct nek_server {
                                         nullptr, nullptr, stream));
         }
         if (is_mixed(q.precision))
-            NEK_HIP(launch_convert_g(R->E, q.N, S->g,
-                                     q.precision == NEK_PREC_F32G32 ? NEK_G_F32 : NEK_G_BF16, S->glo, stream));
+            NEK_HIP(launch_convert_g(R->E, q.N, S->g, g_storage(q.precision), S->glo, stream));
         const double drop = is_mixed(q.precision) ? reliable_drop_default(q.precision) : 0.0;
         NEK_HIP(launch_cg_reset(S->W.sc, S->W.tickets, N_SITES * RED_TICKETS, q.max_iter, q.rel_tol, drop,
                                 stream));
@@ -565,7 +566,7 @@ struct nek_server {
                 A.E = E;
                 A.nx = q.N + 1;
                 A.precision = q.precision;
-                A.D = mixed ? (const void *)S->D32 : (const void *)S->D;
+                A.D = f32_operator(q.precision) ? (const void *)S->D32 : (const void *)S->D;
                 A.g = mixed ? (const void *)S->glo : (const void *)S->g;
                 A.p = S->W.p;
                 A.w = S->W.w;
@@ -586,7 +587,7 @@ struct nek_server {
             U.nparts = nparts;
             U.red = S->W.site(SITE_UPDATE);
             U.sc = S->W.sc;
-            U.w_f32 = mixed ? 1 : 0;   // the FP32 operator leaves w in FP32
+            U.w_f32 = f32_operator(q.precision) ? 1 : 0;   // the FP32 operator leaves w in FP32
             blk[L_ASM] += U.nblocks;
             scp[ordered.size()] = S->W.sc;
             ordered.push_back(S);

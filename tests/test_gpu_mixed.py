@@ -1,5 +1,6 @@
-"""Mixed-precision form: FP32 operator (g in FP32 or BF16) inside FP64
-reliable-update CG, against the FP64 oracle.
+"""Mixed-precision forms inside FP64 reliable-update CG, against the FP64
+oracle: the FP32 operator with g in FP32 or BF16 (NEK_PREC_F32G*), and the
+FP64 operator reading g stored in FP32 or BF16 (NEK_PREC_F64G*).
 
 * nek_convert_g: bit-exact against numpy's round-to-nearest-even (FP32 via
   astype, BF16 from the FP32 bits).
@@ -11,7 +12,10 @@ reliable-update CG, against the FP64 oracle.
   below that).
 * mixed CG to a true relative residual of 1e-10 on the manufactured solution:
   status OK, ||b - A64 x|| / ||b|| <= 1e-10 evaluated in FP64 by the library,
-  and the solution within 1e-8 of the oracle's FP64 solve to 1e-13.
+  and the solution within 1e-8 of the oracle's FP64 solve to 1e-13; with the
+  FP64 operator on FP32 g the iteration count stays within 5% of the FP64
+  solve's (FP32 contractions, not FP32 storage of g, cost the FP32 operator
+  its extra iterations).
 """
 import numpy as np
 import pytest
@@ -52,9 +56,9 @@ def _bf16_to_f64(bits):
     return (bits.astype(np.uint32) << 16).view(np.float32).astype(np.float64)
 
 
-def _paired(a, E, n3):
-    """[e][c][pt] -> [e][q][pt][2] with (c = 2q, 2q+1): the paired layout."""
-    return a.reshape(E, 3, 2, n3).transpose(0, 1, 3, 2).reshape(-1)
+def _point_major(a, E, n3):
+    """[e][c][pt] -> [e][pt][c]: the six factors of a point side by side."""
+    return a.reshape(E, 6, n3).transpose(0, 2, 1).reshape(-1)
 
 
 def test_convert_g_bit_exact(nek):
@@ -62,9 +66,9 @@ def test_convert_g_bit_exact(nek):
     g = _dev(m.g)
     n3 = 6 ** 3
     g32 = nek.convert_g(g, 5, nek.NEK_G_F32)
-    np.testing.assert_array_equal(g32.cpu().numpy(), _paired(m.g.astype(np.float32), m.E, n3))
+    np.testing.assert_array_equal(g32.cpu().numpy(), _point_major(m.g.astype(np.float32), m.E, n3))
     g16 = nek.convert_g(g, 5, nek.NEK_G_BF16)
-    np.testing.assert_array_equal(g16.cpu().numpy().view(np.uint16), _paired(_bf16_rne(m.g), m.E, n3))
+    np.testing.assert_array_equal(g16.cpu().numpy().view(np.uint16), _point_major(_bf16_rne(m.g), m.E, n3))
 
 
 @pytest.mark.parametrize("N", [1, 3, 5, 7, 9, 11, 15])
@@ -91,7 +95,17 @@ def test_ax_f32_against_oracle_on_rounded_inputs(nek, N, gdt):
     assert _rel(w, full) <= (2e-6 if gdt == "f32" else 2e-2)
 
 
-@pytest.mark.parametrize("prec", ["f32", "bf16"])
+def _prec(nek, prec):
+    """(precision mode, storage type of g) of a test label"""
+    return {"f32": (nek.NEK_PREC_F32G32, nek.NEK_G_F32), "bf16": (nek.NEK_PREC_F32GBF16, nek.NEK_G_BF16),
+            "f64g32": (nek.NEK_PREC_F64G32, nek.NEK_G_F32),
+            "f64gbf16": (nek.NEK_PREC_F64GBF16, nek.NEK_G_BF16)}[prec]
+
+
+PRECS = ["f32", "bf16", "f64g32", "f64gbf16"]
+
+
+@pytest.mark.parametrize("prec", PRECS)
 def test_mixed_cg_reaches_1e10_true_residual(nek, prec):
     box, N = (4, 4, 4), 7
     m = oracle.box_mesh(*box, N, synth.AMP, synth.geom_coeffs())
@@ -99,8 +113,7 @@ def test_mixed_cg_reaches_1e10_true_residual(nek, prec):
     gs = nek.GatherScatter(m.E, N, m.glo, m.dirichlet)
     Dt, gt = _dev(m.D), _dev(m.g)
     D32 = _dev(m.D.astype(np.float32))
-    code = nek.NEK_G_F32 if prec == "f32" else nek.NEK_G_BF16
-    precision = nek.NEK_PREC_F32G32 if prec == "f32" else nek.NEK_PREC_F32GBF16
+    precision, code = _prec(nek, prec)
     glo = nek.convert_g(gt, N, code)
     x, res = nek.cg_solve(Dt, gt, gs, _dev(b), max_iter=3000, rel_tol=1e-10, precision=precision,
                           D32=D32, g_lo=glo)
@@ -116,10 +129,12 @@ def test_mixed_cg_reaches_1e10_true_residual(nek, prec):
     # the FP64 solve of the same system takes a comparable number of iterations
     _, r64 = nek.cg_solve(Dt, gt, gs, _dev(b), max_iter=3000, rel_tol=1e-10)
     assert res.iters <= 1.5 * r64.iters + 20
+    if prec == "f64g32":
+        assert res.iters <= 1.05 * r64.iters + 5, (res.iters, r64.iters)
     gs.close()
 
 
-@pytest.mark.parametrize("prec", ["f32", "bf16"])
+@pytest.mark.parametrize("prec", PRECS)
 def test_mixed_full_size_true_residual_by_the_oracle(nek, prec):
     # the mixed-precision workload at its full size (E = 4096, N = 9, manufactured
     # rhs, 1e-10): the oracle evaluates b - A x of the GPU's solution itself
@@ -128,8 +143,7 @@ def test_mixed_full_size_true_residual_by_the_oracle(nek, prec):
     b = oracle.manufactured_rhs(m)
     gs = nek.GatherScatter(m.E, N, m.glo, m.dirichlet)
     Dt, gt = _dev(m.D), _dev(m.g)
-    code = nek.NEK_G_F32 if prec == "f32" else nek.NEK_G_BF16
-    precision = nek.NEK_PREC_F32G32 if prec == "f32" else nek.NEK_PREC_F32GBF16
+    precision, code = _prec(nek, prec)
     x, res = nek.cg_solve(Dt, gt, gs, _dev(b), max_iter=5000, rel_tol=1e-10, precision=precision,
                           D32=_dev(m.D.astype(np.float32)), g_lo=nek.convert_g(gt, N, code))
     torch.cuda.synchronize()
@@ -157,6 +171,9 @@ def test_mixed_cg_fixed_iterations_and_errors(nek):
     x, res = nek.cg_solve(Dt, gt, gs, _dev(b), max_iter=20, precision=nek.NEK_PREC_F32G32,
                           D32=_dev(m.D.astype(np.float32)), g_lo=glo)
     assert res.iters == 20 and res.status == 0 and res.rel_res_true > 0
+    # the FP64 operator on FP32 g needs no D32
+    x2, res2 = nek.cg_solve(Dt, gt, gs, _dev(b), max_iter=20, precision=nek.NEK_PREC_F64G32, g_lo=glo)
+    assert res2.iters == 20 and res2.status == 0 and res2.rel_res_true > 0
     # mixed precision without the FP32 inputs is an argument error
     with pytest.raises(nek.NekError) as ei:
         nek._check(nek._lib.nek_cg_solve(m.E, 4, Dt.data_ptr(), gt.data_ptr(), gs.handle,

@@ -100,17 +100,21 @@ def test_alone_equals_in_the_mix_bitwise(nek):
     B = ((3, 3, 2), 5, nek.NEK_PREC_F32G32, 2)
     C = ((2, 2, 4), 9, nek.NEK_PREC_F64, 3)
     Dq = ((4, 2, 2), 7, nek.NEK_PREC_F32GBF16, 4)
+    F = ((3, 2, 2), 9, nek.NEK_PREC_F64G32, 5)       # FP64 operator on FP32 g
     xa, ra, _ = _serve(nek, [A])
     xb, rb, _ = _serve(nek, [B])
-    xm, rm, trace = _serve(nek, [A, C, B, Dq], stagger=7)
+    xf, rf, _ = _serve(nek, [F])
+    xm, rm, trace = _serve(nek, [A, C, B, Dq, F], stagger=7)
     assert max(t[1] for t in trace) >= 2            # solves ran side by side
     np.testing.assert_array_equal(xm[0], xa[0])
     np.testing.assert_array_equal(xm[2], xb[0])
+    np.testing.assert_array_equal(xm[4], xf[0])
     assert rm[0]["iters"] == ra[0]["iters"] and rm[2]["iters"] == rb[0]["iters"]
+    assert rm[4]["iters"] == rf[0]["iters"]
     for k in rm:
         assert rm[k]["status"] == 0, rm[k]
         assert rm[k]["rel_res_true"] <= 1e-9
-    assert rm[2]["n_replacements"] >= 1 and rm[3]["n_replacements"] >= 1
+    assert rm[2]["n_replacements"] >= 1 and rm[3]["n_replacements"] >= 1 and rm[4]["n_replacements"] >= 1
 
 
 def _cg_solve_box(nek, box, N, b, rel_tol=1e-10):
