@@ -7,7 +7,7 @@ a general one.  These cases reach what the box tests of the paper's shapes do
 not:
 
 * every degree N = 1..15 (N = 1 has no points with 0 < i < n-1, N = 2 one per
-  row), 40 iterations (12 at N = 1): the solution within rel-L2 1e-11 of the
+  row), 40 iterations (12 at N = 1): the solution within rel-L2 1e-12 of the
   oracle's and the same recurrence residual to 1e-9 relative;
 * a numbering in which groups of nodes are glued into one: nodes with 3, 5, 6
   and 12 copies (the general rows, including the CSR rows of more than 8

@@ -2,7 +2,7 @@
 FP64 oracle: the CG layout, the gather-scatter maps and the assemble-update
 on shapes no other test picks (thin boxes, one element across, odd and even
 point counts).  30 iterations of CG and of Jacobi PCG each; the same bars as
-the fixed-shape tests (solution rel-L2 <= 1e-11 after 30 iterations, same
+the fixed-shape tests (solution rel-L2 <= 1e-12 after 30 iterations, same
 recurrence residual to 1e-9 relative).
 """
 import numpy as np
