@@ -48,10 +48,15 @@ probe_kernel(int64_t n, const double *__restrict__ src, int64_t stride, double *
             // in block base / chunk of the interleaved layout
             const dvec2 *s2 = BLK ? (const dvec2 *)src + ((base / chunk) * R + k) * chunk
                                   : (const dvec2 *)(src + (int64_t)k * stride) + base;
+            // every lane loads (a lane past the end reads the last pair again):
+            // no load in a branch, so all R * PROBE_PAIRS loads are in flight
+            // together instead of one at a time
 #pragma unroll
             for (int m = 0; m < PROBE_PAIRS; ++m) {
                 const int64_t o = threadIdx.x + (int64_t)m * PROBE_THREADS;
-                if (base + o < npairs) acc[m] += NT ? __builtin_nontemporal_load(&s2[o]) : s2[o];
+                const int64_t oc = base + o < npairs ? o : npairs - 1 - base;
+                const dvec2 v = NT ? __builtin_nontemporal_load(&s2[oc]) : s2[oc];
+                acc[m] += base + o < npairs ? v : dvec2{0.0, 0.0};
             }
         }
 #pragma unroll
