@@ -515,8 +515,13 @@ __device__ __forceinline__ void assemble_update_body(int lb, int nb, int64_t P, 
     row_finish<PRE>(J0, r, alpha, acc);
     row_finish<PRE>(J1, r, alpha, acc);
     chunk_finish<PRE>(base0, r, alpha, Q, acc);
+    // Large meshes: the further row blocks and chunks, two at a time in
+    // flight (the indices or bits of the next are loaded before the current
+    // one is updated); the updates keep the order of a plain loop.
     {
         int seen = 0;   // row blocks of the common kinds past the first two
+        RowJob cur;
+        bool have = false;
         for (int g = 0; g < a.ngroups; ++g) {
             const GsGroup &G = a.grp[g];
             if (G.kind == 0) continue;
@@ -526,22 +531,34 @@ __device__ __forceinline__ void assemble_update_body(int lb, int nb, int64_t P, 
             for (int vb = u0 + lq; vb < u1; vb += per) {
                 if (fast_kind(G.kind)) {
                     if (seen++ < 2) continue;
-                    RowJob J;
-                    row_setup(a, vb, J);
-                    row_load<PRE, WT>(J, w, r, dinv);
-                    row_finish<PRE>(J, r, alpha, acc);
+                    RowJob nx;
+                    row_setup(a, vb, nx);
+                    if (have) row_finish<PRE>(cur, r, alpha, acc);
+                    row_load<PRE, WT>(nx, w, r, dinv);
+                    cur = nx;
+                    have = true;
                 } else {   // rare kinds: corners of 8 elements, many-copy CSR rows
+                    if (have) row_finish<PRE>(cur, r, alpha, acc);
+                    have = false;
                     asm_vblock<PRE, WT>(a, vb, w, r, dinv, alpha, acc);
                 }
             }
         }
+        if (have) row_finish<PRE>(cur, r, alpha, acc);
     }
-    for (int64_t c = c0 + lq + per; c < c1; c += per) {
-        const int64_t base = c * VEC_CHUNK;
-        PairChunk<PRE> Qn;
-        chunk_bits<PRE>(base, npairs, rowed, Qn);
-        chunk_load<PRE, WT>(base, r, w, dinv, Qn);
-        chunk_finish<PRE>(base, r, alpha, Qn, acc);
+    {
+        PairChunk<PRE> cur;
+        int64_t cbase = -1;
+        for (int64_t c = c0 + lq + per; c < c1; c += per) {
+            const int64_t base = c * VEC_CHUNK;
+            PairChunk<PRE> nx;
+            chunk_bits<PRE>(base, npairs, rowed, nx);
+            if (cbase >= 0) chunk_finish<PRE>(cbase, r, alpha, cur, acc);
+            chunk_load<PRE, WT>(base, r, w, dinv, nx);
+            cur = nx;
+            cbase = base;
+        }
+        if (cbase >= 0) chunk_finish<PRE>(cbase, r, alpha, cur, acc);
     }
     if ((P & 1) && lb == nb - 1 && threadIdx.x == VEC_THREADS - 1) {
         const int64_t t = P - 1;
