@@ -4,7 +4,8 @@
 // by RED_GROUP; the workgroup that takes the last ticket of its group sums the
 // group's partials in index order, and the workgroup that finishes the last
 // group sums the group sums (and any partials left by an earlier launch) in
-// index order.  The order of every sum is fixed by the launch shape, so the
+// index order.  A grid of at most RED_ONE_LEVEL workgroups uses one level:
+// the workgroup that takes the last ticket sums all partials in index order.  The order of every sum is fixed by the launch shape, so the
 // result is bitwise reproducible.  Every counter sits on a cache line of its
 // own: atomics on one line are serialised, and with the counters packed the
 // reduction at the end of a 2048-workgroup launch took 3 us longer; groups of
@@ -21,6 +22,14 @@ constexpr int RED_GROUP = 16;          // workgroups per first-level ticket
 constexpr int RED_MAX_BLOCKS = 2048;   // grid cap of the reduction kernels
 constexpr int RED_MAX_GROUPS = RED_MAX_BLOCKS / RED_GROUP;
 constexpr int RED_TICKET_STRIDE = 32;  // counters 128 bytes apart
+// grids of at most this many workgroups take one ticket level: the second
+// level's store, ticket and loads cost more than the contention of every
+// workgroup on one counter there (the assemble-update at N = 9: 1.0-1.1 us
+// less with 80 to 280 workgroups, 1.1 us more with 528, 7 us more with 1016)
+#ifndef NEK_RED_ONE_LEVEL
+#define NEK_RED_ONE_LEVEL 384
+#endif
+constexpr unsigned int RED_ONE_LEVEL = NEK_RED_ONE_LEVEL;
 constexpr int RED_TICKETS = (1 + RED_MAX_GROUPS) * RED_TICKET_STRIDE;   // words per reduction site
 
 __device__ __forceinline__ double wave_sum(double v) {
@@ -124,6 +133,35 @@ __device__ bool grid_finish_k(const double *s, const RedSite &r, double *out, do
     const gptr<double> gpart = (gptr<double>)r.gpart;
     const gptr<unsigned int> tk = (gptr<unsigned int>)r.tk;
     const gptr<const double> extra = (gptr<const double>)r.extra;
+    if (nb <= RED_ONE_LEVEL) {
+        // one level: every workgroup takes a ticket on the top counter, the
+        // last sums all partials in index order
+        if (threadIdx.x == 0) {
+#pragma unroll
+            for (int c = 0; c < K; ++c) store_coherent(part + (size_t)lb * K + c, s[c]);
+            const unsigned int t = take_ticket(tk);
+            stage = (t == nb - 1u) ? 2 : 0;
+        }
+        __syncthreads();
+        if (stage != 2) return false;
+        double e = 0.0;
+        for (long q = threadIdx.x; q < r.nextra; q += NT) e += load_coherent(extra + q);
+        e = block_sum<NT>(e, lds);
+        double u[K];
+#pragma unroll
+        for (int c = 0; c < K; ++c) {
+            u[c] = 0.0;
+            for (long q = threadIdx.x; q < (long)nb; q += NT) u[c] += load_coherent(part + q * K + c);
+            u[c] = block_sum<NT>(u[c], lds);
+        }
+        if (threadIdx.x == 0) {
+            tk[0] = 0u;
+            out[0] = e + u[0];
+#pragma unroll
+            for (int c = 1; c < K; ++c) out[c] = u[c];
+        }
+        return true;
+    }
     const unsigned int grp = lb / RED_GROUP;
     const unsigned int ngroups = (nb + RED_GROUP - 1) / RED_GROUP;
     const unsigned int gsize = (grp + 1 == ngroups) ? nb - grp * RED_GROUP : RED_GROUP;
