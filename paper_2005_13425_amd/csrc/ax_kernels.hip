@@ -290,9 +290,17 @@ __device__ __forceinline__ void ax_body(int64_t blk, int64_t E, kptr<T> D, gptr<
 
     // ---- 1. u column (in the CG: x += alpha p_old and p <- r + beta p_old first)
     const int64_t base = e * N3 + c;
-    // FP64 p at the thread's vector entries, for the (p, w) sum (the CG layout
-    // reads it back from memory at the end instead: fewer registers)
-    double pcol[FUSE && !CGL ? NX : 1];
+    // (p, A_L p) in the FP64 operator: p^T D^T G D p = (D p)^T G (D p), summed
+    // point by point at the geometric multiply from the gradient and the
+    // multiplied gradient in registers.  Taking it from p and w instead meant
+    // reading p again at the end, and p written at the start was no longer in
+    // L2 by then: 32.8 MB more to read per launch at E = 4096, N = 9.  The
+    // FP32 operator keeps the FP64 sum of p times its FP32 w.
+    constexpr bool EPW = FUSE && sizeof(T) == 8;
+    // FP64 p at the thread's vector entries, for that sum in the FP32 operator
+    // (the CG layout reads it back from memory at the end instead: fewer
+    // registers)
+    double pcol[FUSE && !CGL && !EPW ? NX : 1];
     {
         double pv[NX];
         if (active) {
@@ -337,7 +345,7 @@ __device__ __forceinline__ void ax_body(int64_t blk, int64_t E, kptr<T> D, gptr<
 #pragma unroll
             for (int k = 0; k < NX; ++k) pv[k] = 0.0;
         }
-        if constexpr (FUSE && !CGL) {
+        if constexpr (FUSE && !CGL && !EPW) {
 #pragma unroll
             for (int k = 0; k < NX; ++k) pcol[k] = pv[k];
         }
@@ -401,6 +409,7 @@ __device__ __forceinline__ void ax_body(int64_t blk, int64_t E, kptr<T> D, gptr<
 
     // ---- 3. column: symmetric geometric multiply
     T ut[NX];
+    double pw = 0.0;
 #pragma unroll
     for (int k = 0; k < NX; ++k) {
         const T *gc = gq[k % PF];
@@ -413,6 +422,7 @@ __device__ __forceinline__ void ax_body(int64_t blk, int64_t E, kptr<T> D, gptr<
             utv = gc[2] * wrv + gc[4] * wsv + gc[5] * wt[k];
             B1[k * LS + col] = urv;
             B0[k * LS + col] = usv;
+            if constexpr (EPW) pw += wrv * urv + wsv * usv + wt[k] * utv;
         }
         ut[k] = utv;
         if (k + PF < NX) GLoad<T, GT, N3, NN>::template load<STREAM>(gs, k + PF, gq[k % PF]);
@@ -464,7 +474,6 @@ __device__ __forceinline__ void ax_body(int64_t blk, int64_t E, kptr<T> D, gptr<
             }
         }
     }
-    double pw = 0.0;
     if constexpr (CGL) {
         // ---- 6b. w leaves LDS at the thread's CG-layout entries; the CG-fused
         // FP32 operator stores its FP32 result as it is (the assemble-update
@@ -476,10 +485,10 @@ __device__ __forceinline__ void ax_body(int64_t blk, int64_t E, kptr<T> D, gptr<
             for (int k = 0; k < NX; ++k) {
                 const T wv = B0[k * LS + colv];
                 ((gptr<WT>)w)[base + k * NN] = (WT)wv;
-                if constexpr (FUSE) pw += p[base + k * NN] * (double)wv;   // written by this thread
+                if constexpr (FUSE && !EPW) pw += p[base + k * NN] * (double)wv;   // written by this thread
             }
         }
-    } else if constexpr (FUSE) {
+    } else if constexpr (FUSE && !EPW) {
         if (active) {
 #pragma unroll
             for (int k = 0; k < NX; ++k) pw += pcol[k] * (double)B0[k * LS + col];
