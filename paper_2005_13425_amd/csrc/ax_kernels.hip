@@ -290,17 +290,12 @@ __device__ __forceinline__ void ax_body(int64_t blk, int64_t E, kptr<T> D, gptr<
 
     // ---- 1. u column (in the CG: x += alpha p_old and p <- r + beta p_old first)
     const int64_t base = e * N3 + c;
-    // (p, A_L p) in the FP64 operator: p^T D^T G D p = (D p)^T G (D p), summed
+    // (p, A_L p) in the CG: p^T D^T G D p = (D p)^T G (D p), summed in FP64
     // point by point at the geometric multiply from the gradient and the
     // multiplied gradient in registers.  Taking it from p and w instead meant
     // reading p again at the end, and p written at the start was no longer in
-    // L2 by then: 32.8 MB more to read per launch at E = 4096, N = 9.  The
-    // FP32 operator keeps the FP64 sum of p times its FP32 w.
-    constexpr bool EPW = FUSE && sizeof(T) == 8;
-    // FP64 p at the thread's vector entries, for that sum in the FP32 operator
-    // (the CG layout reads it back from memory at the end instead: fewer
-    // registers)
-    double pcol[FUSE && !CGL && !EPW ? NX : 1];
+    // L2 by then: 32.8 MB more to read per launch at E = 4096, N = 9 (the FP32
+    // operator's iterations were unchanged by the switch, 4-5% faster).
     {
         double pv[NX];
         if (active) {
@@ -344,10 +339,6 @@ __device__ __forceinline__ void ax_body(int64_t blk, int64_t E, kptr<T> D, gptr<
         } else {
 #pragma unroll
             for (int k = 0; k < NX; ++k) pv[k] = 0.0;
-        }
-        if constexpr (FUSE && !CGL && !EPW) {
-#pragma unroll
-            for (int k = 0; k < NX; ++k) pcol[k] = pv[k];
         }
         if (in_slab) {
 #pragma unroll
@@ -422,7 +413,8 @@ __device__ __forceinline__ void ax_body(int64_t blk, int64_t E, kptr<T> D, gptr<
             utv = gc[2] * wrv + gc[4] * wsv + gc[5] * wt[k];
             B1[k * LS + col] = urv;
             B0[k * LS + col] = usv;
-            if constexpr (EPW) pw += wrv * urv + wsv * usv + wt[k] * utv;
+            if constexpr (FUSE)
+                pw += (double)wrv * (double)urv + (double)wsv * (double)usv + (double)wt[k] * (double)utv;
         }
         ut[k] = utv;
         if (k + PF < NX) GLoad<T, GT, N3, NN>::template load<STREAM>(gs, k + PF, gq[k % PF]);
@@ -485,18 +477,13 @@ __device__ __forceinline__ void ax_body(int64_t blk, int64_t E, kptr<T> D, gptr<
             for (int k = 0; k < NX; ++k) {
                 const T wv = B0[k * LS + colv];
                 ((gptr<WT>)w)[base + k * NN] = (WT)wv;
-                if constexpr (FUSE && !EPW) pw += p[base + k * NN] * (double)wv;   // written by this thread
             }
         }
-    } else if constexpr (FUSE && !EPW) {
-        if (active) {
-#pragma unroll
-            for (int k = 0; k < NX; ++k) pw += pcol[k] * (double)B0[k * LS + col];
-        }
     }
-    // ---- 7. CG: sum of p (A_L p) over all local points.  For a continuous p
-    // that vanishes on masked nodes this is (p, mask(dssum(A_L p))) over unique
-    // nodes, so the assembly needs no product of its own.
+    // ---- 7. CG: sum of p (A_L p) over all local points (formed in step 3).
+    // For a continuous p that vanishes on masked nodes this is
+    // (p, mask(dssum(A_L p))) over unique nodes, so the assembly needs no
+    // product of its own.
     if constexpr (FUSE) {
         if (fz.partials != nullptr) {
             const double bs = seg_sum<S::THREADS>(pw, red, rbase);
