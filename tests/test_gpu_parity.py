@@ -189,6 +189,23 @@ def test_cg_100_iterations_full_shapes(nek, box):
     assert res.iters == 100 and err <= TOL
 
 
+def test_cg_30_iterations_large_mesh(nek):
+    # E = 8192 at N = 9: the assemble-update's workgroups take several row
+    # blocks and chunks of pairs each, two at a time in flight
+    box, N = (32, 16, 16), 9
+    m = _mesh(box, N)
+    b = oracle.lattice_to_local(m, synth.lattice_uniform(*box, N))
+    gs = nek.GatherScatter(m.E, N, m.glo, m.dirichlet)
+    x, res = nek.cg_solve(_dev(m.D), _dev(m.g), gs, _dev(b), max_iter=30)
+    torch.cuda.synchronize()
+    gs.close()
+    ref = oracle.cg(m, b, max_iter=30)
+    err = _rel(x, ref.x)
+    print(f"CG E={m.E} N=9, 30 iterations: rel-L2 {err:.2e}", flush=True)
+    assert res.iters == 30 and err <= TOL
+    assert abs(res.rel_res - ref.res_hist[-1]) <= 1e-9 * ref.res_hist[-1]
+
+
 def test_cg_to_tolerance(nek):
     m, x, res, ref = _cg_case(nek, (4, 4, 4), 7, 2000, rel_tol=1e-13)
     assert res.status == 0 and ref.status == 0
