@@ -618,6 +618,26 @@ assemble_update_batch_kernel(const AsmSlot *__restrict__ slots, int nslots) {
                                             (gptr<const double>)S.axparts, S.nparts, S.red, (gptr<CgScalars>)S.sc);
 }
 
+__global__ void __launch_bounds__(VEC_THREADS)
+assemble_update_batch_karg_kernel(AsmKargTable t) {
+    const int64_t blk = (int64_t)blockIdx.x;
+    int i = 0;
+#pragma unroll
+    for (int k = 1; k < ASM_KARG_SLOTS; ++k) i += t.block0[k] <= blk ? 1 : 0;
+    const AsmSlot &S = t.slot[i];
+    // the slots tile the grid (checked by the launcher), so lb < S.nblocks
+    // and every field of S is requested at once
+    const int lb = (int)(blk - S.block0);
+    if (S.w_f32)
+        assemble_update_body<false, float>(lb, (int)S.nblocks, S.P, S.args, (gptr<const uint32_t>)S.rowed,
+                                           (gptr<double>)S.r, (gptr<const float>)S.w, nullptr,
+                                           (gptr<const double>)S.axparts, S.nparts, S.red, (gptr<CgScalars>)S.sc);
+    else
+        assemble_update_body<false, double>(lb, (int)S.nblocks, S.P, S.args, (gptr<const uint32_t>)S.rowed,
+                                            (gptr<double>)S.r, (gptr<const double>)S.w, nullptr,
+                                            (gptr<const double>)S.axparts, S.nparts, S.red, (gptr<CgScalars>)S.sc);
+}
+
 __global__ void gather_scalars_kernel(CgScalars *const *src, int n, CgScalars *dst) {
     typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
     static_assert(sizeof(CgScalars) % sizeof(u32x4) == 0, "CgScalars is copied in 16-byte pieces");
@@ -828,6 +848,22 @@ hipError_t launch_assemble_update_batch(const AsmSlot *slots, int nslots, int64_
         return hipErrorInvalidValue;
     hipLaunchKernelGGL(assemble_update_batch_kernel, dim3((unsigned)blocks), dim3(VEC_THREADS), 0, s, slots,
                        nslots);
+    return hipGetLastError();
+}
+
+hipError_t launch_assemble_update_batch_karg(const AsmSlot *slots, int nslots, int64_t blocks, hipStream_t s) {
+    if (nslots < 1 || nslots > ASM_KARG_SLOTS || blocks < 1 || blocks > 0x7fffffff || slots[0].block0 != 0)
+        return hipErrorInvalidValue;
+    for (int k = 0; k < nslots; ++k) {
+        const int64_t end = k + 1 < nslots ? slots[k + 1].block0 : blocks;
+        if (slots[k].nblocks < 1 || slots[k].block0 + slots[k].nblocks != end) return hipErrorInvalidValue;
+    }
+    AsmKargTable t;
+    for (int k = 0; k < ASM_KARG_SLOTS; ++k) {
+        t.block0[k] = k < nslots ? slots[k].block0 : INT64_MAX;
+        t.slot[k] = slots[k < nslots ? k : nslots - 1];
+    }
+    hipLaunchKernelGGL(assemble_update_batch_karg_kernel, dim3((unsigned)blocks), dim3(VEC_THREADS), 0, s, t);
     return hipGetLastError();
 }
 

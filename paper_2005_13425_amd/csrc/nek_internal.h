@@ -333,6 +333,18 @@ struct AsmSlot {
     int w_f32;
 };
 hipError_t launch_assemble_update_batch(const AsmSlot *slots, int nslots, int64_t blocks, hipStream_t s);
+// The same launch with the slots passed by value among the kernel arguments
+// (at most ASM_KARG_SLOTS of them): a workgroup then finds its slot without
+// first reading the device table, and takes every field of it in one round
+// trip.  `slots` is a host array, read at the call; the slots must tile the
+// grid (slot k's workgroups end where slot k+1's begin, the last at `blocks`).
+constexpr int ASM_KARG_SLOTS = 8;
+struct AsmKargTable {
+    int64_t block0[ASM_KARG_SLOTS];   // slots[i].block0, unused entries INT64_MAX
+    AsmSlot slot[ASM_KARG_SLOTS];
+};
+static_assert(sizeof(AsmKargTable) <= 4096, "kernel arguments are limited to 4 KiB");
+hipError_t launch_assemble_update_batch_karg(const AsmSlot *slots, int nslots, int64_t blocks, hipStream_t s);
 
 // copy the scalars of several solves into one contiguous array
 hipError_t launch_gather_scalars(CgScalars *const *src, int n, CgScalars *dst, hipStream_t s);

@@ -711,6 +711,9 @@ struct nek_server {
             const ServeNodeSlot *node9 = node + MAX_SLOTS;
             const AsmSlot *asl = (const AsmSlot *)(node9 + MAX_SLOTS);
             CgScalars *const *scp = (CgScalars *const *)(asl + MAX_SLOTS);
+            // the host image of the same assembly slots, for launches that take them by value
+            const AsmSlot *asl_host =
+                (const AsmSlot *)((const ServeNodeSlot *)((const ServeAxSlot *)T.host + 2 * MAX_SLOTS) + 2 * MAX_SLOTS);
             const int base_iters = std::max(1, iters);
             for (int it = 0; it < base_iters; ++it) {
                 for (int j = 0; j < wmax; ++j) {
@@ -722,7 +725,10 @@ struct nek_server {
                         NEK_HIP(launch_ax_node_serve(node, V.count[j], V.blocks[j], V.lds[j], false, stream));
                     if (V9.count[j])
                         NEK_HIP(launch_ax_node_serve(node9, V9.count[j], V9.blocks[j], V9.lds[j], true, stream));
-                    if (U.count[j]) NEK_HIP(launch_assemble_update_batch(asl, U.count[j], U.blocks[j], stream));
+                    if (U.count[j] && U.count[j] <= ASM_KARG_SLOTS)
+                        NEK_HIP(launch_assemble_update_batch_karg(asl_host, U.count[j], U.blocks[j], stream));
+                    else if (U.count[j])
+                        NEK_HIP(launch_assemble_update_batch(asl, U.count[j], U.blocks[j], stream));
                 }
             }
             // snapshot of every active solve's scalars into buffer q; the snapshot

@@ -186,6 +186,22 @@ def test_mix_of_every_operator_form_bitwise_vs_cg_solve(nek):
         np.testing.assert_array_equal(xs[k], x)
 
 
+def test_more_solves_than_the_by_value_slot_table_holds(nek):
+    """Twelve small FP64 requests admitted together: their assembly is one
+    batched launch over more slots than its kernel arguments carry, so it
+    reads them from the device table.  Every solution is bitwise that of
+    nek_cg_solve, with the same iteration count."""
+    reqs = [((2, 2, 2), 5, nek.NEK_PREC_F64, 60 + k) for k in range(12)]
+    print("serve 12 requests side by side", flush=True)
+    xs, res, trace = _serve(nek, reqs, budget=16 * GB)
+    assert max(act for _, act, _ in trace) == len(reqs)
+    for k, (box, N, prec, seed) in enumerate(reqs):
+        assert res[k]["status"] == 0, (k, res[k])
+        x, r = _cg_solve_box(nek, box, N, _rhs(nek, box, N, seed))
+        assert r.iters == res[k]["iters"], (k, r.iters, res[k]["iters"])
+        np.testing.assert_array_equal(xs[k], x)
+
+
 def test_admission_by_footprint(nek):
     box, N = (4, 4, 4), 7
     f = nek.server_footprint(*box, N)
