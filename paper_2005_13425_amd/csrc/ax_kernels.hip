@@ -65,10 +65,12 @@ struct AxShape {
 #endif
 };
 
-// The plain FP64 operator at n = 10 runs two elements per workgroup: 2048
-// workgroups at E = 4096 are resident at once, where 4096 took two rounds and
-// the second round's stragglers set the end (3.5% faster; the CG-fused form
-// is 1% slower that way and keeps one element per workgroup).
+// The plain FP64 operator at n = 10 runs two elements per workgroup: the
+// 2048 workgroups of E = 4096 fill exactly two rounds of 1024 (four per CU,
+// as LDS allows), where one element per workgroup ran 4096 workgroups in 1.8
+// rounds of 2304 (nine per CU) and the partial last round set the end (3.5%
+// faster; the CG-fused form is 1% slower that way and keeps one element per
+// workgroup).
 template <int NX, typename T, bool FUSE, bool CGL>
 using AxShapeFor = AxShape<NX, T, !FUSE && !CGL && sizeof(T) == 8 && NX == 10>;
 
