@@ -187,16 +187,22 @@ def test_mix_of_every_operator_form_bitwise_vs_cg_solve(nek):
 
 
 def test_more_solves_than_the_by_value_slot_table_holds(nek):
-    """Twelve small FP64 requests admitted together: their assembly is one
+    """Twelve small requests admitted together (eleven FP64, one with the FP32
+    operator, whose w the assembly reads in FP32): their assembly is one
     batched launch over more slots than its kernel arguments carry, so it
-    reads them from the device table.  Every solution is bitwise that of
-    nek_cg_solve, with the same iteration count."""
-    reqs = [((2, 2, 2), 5, nek.NEK_PREC_F64, 60 + k) for k in range(12)]
+    reads them from the device table.  Every FP64 solution is bitwise that of
+    nek_cg_solve, with the same iteration count; the FP32-operator solve
+    reaches its true residual."""
+    reqs = [((2, 2, 2), 5, nek.NEK_PREC_F64, 60 + k) for k in range(11)]
+    reqs.append(((2, 2, 2), 5, nek.NEK_PREC_F32G32, 71))
     print("serve 12 requests side by side", flush=True)
     xs, res, trace = _serve(nek, reqs, budget=16 * GB)
     assert max(act for _, act, _ in trace) == len(reqs)
     for k, (box, N, prec, seed) in enumerate(reqs):
         assert res[k]["status"] == 0, (k, res[k])
+        if prec != nek.NEK_PREC_F64:
+            assert res[k]["rel_res_true"] <= 1e-10, (k, res[k])
+            continue
         x, r = _cg_solve_box(nek, box, N, _rhs(nek, box, N, seed))
         assert r.iters == res[k]["iters"], (k, r.iters, res[k]["iters"])
         np.testing.assert_array_equal(xs[k], x)
